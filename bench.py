@@ -1,0 +1,204 @@
+#!/usr/bin/env python
+"""Log-likelihood + gradient evaluations per second on one MI355X.
+
+Workload (the paper's synthetic design, Section VII): n = 102,400 locations
+on a 320 x 320 jittered grid in the unit square (seed 0), Morton-ordered;
+Matérn theta = (sigma^2 1.0, beta 0.1, nu 0.5); tile 800; TLR threshold 1e-7
+(FP64).  z = L eps with L the dense FP64 factor of Sigma(theta) computed on the
+GPU and eps ~ N(0, I) (seed 1).  One step is one tlr_loglik_grad call: Matérn
+generation, TLR Cholesky with compression, log-determinant, forward and
+backward solves, tangent trace term and a^T dSigma a -> (l, dl/dsigma^2,
+dl/dbeta).  Inputs are resident in HBM before the timed region.
+
+The dense FP64 tile Cholesky of the same Sigma (the paper's full-tile variant)
+is timed once beside it; the relative difference of the two log-likelihoods
+is reported.  The CPU oracle is timed on a bounded sample (see cpu_baseline).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "loglik+grad evals/s at n=102400: TLR vs dense FP64, |Δℓ|≤1e-6·|ℓ|"
+PEAK_FP64_MFMA = 78.6     # TFLOP/s, MI355X dense FP64 matrix
+PEAK_FP64_VALU = 78.6     # TFLOP/s, MI355X FP64 vector
+PEAK_HBM = 8000.0         # GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_target: int, theta, n_sample: int) -> dict:
+    """Time the CPU oracle's dense l + gradient on n_sample points of the same
+    design and scale the rate by (n_sample / n_target)^3 (the O(n^3) factor
+    and inverse dominate)."""
+    import numpy as np
+    import synth
+    from oracle import dense as D
+    from oracle import ordering as O
+    x, y = synth.jittered_subset(n_sample, 0)
+    p = O.morton_order(x, y)
+    x, y = x[p], y[p]
+    z = D.sample_z(x, y, theta, synth.standard_normal(n_sample, 1))
+    t0 = time.perf_counter()
+    D.gradient(x, y, z, theta)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else os.cpu_count()
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    rate = (1.0 / dt) * (n_sample / n_target) ** 3
+    return {"value": rate, "unit": "evals/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"dense oracle l+grad (numpy/scipy FP64) at n={n_sample} took {dt:.2f} s; "
+                      f"rate scaled by (n_sample/n)^3 to n={n_target}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=102400)
+    ap.add_argument("--nb", type=int, default=800)
+    ap.add_argument("--dense-nb", type=int, default=512)
+    ap.add_argument("--eps", type=float, default=1e-7)
+    ap.add_argument("--maxrank", type=int, default=256)
+    ap.add_argument("--beta", type=float, default=0.1)
+    ap.add_argument("--nu", type=float, default=0.5)
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=5000)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the TLR likelihood here runs on a single MI355X "
+              "(multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1804_09137_amd as P
+
+    torch.cuda.set_device(0)
+    n = args.n
+    th = (1.0, args.beta, args.nu)
+    x, y = synth.jittered_subset(n, 0)
+    perm = P.morton_order(x, y)
+    x, y = x[perm].copy(), y[perm].copy()
+    eps_v = synth.standard_normal(n, 1)
+    xd, yd, ed = (torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (x, y, eps_v))
+
+    out = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic"}
+    dense = None
+    if not args.no_dense:
+        log(f"[bench] dense FP64 handle n={n} nb={args.dense_nb}")
+        hd = P.Handle(n, args.dense_nb, mode="dense", want_grad=True)
+        hd.generate(xd, yd, th)
+        t0 = time.perf_counter()
+        hd.potrf()
+        t_potrf = time.perf_counter() - t0
+        zd = hd.sample(ed)
+        log(f"[bench] dense potrf {t_potrf:.2f} s; timing dense l+grad")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ll_d, g_d = hd.loglik_grad(xd, yd, zd, th)
+        torch.cuda.synchronize()
+        t_dense = time.perf_counter() - t0
+        dense = {"evals_per_s": 1.0 / t_dense, "ms_per_eval": 1e3 * t_dense, "ll": ll_d, "grad": list(g_d),
+                 "nb": args.dense_nb, "potrf_ms": 1e3 * t_potrf}
+        log(f"[bench] dense l+grad {t_dense:.2f} s ll={ll_d:.10g} grad={g_d}")
+        hd.close()
+        del hd
+        torch.cuda.empty_cache()
+    else:
+        log("[bench] --no-dense: z from a TLR factor at eps=1e-10")
+        hz = P.Handle(n, args.nb, tol=1e-10, maxrank=args.nb // 2)
+        hz.generate(xd, yd, th)
+        hz.potrf()
+        zd = hz.sample(ed)
+        hz.close()
+        del hz
+        torch.cuda.empty_cache()
+
+    log(f"[bench] TLR handle n={n} nb={args.nb} eps={args.eps} maxrank={args.maxrank}")
+    ht = P.Handle(n, args.nb, tol=args.eps, maxrank=args.maxrank, want_grad=True)
+    for w in range(args.warmup):
+        ll, g = ht.loglik_grad(xd, yd, zd, th)
+        log(f"[bench] warmup {w}: ll={ll:.10g} grad={g} factor {ht.info().t_factor_ms:.1f} ms")
+    ht.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ll, g = ht.loglik_grad(xd, yd, zd, th)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ks = ht.kstats()
+    ht.profile(False)
+    info = ht.info()
+    R = ht.ranks()
+    low = R[np.tril_indices(R.shape[0], -1)]
+    log(f"[bench] TLR {args.steps} steps {dt:.3f} s ll={ll:.10g} grad={g}")
+    for name, k in ks.items():
+        log(f"[bench]   {name:9s} launches={k['launches']:6d} ms={k['ms'] / args.steps:9.2f}/step "
+            f"flops={k['flops'] / args.steps:.3e}/step")
+
+    value = args.steps / dt
+    out["value"] = value
+    out["ms_per_step"] = 1e3 * dt / args.steps
+    out["config"] = {"workload": f"Matérn TLR l+grad, n={n} (jittered 320x320 grid, Morton), tile {args.nb}, "
+                                 f"eps={args.eps:g}, theta=(1.0,{args.beta},{args.nu})",
+                     "n": n, "nb": args.nb, "eps": args.eps, "maxrank": args.maxrank,
+                     "theta": list(th), "dense_nb": args.dense_nb}
+    # dominant kernel class by device time
+    dom = max(ks, key=lambda c: ks[c]["ms"])
+    k = ks[dom]
+    if dom == "update":
+        ach = k["flops"] / (k["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_MFMA}
+    elif dom in ("solve",):
+        ach = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM, "unit": "GB/s", "frac": ach / PEAK_HBM}
+    else:
+        ach = k["flops"] / (k["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu" if dom in ("compress", "gradq") else "mfma", "achieved": ach,
+                "peak": PEAK_FP64_VALU, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU}
+    roof.update({"traffic": None, "kernel_class": dom, "launches_per_step": k["launches"] / args.steps,
+                 "ms_per_launch": k["ms"] / max(1, k["launches"])})
+    out["roofline"] = roof
+    out["kernel_classes"] = {c: {"ms_per_step": v["ms"] / args.steps, "flops_per_step": v["flops"] / args.steps,
+                                 "bytes_per_step": v["bytes"] / args.steps,
+                                 "launch_groups_per_step": v["launches"] / args.steps} for c, v in ks.items()}
+    out["tlr"] = {"ll": ll, "grad": list(g), "rank_mean": float(low.mean()) if low.size else 0.0,
+                  "rank_max": int(low.max()) if low.size else 0, "device_GB": info.device_bytes / 1e9,
+                  "factor_ms": info.t_factor_ms, "solve_ms": info.t_solve_ms, "gradq_ms": info.t_grad_ms}
+    if dense is not None:
+        out["dense_fp64"] = dense
+        out["speedup_vs_dense"] = value / dense["evals_per_s"]
+        out["rel_err_ll_vs_dense"] = abs(ll - dense["ll"]) / abs(dense["ll"])
+        out["rel_err_grad_vs_dense"] = [abs(g[i] - dense["grad"][i]) / max(1e-300, abs(dense["grad"][i]))
+                                        for i in range(2)]
+    ht.close()
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle sample n={args.cpu_n}")
+        out["cpu_baseline"] = cpu_baseline(n, th, args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * tlr.h -- C-ABI of the MI355X (gfx950) tile low-rank Matérn log-likelihood.
+ *
+ * Method: arXiv 1804.09137 (Abdulah, Ltaief, Sun, Genton, Keyes), "Parallel
+ * Approximation of the Maximum Likelihood Estimation for the Prediction of
+ * Large-Scale Geostatistics Simulations".
+ *   Section III, Eq. (1):  l(theta) = -n/2 log(2 pi) - 1/2 log|Sigma(theta)|
+ *                                     - 1/2 z^T Sigma(theta)^{-1} z
+ *   Section IV, Eq. (MaternCov): Sigma_ab = C(||s_a - s_b||; theta),
+ *       theta = (sigma^2 variance, beta range, nu smoothness)
+ *   Section V: Sigma is cut into nb x nb tiles, every off-diagonal tile is
+ *       held as U V^T at an absolute accuracy threshold, and the matrix is
+ *       factored by a tile low-rank (TLR) Cholesky.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device (HIP) pointers owned by the caller; they
+ *    must stay valid until the call's stream work has finished.  All other
+ *    pointers are host pointers.
+ *  - Vectors are FP64, length n, in the caller's point order (the order of
+ *    the tiles).  tlr_morton_order gives the ordering the library is tuned
+ *    for; the dense likelihood does not depend on the order, TLR ranks do.
+ *  - Work is enqueued on the handle's stream.  Every call that returns host
+ *    scalars synchronises that stream before returning.
+ *  - Errors are reported only through the return code; nothing aborts or
+ *    prints.  After TLR_EHIP the handle must be destroyed.
+ *  - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef TLR_H_
+#define TLR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tlr_handle_s* tlr_handle_t;
+
+typedef enum {
+  TLR_OK = 0,
+  TLR_ENOTSPD = 1,     /* Sigma not positive definite: *info = 1-based global row of the first bad pivot */
+  TLR_EINVAL = -1,     /* bad argument (null pointer, size, non-positive or non-finite theta, ...) */
+  TLR_ENOMEM = -2,     /* device allocation failed in tlr_create */
+  TLR_EHIP = -3,       /* a HIP runtime call failed */
+  TLR_ERANK = -4,      /* a tile needed a rank above opts.maxrank; see tlr_get_info().bad_tile_* */
+  TLR_ENOTIMPL = -5,   /* requested combination not available */
+  TLR_ESTATE = -6      /* call order violated (e.g. tlr_loglik before tlr_potrf) */
+} tlr_status;
+
+typedef enum {
+  TLR_MODE_TLR = 0,    /* tile low-rank factorisation (Section V) */
+  TLR_MODE_DENSE = 1   /* dense tile Cholesky at full accuracy (the paper's "full-tile" variant) */
+} tlr_mode;
+
+typedef enum {
+  TLR_PREC_FP64 = 0,          /* all arithmetic in FP64 */
+  TLR_PREC_FP32_UPDATES = 1   /* TLR only: low-rank update products in FP32, everything else FP64 */
+} tlr_prec;
+
+typedef struct {
+  int64_t n;          /* number of locations (>= 1) */
+  int32_t nb;         /* tile size (multiple of 16, 32 <= nb <= 1024) */
+  int32_t maxrank;    /* TLR: largest rank a tile may take; 0 selects nb / 2 */
+  double tol;         /* TLR: absolute per-tile accuracy threshold (spectral norm), > 0 */
+  int32_t mode;       /* tlr_mode */
+  int32_t prec;       /* tlr_prec */
+  int32_t want_grad;  /* non-zero: also allocate what tlr_loglik_grad needs */
+  int32_t seed;       /* seed of the Gaussian sketch matrix used by TLR compression */
+} tlr_opts;
+
+typedef struct {
+  int64_t n;
+  int32_t nb, nt, maxrank, mode;
+  int64_t device_bytes;       /* device memory held by the handle */
+  int64_t rank_sum;           /* sum of the ranks of the strictly-lower tiles of the last factor */
+  int32_t rank_max;
+  int32_t bad_tile_i, bad_tile_j; /* TLR_ERANK: offending tile */
+  double t_factor_ms;         /* device time of the last factorisation (hipEvents) */
+  double t_solve_ms;          /* device time of the last log-det + solves */
+  double t_grad_ms;           /* device time of the gradient terms of the last tlr_loglik_grad */
+} tlr_info;
+
+/* Kernel classes timed by tlr_profile (each a group of launches). */
+typedef enum {
+  TLR_K_UPDATE = 0,    /* left-looking column update GEMM with the Matern generation epilogue */
+  TLR_K_LOWRANK = 1,   /* low-rank products: W = U (V^T V) builds, low-rank TRSM, tangent corrections */
+  TLR_K_COMPRESS = 2,  /* sketch GEMM, pivoted Householder QRs, projection, U assembly */
+  TLR_K_DIAG = 3,      /* diagonal tile POTRF + inverse (+ tangent of the diagonal step) */
+  TLR_K_SOLVE = 4,     /* forward and backward solves */
+  TLR_K_GRADQ = 5,     /* a^T dSigma a over all pairs */
+  TLR_K_COUNT = 6
+} tlr_kclass;
+
+typedef struct {
+  int64_t launches;   /* timed launch groups */
+  double ms;          /* sum of their device times (hipEvents on the handle's stream) */
+  double flops;       /* algorithmic flops (true ranks; no padding, no redundant work) */
+  double bytes;       /* algorithmic bytes moved to/from HBM */
+} tlr_kstat;
+
+/* Create a handle for problems of size opts->n on the current HIP device.
+ * stream: a hipStream_t (NULL = the null stream).  All device memory the
+ * handle will use is allocated here (TLR_ENOMEM on failure). */
+tlr_status tlr_create(tlr_handle_t* h, const tlr_opts* opts, void* stream);
+
+/* Release every resource of the handle (NULL is accepted). */
+tlr_status tlr_destroy(tlr_handle_t h);
+
+/* Bind the locations d_x[n], d_y[n] (device, read-only) and theta =
+ * (sigma^2, beta, nu) (host, all finite, beta > 0, nu > 0, sigma^2 != 0) to the
+ * handle.  Sigma(theta) is defined by Eq. (MaternCov) with Euclidean distance
+ * (Section IV); C(0) = sigma^2.  No n x n storage is written here: the tiles
+ * are generated inside tlr_compress / tlr_potrf where they are consumed. */
+tlr_status tlr_generate(tlr_handle_t h, const double* d_x, const double* d_y, const double theta[3]);
+
+/* TLR mode: compress every strictly-lower tile of Sigma(theta) to U V^T with
+ * ||A_ij - U V^T||_2 <= tol (Section V; randomized range finder followed by a
+ * column-pivoted Householder QR truncation).  Fills the rank table that
+ * tlr_get_ranks returns.  This is the TLR form of Sigma itself; tlr_potrf
+ * does not need it. */
+tlr_status tlr_compress(tlr_handle_t h);
+
+/* Factor Sigma(theta) = L L^T.  TLR mode: left-looking tile low-rank
+ * Cholesky (dense POTRF of diagonal tiles, low-rank TRSM, SYRK/GEMM updates
+ * accumulated per tile and recompressed to tol).  DENSE mode: dense tile
+ * Cholesky.  On TLR_ENOTSPD *info holds the 1-based global row of the first
+ * non-positive pivot (LAPACK convention), else 0. */
+tlr_status tlr_potrf(tlr_handle_t h, int64_t* info);
+
+/* After tlr_potrf: log|Sigma| = 2 sum log diag(L), y = L^{-1} d_z,
+ * quad = y^T y, and Eq. (1).  Any output pointer may be NULL. */
+tlr_status tlr_loglik(tlr_handle_t h, const double* d_z, double* ll, double* logdet, double* quad);
+
+/* Full evaluation: bind (d_x, d_y, theta), factor, and return l(theta) and
+ * grad = (dl/dsigma^2, dl/dbeta) with nu held fixed.  The score is
+ *   dl/dtheta_i = -1/2 tr(Sigma^{-1} dSigma_i) + 1/2 a^T dSigma_i a, a = Sigma^{-1} z;
+ * dl/dsigma^2 = (q - n) / (2 sigma^2); the beta trace term is propagated
+ * through the factorisation in tangent mode, the quadratic term uses exact
+ * dSigma/dbeta entries.  Requires opts.want_grad.  info as in tlr_potrf. */
+tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
+                           const double theta[3], double* ll, double grad[2], int64_t* info);
+
+/* After tlr_potrf: d_z = L d_eps (the factor of Sigma(theta) times a caller
+ * vector), e.g. a synthetic measurement vector z ~ N(0, Sigma) from
+ * d_eps ~ N(0, I) (the data generator of Section VIII-D).  d_z must not alias
+ * d_eps. */
+tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z);
+
+/* enable != 0: bracket every launch group with hipEvents on the handle's
+ * stream and accumulate per-class device time and algorithmic work (costs a
+ * few microseconds per group).  Resets the counters either way. */
+tlr_status tlr_profile(tlr_handle_t h, int32_t enable);
+
+/* Copy the TLR_K_COUNT per-class counters into out[]. */
+tlr_status tlr_get_kstats(tlr_handle_t h, tlr_kstat* out);
+
+/* Rank table of the last tlr_compress or tlr_potrf: host_ranks[i * nt + j]
+ * for i > j (other entries 0).  nt = ceil(n / nb). */
+tlr_status tlr_get_ranks(tlr_handle_t h, int32_t* host_ranks);
+
+/* Sizes, memory, rank statistics and timings of the handle. */
+tlr_status tlr_get_info(tlr_handle_t h, tlr_info* out);
+
+/* Copy tile (i, j), i >= j, of the last factor (or of the compressed Sigma
+ * after tlr_compress) densely into d_out (column-major, ld >= tile rows).
+ * Diagonal tiles are lower triangular with zeros above. */
+tlr_status tlr_get_tile(tlr_handle_t h, int32_t i, int32_t j, double* d_out, int64_t ld);
+
+/* Write Sigma(theta)[r0:r0+m, c0:c0+k] (deriv = 0) or dSigma/dbeta (deriv =
+ * 1) of the bound locations into d_out (column-major, ld >= m). */
+tlr_status tlr_covariance_block(tlr_handle_t h, int64_t r0, int64_t m, int64_t c0, int64_t k, int32_t deriv,
+                                double* d_out, int64_t ld);
+
+/* Host helper: Morton (Z-order) permutation of n host points: each
+ * coordinate is quantised to 16 bits over the points' bounding box, bits are
+ * interleaved (x on even positions), keys are sorted stably.  perm[k] is the
+ * input index of the k-th point. */
+tlr_status tlr_morton_order(int64_t n, const double* x, const double* y, int64_t* perm);
+
+/* Text describing the last TLR_EHIP failure of the calling thread (the HIP
+ * error name and the failing call); "" if none.  The string is owned by the
+ * library and stays valid until the next failing call on this thread. */
+const char* tlr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLR_H_ */

@@ -1,0 +1,1419 @@
+// C-ABI entry points and the factorisation drivers.
+//
+// Both variants are left-looking over tile columns j = 0 .. nt-1:
+//   C(:, j) = Sigma(theta)(j.., j) - sum_{k<j} L(j.., k) L(j, k)^T
+// computed by one MFMA GEMM whose epilogue generates the Matérn entries
+// (Section IV, Eq. (MaternCov)), so Sigma is never stored.  Then the diagonal
+// tile is factored (dense POTRF plus its inverse) and the tiles below are
+//   DENSE: multiplied by L_jj^{-T}                     (dense TRSM)
+//   TLR:   compressed to U V~^T at the threshold and V = L_jj^{-1} V~
+//          (low-rank TRSM acts on V only, Section V).
+// In the TLR case L(i, k) L(j, k)^T = U_ik (V_ik^T V_jk) U_jk^T, so the sum
+// over k is W U_row^T with W_ik = U_ik (V_ik^T V_jk) (batched MFMA GEMMs) and
+// U_row = [U_j0 .. U_j,j-1]: the low-rank SYRK (i = j) and GEMM (i > j)
+// updates of the paper's TLR Cholesky, accumulated per tile and recompressed
+// once.
+#include "tlr.h"
+#include "common.h"
+#include "kernels.h"
+#include "chol.h"
+#include "compress.h"
+#include "solve.h"
+#include "grad.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace tlrk;
+
+namespace {
+
+constexpr int64_t kAlign = 16;
+inline int64_t pad16(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct tlr_handle_s {
+  tlr_opts o{};
+  hipStream_t s = nullptr;
+  int device = 0;
+  int64_t n = 0;
+  int nb = 0, nt = 0, maxrank = 0, smax = 0;
+  int maxrank_t = 0;     // tangent tiles (gradient) may take up to 1.5 maxrank
+  bool dense = false, grad = false;
+  int64_t slot = 0;      // doubles per low-rank slot (nb * max(maxrank, maxrank_t))
+  int64_t ntiles = 0;    // strictly-lower tiles
+
+  const double* x = nullptr;
+  const double* y = nullptr;
+  double theta[3] = {0, 0, 0};
+  MaternParams mp{};
+  double* d_tab = nullptr;
+  std::vector<double> h_tab;
+  bool bound = false;
+  int state = 0;  // 0 nothing; 1 compressed Sigma; 2 factor; 3 factor + tangent
+
+  std::vector<void*> dev_allocs;
+  std::vector<void*> host_allocs;
+  int64_t bytes = 0;
+
+  // factor storage
+  double* Lp = nullptr;   // DENSE: lower-panel storage of L
+  double* Ldp = nullptr;  // DENSE: tangent
+  double* D = nullptr;    // TLR: diagonal tiles nt x (nb x nb)
+  double* Dd = nullptr;   // TLR tangent diagonal tiles
+  double* Dinv = nullptr; // both: inverses of the diagonal tiles
+  double* U = nullptr;
+  double* V = nullptr;
+  double* Ud = nullptr;
+  double* Vd = nullptr;
+  int* rk_d = nullptr;    // device rank tables (nt*nt), primal and tangent
+  int* rkd_d = nullptr;
+  std::vector<int> rk, rkd;
+
+  // scratch
+  double* col = nullptr;   // n x nb, ld n
+  double* cold = nullptr;  // tangent column
+  double* omega = nullptr; // nb x smax
+  double* Ybuf = nullptr;  // n x smax, ld n
+  double* Q1 = nullptr;    // n x smax, ld n
+  double* Bt = nullptr;    // nt x (nb x smax)
+  double* Vtmp = nullptr;  // nt x slot
+  double* Zb = nullptr;    // nt x (smax x maxrank)
+  double* Wb = nullptr;
+  int64_t w_cap = 0;
+  double* Xb = nullptr;
+  int64_t x_cap = 0;
+  double* Urow = nullptr;
+  int64_t urow_cap = 0;
+  double* skw = nullptr;
+  int64_t sk_cap = 0;
+  double* tw = nullptr;    // 64 * nb (+ nb * nb tangent scratch)
+  double* vec = nullptr;   // 4 vectors of n
+  double* scal = nullptr;  // device scalars: [0, nt) log-diag, [nt, 2nt) tangent traces, ...
+  double* h_scal = nullptr;
+  unsigned long long* info_d = nullptr;
+  unsigned long long* h_info = nullptr;
+
+  // per-launch metadata, bump-allocated per column
+  int* im_d = nullptr;
+  int* im_h = nullptr;
+  int64_t im_cap = 0, im_use = 0;
+  int64_t* lm_d = nullptr;
+  int64_t* lm_h = nullptr;
+  int64_t lm_cap = 0, lm_use = 0;
+  QrcpTask* tk_d = nullptr;
+  QrcpTask* tk_h = nullptr;
+  int tk_cap = 0;
+  int* qr_d = nullptr;  // 2 * nt: ranks, flags
+  int* qr_h = nullptr;
+
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // per-kernel-class event timing (tlr_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  struct Pending { int cls; size_t e0, e1; double flops, bytes; };
+  std::vector<Pending> pend;
+  tlr_kstat kst[TLR_K_COUNT]{};
+  tlr_info info{};
+  int bad_i = -1, bad_j = -1;
+};
+
+namespace {
+
+struct Fail {
+  tlr_status st;
+};
+
+thread_local char g_last_error[256] = "";
+
+[[noreturn]] void hip_fail(hipError_t e, const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in %s at api.hip:%d", hipGetErrorName(e), (int)e, what, line);
+  (void)hipGetLastError();
+  throw Fail{TLR_EHIP};
+}
+
+#define HIPCHK(x)                                    \
+  do {                                               \
+    hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) hip_fail(e_, #x, __LINE__); \
+  } while (0)
+
+template <class T>
+T* dalloc(tlr_handle_s* h, int64_t count) {
+  if (count <= 0) count = 1;
+  void* p = nullptr;
+  if (hipMalloc(&p, (size_t)count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{TLR_ENOMEM};
+  }
+  h->dev_allocs.push_back(p);
+  h->bytes += count * (int64_t)sizeof(T);
+  return (T*)p;
+}
+
+template <class T>
+T* halloc(tlr_handle_s* h, int64_t count) {
+  if (count <= 0) count = 1;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, (size_t)count * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{TLR_ENOMEM};
+  }
+  h->host_allocs.push_back(p);
+  return (T*)p;
+}
+
+inline int tile_rows(const tlr_handle_s* h, int i) {
+  return (i == h->nt - 1) ? (int)(h->n - (int64_t)i * h->nb) : h->nb;
+}
+inline int64_t slot_of(const tlr_handle_s* h, int i, int j) {  // i > j
+  return (int64_t)j * h->nt - (int64_t)j * (j + 1) / 2 + (i - j - 1);
+}
+
+// ---- metadata staging (pinned host -> device, one column at a time) ----
+int* im_take(tlr_handle_s* h, int64_t cnt, int** dptr) {
+  if (h->im_use + cnt > h->im_cap) throw Fail{TLR_ENOMEM};
+  int* hp = h->im_h + h->im_use;
+  *dptr = h->im_d + h->im_use;
+  h->im_use += cnt;
+  return hp;
+}
+int64_t* lm_take(tlr_handle_s* h, int64_t cnt, int64_t** dptr) {
+  if (h->lm_use + cnt > h->lm_cap) throw Fail{TLR_ENOMEM};
+  int64_t* hp = h->lm_h + h->lm_use;
+  *dptr = h->lm_d + h->lm_use;
+  h->lm_use += cnt;
+  return hp;
+}
+void im_push(tlr_handle_s* h, const int* hp, int* dp, int64_t cnt) {
+  HIPCHK(hipMemcpyAsync(dp, hp, cnt * sizeof(int), hipMemcpyHostToDevice, h->s));
+}
+void lm_push(tlr_handle_s* h, const int64_t* hp, int64_t* dp, int64_t cnt) {
+  HIPCHK(hipMemcpyAsync(dp, hp, cnt * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
+}
+void meta_reset(tlr_handle_s* h) {
+  // callers reset only after a stream synchronisation
+  h->im_use = 0;
+  h->lm_use = 0;
+}
+void prof_harvest(tlr_handle_s* h);
+void sync(tlr_handle_s* h) {
+  HIPCHK(hipStreamSynchronize(h->s));
+  prof_harvest(h);
+}
+
+// ---- per-kernel-class timing: an event pair around each launch group ----
+size_t prof_mark(tlr_handle_s* h) {
+  if (!h->prof) return 0;
+  if (h->ev_used == h->evpool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    h->evpool.push_back(e);
+  }
+  const size_t i = h->ev_used++;
+  HIPCHK(hipEventRecord(h->evpool[i], h->s));
+  return i;
+}
+void prof_add(tlr_handle_s* h, int cls, size_t e0, double flops, double bytes) {
+  if (!h->prof) return;
+  const size_t e1 = prof_mark(h);
+  h->pend.push_back({cls, e0, e1, flops, bytes});
+}
+// call after a stream synchronisation: folds finished pairs into the stats
+void prof_harvest(tlr_handle_s* h) {
+  if (!h->prof) return;
+  for (const auto& p : h->pend) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->evpool[p.e0], h->evpool[p.e1]));
+    tlr_kstat& k = h->kst[p.cls];
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += p.flops;
+    k.bytes += p.bytes;
+  }
+  h->pend.clear();
+}
+// start of an API call: no event pair is open, the pool can be reused
+void prof_reset_pool(tlr_handle_s* h) {
+  h->pend.clear();
+  h->ev_used = 0;
+}
+
+Operand op_contig(const double* base, int64_t ld, int64_t r0 = 0, int64_t c0 = 0) {
+  Operand o{};
+  o.base = base;
+  o.ld = ld;
+  o.r0 = r0;
+  o.c0 = c0;
+  o.layout = kContig;
+  return o;
+}
+Operand op_contigT(const double* base, int64_t ld, int64_t r0 = 0, int64_t c0 = 0) {
+  Operand o = op_contig(base, ld, r0, c0);
+  o.layout = kContigT;
+  return o;
+}
+Operand op_panels(const double* base, int64_t n, int nb, int64_t r0, int64_t c0) {
+  Operand o{};
+  o.base = base;
+  o.n = n;
+  o.nb = nb;
+  o.r0 = r0;
+  o.c0 = c0;
+  o.layout = kPanels;
+  return o;
+}
+GemmEpi epi_linear(double alpha, double beta) {
+  GemmEpi e{};
+  e.kind = kEpiLinear;
+  e.alpha = alpha;
+  e.beta = beta;
+  return e;
+}
+GemmEpi epi_gen(const tlr_handle_s* h, int kind, int64_t grow0, int64_t gcol0) {
+  GemmEpi e{};
+  e.kind = kind;
+  e.alpha = 1.0;
+  e.mp = h->mp;
+  e.x = h->x;
+  e.y = h->y;
+  e.grow0 = grow0;
+  e.gcol0 = gcol0;
+  return e;
+}
+
+// split-K factor for a GEMM whose output grid is small and whose K is long
+int choose_splitk(const tlr_handle_s* h, int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+  if (tiles >= 256 || K < 2048) return 1;
+  int64_t sk = std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 1024);
+  sk = std::max<int64_t>(1, std::min<int64_t>(sk, 32));
+  while (sk > 1 && sk * M * N > h->sk_cap) --sk;
+  return (int)sk;
+}
+
+void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
+          const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false) {
+  int sk = 1;
+  if (allow_split && !b) {
+    int64_t K = 0;
+    for (int i = 0; i < nseg; ++i) K += segs[i].K;
+    sk = choose_splitk(h, M, N, K);
+  }
+  HIPCHK(launch_gemm(M, N, nseg, segs, C, ldc, ep, b, sk, sk > 1 ? h->skw : nullptr, h->s));
+}
+
+// ---------------------------------------------------------------------------
+// Compression of the tiles below the diagonal of one column held densely in
+// src (ld), rows [row0, row0 + sum m_i); tile t (0 .. T-1) is global tile
+// i = i_first + t.  Results: U slots of (i, col), V~ in vt (per tile slot,
+// ld nb), ranks into rk_out[i * nt + col].  pred holds predicted ranks.
+// ---------------------------------------------------------------------------
+void throw_if_not_spd(tlr_handle_s* h) {
+  // *h_info was copied back before the last synchronisation
+  if (*h->h_info != ~0ull) throw Fail{TLR_ENOTSPD};
+}
+
+void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first, int T, int col,
+                     int ncols, double* Uslots, double* vt, std::vector<int>& rk_out, const std::vector<int>& pred,
+                     int maxrank) {
+  if (T <= 0) return;
+  const int nb = h->nb;
+  const size_t e_c = prof_mark(h);
+  double cflops = 0.0;
+  int s = 32;
+  for (int t = 0; t < T; ++t) s = std::max(s, (int)pad16(pred[t] + 24));
+  s = std::min(s, h->smax);
+  const double tol = h->o.tol;
+  const double tol_range = 0.05 * tol;  // range finder residual target (Frobenius of the samples)
+  const double tol_trunc = 0.9 * tol;
+  std::vector<int> t1(T);
+  for (;;) {
+    // 1. sketch Y = C Omega for all tiles at once
+    int64_t rows = 0;
+    for (int t = 0; t < T; ++t) rows += tile_rows(h, i_first + t);
+    GemmSeg sg{};
+    sg.A = op_contig(src, ld, 0, 0);
+    sg.B = op_contigT(h->omega, nb, 0, 0);
+    sg.K = ncols;
+    gemm(h, rows, s, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0));
+    // 2. pivoted QR of each tile's samples: orthonormal range basis Q1
+    for (int t = 0; t < T; ++t) {
+      QrcpTask& q = h->tk_h[t];
+      q = QrcpTask{};
+      q.Y = h->Ybuf + (int64_t)t * nb;
+      q.ldy = h->n;
+      q.m = tile_rows(h, i_first + t);
+      q.q = s;
+      q.tol = tol_range * std::sqrt((double)s);
+      q.max_rank = s;
+      q.min_tail = 8;
+      q.Q = h->Q1 + (int64_t)t * nb;
+      q.ldq = h->n;
+      q.rank = h->qr_d + t;
+      q.flag = h->qr_d + h->nt + t;
+    }
+    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, T * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_qrcp(h->tk_d, T, h->s));
+    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
+    sync(h);
+    throw_if_not_spd(h);
+    bool redo = false;
+    for (int t = 0; t < T; ++t) {
+      t1[t] = h->qr_h[t];
+      if (h->qr_h[h->nt + t]) redo = true;
+      const double m = tile_rows(h, i_first + t);
+      cflops += 2.0 * m * s * ncols + 4.0 * m * s * t1[t] + 2.0 * m * t1[t] * t1[t];
+    }
+    if (!redo) break;
+    if (s >= h->smax) {
+      int worst = 0;
+      for (int t = 0; t < T; ++t)
+        if (h->qr_h[h->nt + t]) { worst = t; break; }
+      h->bad_i = i_first + worst;
+      h->bad_j = col;
+      throw Fail{TLR_ERANK};
+    }
+    s = std::min(h->smax, 2 * s);
+  }
+  meta_reset(h);
+  // 3. project: Bt_t = C_t^T Q1_t (ncols x t1)
+  int *m_d, *n_d, *k_d;
+  int* m_h = im_take(h, T, &m_d);
+  int* n_h = im_take(h, T, &n_d);
+  int* k_h = im_take(h, T, &k_d);
+  int64_t *a_d, *b_d, *c_d;
+  int64_t* a_h = lm_take(h, T, &a_d);
+  int64_t* b_h = lm_take(h, T, &b_d);
+  int64_t* c_h = lm_take(h, T, &c_d);
+  int maxn = 1;
+  for (int t = 0; t < T; ++t) {
+    m_h[t] = ncols;
+    n_h[t] = t1[t];
+    k_h[t] = tile_rows(h, i_first + t);
+    a_h[t] = (int64_t)t * nb;                       // row offset of tile t in src (contigT frame)
+    b_h[t] = (int64_t)t * nb;                       // Q1 rows
+    c_h[t] = (int64_t)t * nb * h->smax;             // Bt block
+    maxn = std::max(maxn, t1[t]);
+  }
+  im_push(h, m_h, m_d, 3 * T);
+  lm_push(h, a_h, a_d, 3 * T);
+  {
+    GemmSeg sg{};
+    sg.A = op_contigT(src, ld, 0, 0);
+    sg.B = op_contigT(h->Q1, h->n, 0, 0);
+    sg.K = nb;
+    GemmBatch bt{};
+    bt.count = T;
+    bt.m_of = m_d;
+    bt.n_of = n_d;
+    bt.k_of = k_d;
+    bt.a_off = a_d;
+    bt.b_off = b_d;
+    bt.c_off = c_d;
+    gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt);
+  }
+  // 4. truncation by pivoted QR of Bt: V~ = Q2[:, :k], Z = Pi R2[:k, :]^T
+  for (int t = 0; t < T; ++t) {
+    QrcpTask& q = h->tk_h[t];
+    q = QrcpTask{};
+    q.Y = h->Bt + (int64_t)t * nb * h->smax;
+    q.ldy = nb;
+    q.m = ncols;
+    q.q = t1[t];
+    q.tol = tol_trunc;
+    q.max_rank = maxrank + 1;
+    q.min_tail = 0;
+    q.Q = vt + (int64_t)t * h->slot;
+    q.ldq = nb;
+    q.Z = h->Zb + (int64_t)t * h->smax * (h->slot / h->nb + 1);
+    q.ldz = h->smax;
+    q.rank = h->qr_d + t;
+    q.flag = h->qr_d + h->nt + t;
+  }
+  HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, T * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+  HIPCHK(launch_qrcp(h->tk_d, T, h->s));
+  HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
+  sync(h);
+  meta_reset(h);
+  std::vector<int> k2(T);
+  int maxk = 0;
+  for (int t = 0; t < T; ++t) {
+    k2[t] = h->qr_h[t];
+    if (k2[t] > maxrank) {
+      h->bad_i = i_first + t;
+      h->bad_j = col;
+      throw Fail{TLR_ERANK};
+    }
+    rk_out[(size_t)(i_first + t) * h->nt + col] = k2[t];
+    maxk = std::max(maxk, k2[t]);
+    const double m = tile_rows(h, i_first + t);
+    cflops += 2.0 * ncols * t1[t] * m + 4.0 * ncols * t1[t] * k2[t] + 2.0 * ncols * k2[t] * k2[t] +
+              2.0 * m * t1[t] * k2[t];
+  }
+  if (maxk == 0) {
+    prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
+    return;
+  }
+  // 5. U_t = Q1_t Z_t  (m_t x k_t)
+  m_h = im_take(h, T, &m_d);
+  n_h = im_take(h, T, &n_d);
+  k_h = im_take(h, T, &k_d);
+  a_h = lm_take(h, T, &a_d);
+  b_h = lm_take(h, T, &b_d);
+  c_h = lm_take(h, T, &c_d);
+  int maxm = 1;
+  for (int t = 0; t < T; ++t) {
+    m_h[t] = tile_rows(h, i_first + t);
+    n_h[t] = k2[t];
+    k_h[t] = t1[t];
+    a_h[t] = (int64_t)t * nb;
+    b_h[t] = (int64_t)t * h->smax * (h->slot / h->nb + 1);
+    c_h[t] = slot_of(h, i_first + t, col) * h->slot;
+    maxm = std::max(maxm, m_h[t]);
+  }
+  im_push(h, m_h, m_d, 3 * T);
+  lm_push(h, a_h, a_d, 3 * T);
+  GemmSeg sg{};
+  sg.A = op_contig(h->Q1, h->n, 0, 0);
+  sg.B = op_contigT(h->Zb, h->smax, 0, 0);
+  sg.K = h->smax;
+  GemmBatch bt{};
+  bt.count = T;
+  bt.m_of = m_d;
+  bt.n_of = n_d;
+  bt.k_of = k_d;
+  bt.a_off = a_d;
+  bt.b_off = b_d;
+  bt.c_off = c_d;
+  gemm(h, maxm, maxk, 1, &sg, Uslots, nb, epi_linear(1.0, 0.0), &bt);
+  prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
+}
+
+// V(i, col) = Dinv_col * V~_i  for the T tiles below the diagonal
+void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt, double* Vslots,
+                  const std::vector<int>& rks) {
+  if (T <= 0) return;
+  int *m_d, *n_d, *k_d;
+  int* m_h = im_take(h, T, &m_d);
+  int* n_h = im_take(h, T, &n_d);
+  int* k_h = im_take(h, T, &k_d);
+  int64_t *a_d, *b_d, *c_d;
+  int64_t* a_h = lm_take(h, T, &a_d);
+  int64_t* b_h = lm_take(h, T, &b_d);
+  int64_t* c_h = lm_take(h, T, &c_d);
+  const int nbj = tile_rows(h, col);
+  int maxk = 0;
+  for (int t = 0; t < T; ++t) {
+    const int i = i_first + t;
+    m_h[t] = nbj;
+    n_h[t] = rks[(size_t)i * h->nt + col];
+    k_h[t] = nbj;
+    a_h[t] = 0;
+    b_h[t] = (int64_t)t * h->slot;
+    c_h[t] = slot_of(h, i, col) * h->slot;
+    maxk = std::max(maxk, n_h[t]);
+  }
+  if (maxk == 0) return;
+  im_push(h, m_h, m_d, 3 * T);
+  lm_push(h, a_h, a_d, 3 * T);
+  GemmSeg sg{};
+  sg.A = op_contig(h->Dinv + (int64_t)col * h->nb * h->nb, h->nb, 0, 0);
+  sg.B = op_contigT(vt, h->nb, 0, 0);
+  sg.K = nbj;
+  GemmBatch bt{};
+  bt.count = T;
+  bt.m_of = m_d;
+  bt.n_of = n_d;
+  bt.k_of = k_d;
+  bt.a_off = a_d;
+  bt.b_off = b_d;
+  bt.c_off = c_d;
+  const size_t e_t = prof_mark(h);
+  gemm(h, nbj, maxk, 1, &sg, Vslots, h->nb, epi_linear(1.0, 0.0), &bt);
+  double kt = 0.0;
+  for (int t = 0; t < T; ++t) kt += n_h[t];
+  prof_add(h, TLR_K_LOWRANK, e_t, 2.0 * nbj * nbj * kt, 8.0 * (2.0 * nbj * kt + (double)nbj * nbj));
+}
+
+// ---------------------------------------------------------------------------
+// W-build and column GEMM of the TLR factorisation (primal):
+// C(i, j) = Sigma(i, j) - sum_k U_ik (V_ik^T V_jk) U_jk^T, i in [j, nt)
+// written to h->col (row offset (i - j) nb, ld n).
+// ---------------------------------------------------------------------------
+struct LRTerm {           // one low-rank product family  L1(i,k) L2(j,k)^T
+  const double* Ui;       // left factor slots of L1: U
+  const double* Vi;       //                          V
+  const std::vector<int>* rki;
+  const double* Uj;       // right factor slots of L2 (row j)
+  const double* Vj;
+  const std::vector<int>* rkj;
+};
+
+void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind) {
+  const int nt = h->nt, nb = h->nb;
+  const int nbj = tile_rows(h, j);
+  // padded K layout: for each term, for each k < j, a segment of pad16(rank_j(k))
+  std::vector<int64_t> off((size_t)nterms * std::max(j, 1));
+  int64_t R = 0, Ktrue = 0;
+  for (int tm = 0; tm < nterms; ++tm)
+    for (int k = 0; k < j; ++k) {
+      off[(size_t)tm * j + k] = R;
+      R += pad16((*terms[tm].rkj)[(size_t)j * nt + k]);
+      Ktrue += (*terms[tm].rkj)[(size_t)j * nt + k];
+    }
+  const size_t e_urow = prof_mark(h);
+  // U_row (nb_j x R): zero, then copy the right factors of row j
+  if (R > 0) {
+    if ((int64_t)nb * R > h->urow_cap) throw Fail{TLR_ENOMEM};
+    HIPCHK(launch_fill(h->Urow, nb, nb, R, 0.0, h->s));
+    for (int tm = 0; tm < nterms; ++tm) {
+      int cnt = 0;
+      for (int k = 0; k < j; ++k)
+        if ((*terms[tm].rkj)[(size_t)j * nt + k] > 0) ++cnt;
+      if (cnt == 0) continue;
+      int *m_d, *k_d;
+      int* m_h = im_take(h, cnt, &m_d);
+      int* k_h = im_take(h, cnt, &k_d);
+      int64_t *so_d, *do_d;
+      int64_t* so_h = lm_take(h, cnt, &so_d);
+      int64_t* do_h = lm_take(h, cnt, &do_d);
+      int c = 0;
+      int64_t maxe = 0;
+      for (int k = 0; k < j; ++k) {
+        const int r = (*terms[tm].rkj)[(size_t)j * nt + k];
+        if (r <= 0) continue;
+        m_h[c] = nbj;
+        k_h[c] = r;
+        so_h[c] = slot_of(h, j, k) * h->slot;
+        do_h[c] = off[(size_t)tm * j + k] * nb;
+        maxe = std::max<int64_t>(maxe, (int64_t)nbj * r);
+        ++c;
+      }
+      im_push(h, m_h, m_d, 2 * (int64_t)cnt);
+      lm_push(h, so_h, so_d, 2 * (int64_t)cnt);
+      HIPCHK(launch_batched_copy(terms[tm].Uj, nb, so_d, h->Urow, nb, do_d, m_d, k_d, maxe, cnt, h->s));
+    }
+  }
+  prof_add(h, TLR_K_LOWRANK, e_urow, 0.0, 16.0 * nbj * (double)Ktrue);
+  // chunks of row tiles [i0, i1) such that W and X fit
+  int i0 = j;
+  while (i0 < nt) {
+    int i1 = i0;
+    int64_t xneed = 0;
+    while (i1 < nt) {
+      const int64_t wrows = (int64_t)(i1 + 1 - i0) * nb;
+      int64_t xadd = 0;
+      for (int tm = 0; tm < nterms; ++tm)
+        for (int k = 0; k < j; ++k)
+          xadd += (int64_t)(h->slot / nb) * pad16((*terms[tm].rkj)[(size_t)j * nt + k]);
+      if (wrows * std::max<int64_t>(R, 1) > h->w_cap || xneed + xadd > h->x_cap) break;
+      xneed += xadd;
+      ++i1;
+    }
+    if (i1 == i0) throw Fail{TLR_ENOMEM};
+    int64_t mrows = 0;
+    for (int i = i0; i < i1; ++i) mrows += tile_rows(h, i);
+    const int64_t ldw = (int64_t)(i1 - i0) * nb;
+    const size_t e_w = prof_mark(h);
+    double wflops = 0.0, wbytes = 0.0;
+    if (R > 0) {
+      HIPCHK(launch_fill(h->Wb, ldw, ldw, R, 0.0, h->s));
+      int64_t xoff = 0;
+      for (int tm = 0; tm < nterms; ++tm) {
+        const LRTerm& T = terms[tm];
+        int cnt = 0, maxa = 1, maxb = 1;
+        for (int i = i0; i < i1; ++i)
+          for (int k = 0; k < j; ++k) {
+            const int a = (*T.rki)[(size_t)i * nt + k];
+            const int b = (*T.rkj)[(size_t)j * nt + k];
+            if (a <= 0 || b <= 0) continue;
+            ++cnt;
+            maxa = std::max(maxa, a);
+            maxb = std::max(maxb, b);
+          }
+        if (cnt == 0) continue;
+        int *xm_d, *xn_d, *xk_d, *wm_d, *wn_d, *wk_d;
+        int* xm_h = im_take(h, cnt, &xm_d);
+        int* xn_h = im_take(h, cnt, &xn_d);
+        int* xk_h = im_take(h, cnt, &xk_d);
+        int* wm_h = im_take(h, cnt, &wm_d);
+        int* wn_h = im_take(h, cnt, &wn_d);
+        int* wk_h = im_take(h, cnt, &wk_d);
+        int64_t *xa_d, *xb_d, *xc_d, *wa_d, *wb_d, *wc_d;
+        int64_t* xa_h = lm_take(h, cnt, &xa_d);
+        int64_t* xb_h = lm_take(h, cnt, &xb_d);
+        int64_t* xc_h = lm_take(h, cnt, &xc_d);
+        int64_t* wa_h = lm_take(h, cnt, &wa_d);
+        int64_t* wb_h = lm_take(h, cnt, &wb_d);
+        int64_t* wc_h = lm_take(h, cnt, &wc_d);
+        int c = 0, maxrows = 1;
+        for (int i = i0; i < i1; ++i)
+          for (int k = 0; k < j; ++k) {
+            const int a = (*T.rki)[(size_t)i * nt + k];
+            const int b = (*T.rkj)[(size_t)j * nt + k];
+            if (a <= 0 || b <= 0) continue;
+            const int64_t si = slot_of(h, i, k) * h->slot;   // i >= j > k
+            xm_h[c] = a; xn_h[c] = b; xk_h[c] = nb;
+            xa_h[c] = si;
+            xb_h[c] = slot_of(h, j, k) * h->slot;
+            xc_h[c] = xoff;                                  // X_ik: a x b, ld maxa
+            wm_h[c] = tile_rows(h, i); wn_h[c] = b; wk_h[c] = a;
+            wa_h[c] = si;
+            wb_h[c] = xoff;
+            wc_h[c] = (int64_t)(i - i0) * nb + off[(size_t)tm * j + k] * ldw;
+            xoff += (int64_t)maxa * b;
+            maxrows = std::max(maxrows, wm_h[c]);
+            wflops += 2.0 * a * b * ((double)nb + wm_h[c]);
+            wbytes += 8.0 * ((double)nb * (a + b) + (double)wm_h[c] * (a + b));
+            ++c;
+          }
+        if (xoff > h->x_cap) throw Fail{TLR_ENOMEM};
+        im_push(h, xm_h, xm_d, 6 * (int64_t)cnt);
+        lm_push(h, xa_h, xa_d, 6 * (int64_t)cnt);
+        GemmSeg xs{};
+        xs.A = op_contigT(T.Vi, nb, 0, 0);
+        xs.B = op_contigT(T.Vj, nb, 0, 0);
+        xs.K = nb;
+        GemmBatch xb{};
+        xb.count = cnt;
+        xb.m_of = xm_d; xb.n_of = xn_d; xb.k_of = xk_d;
+        xb.a_off = xa_d; xb.b_off = xb_d; xb.c_off = xc_d;
+        gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb);
+        GemmSeg ws{};
+        ws.A = op_contig(T.Ui, nb, 0, 0);
+        ws.B = op_contigT(h->Xb, maxa, 0, 0);
+        ws.K = maxa;
+        GemmBatch wb{};
+        wb.count = cnt;
+        wb.m_of = wm_d; wb.n_of = wn_d; wb.k_of = wk_d;
+        wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
+        gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb);
+      }
+    }
+    prof_add(h, TLR_K_LOWRANK, e_w, wflops, wbytes);
+    // column GEMM with generation epilogue
+    GemmSeg cs{};
+    cs.A = op_contig(h->Wb, ldw, 0, 0);
+    cs.B = op_contig(h->Urow, nb, 0, 0);
+    cs.K = R;
+    const size_t e0 = prof_mark(h);
+    gemm(h, mrows, nbj, 1, &cs, out + (int64_t)(i0 - j) * nb, h->n,
+         epi_gen(h, epi_kind, (int64_t)i0 * nb, (int64_t)j * nb), nullptr, true);
+    prof_add(h, TLR_K_UPDATE, e0, 2.0 * mrows * nbj * (double)Ktrue,
+             8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + (double)mrows * nbj));
+    i0 = i1;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// factorisation drivers
+// ===========================================================================
+namespace {
+
+void reset_info(tlr_handle_s* h) {
+  *h->h_info = ~0ull;
+  HIPCHK(hipMemcpyAsync(h->info_d, h->h_info, sizeof(unsigned long long), hipMemcpyHostToDevice, h->s));
+}
+
+double* dinv_tile(tlr_handle_s* h, int j) { return h->Dinv + (int64_t)j * h->nb * h->nb; }
+double* diag_tile(tlr_handle_s* h, int j) { return h->D + (int64_t)j * h->nb * h->nb; }
+double* panel(tlr_handle_s* h, double* base, int j) { return base + panel_offset(h->n, h->nb, j); }
+
+// Tangent of the diagonal step: C_jj = L_jj L_jj^T  =>
+//   M = L_jj^{-1} dC_jj L_jj^{-T},  dL_jj = L_jj Phi(M),  tr(M) -> *trace.
+// dC is read from dc (ld ldc); L_jj from L (ld ldl); dL written to out (ld ldo).
+void tangent_diag(tlr_handle_s* h, int j, const double* dc, int64_t ldc, const double* L, int64_t ldl, double* out,
+                  int64_t ldo) {
+  const int nb = h->nb, nbj = tile_rows(h, j);
+  double* T1 = h->tw + 64 * (int64_t)nb;
+  double* Mj = T1 + (int64_t)nb * nb;
+  GemmSeg a{};
+  a.A = op_contig(dinv_tile(h, j), nb, 0, 0);
+  a.B = op_contigT(dc, ldc, 0, 0);
+  a.K = nbj;
+  gemm(h, nbj, nbj, 1, &a, T1, nb, epi_linear(1.0, 0.0));
+  GemmSeg b{};
+  b.A = op_contig(T1, nb, 0, 0);
+  b.B = op_contig(dinv_tile(h, j), nb, 0, 0);
+  b.K = nbj;
+  gemm(h, nbj, nbj, 1, &b, Mj, nb, epi_linear(1.0, 0.0));
+  HIPCHK(launch_phi_trace(Mj, nb, nbj, h->scal + h->nt + j, h->s));
+  GemmSeg c{};
+  c.A = op_contig(L, ldl, 0, 0);
+  c.B = op_contigT(Mj, nb, 0, 0);
+  c.K = nbj;
+  gemm(h, nbj, nbj, 1, &c, out, ldo, epi_linear(1.0, 0.0));
+}
+
+void factor_dense(tlr_handle_s* h, bool tangent) {
+  const int nt = h->nt, nb = h->nb;
+  const int64_t n = h->n;
+  reset_info(h);
+  for (int j = 0; j < nt; ++j) {
+    const int nbj = tile_rows(h, j);
+    const int64_t M = n - (int64_t)j * nb;
+    GemmSeg sg{};
+    sg.A = op_panels(h->Lp, n, nb, (int64_t)j * nb, 0);
+    sg.B = op_panels(h->Lp, n, nb, (int64_t)j * nb, 0);
+    sg.K = (int64_t)j * nb;
+    const size_t e_u = prof_mark(h);
+    gemm(h, M, nbj, 1, &sg, h->col, n, epi_gen(h, kEpiGenMinus, (int64_t)j * nb, (int64_t)j * nb), nullptr, true);
+    prof_add(h, TLR_K_UPDATE, e_u, 2.0 * M * nbj * (double)sg.K,
+             8.0 * ((double)M * sg.K + (double)nbj * sg.K + (double)M * nbj));
+    const size_t e_d = prof_mark(h);
+    HIPCHK(tile_potrf_inv(h->col, n, nbj, dinv_tile(h, j), nb, h->info_d, (int64_t)j * nb, h->tw, h->s));
+    HIPCHK(launch_logdiag(h->col, n, nbj, h->scal + j, h->s));
+    prof_add(h, TLR_K_DIAG, e_d, 2.0 / 3.0 * nbj * (double)nbj * nbj, 16.0 * nbj * (double)nbj);
+    double* pj = panel(h, h->Lp, j);
+    const int64_t ldp = n - (int64_t)j * nb;
+    if (M > nbj) {
+      GemmSeg ts{};
+      ts.A = op_contig(h->col, n, nbj, 0);
+      ts.B = op_contig(dinv_tile(h, j), nb, 0, 0);
+      ts.K = nbj;
+      gemm(h, M - nbj, nbj, 1, &ts, pj + nbj, ldp, epi_linear(1.0, 0.0));
+    }
+    HIPCHK(launch_copy_block(h->col, n, pj, ldp, nbj, nbj, h->s));
+    if (!tangent) continue;
+    // dC(:, j) = dSigma/dbeta(j.., j) - sum_k [dL(j.., k) L(j, k)^T + L(j.., k) dL(j, k)^T]
+    GemmSeg tg[2]{};
+    tg[0].A = op_panels(h->Ldp, n, nb, (int64_t)j * nb, 0);
+    tg[0].B = op_panels(h->Lp, n, nb, (int64_t)j * nb, 0);
+    tg[0].K = (int64_t)j * nb;
+    tg[1].A = op_panels(h->Lp, n, nb, (int64_t)j * nb, 0);
+    tg[1].B = op_panels(h->Ldp, n, nb, (int64_t)j * nb, 0);
+    tg[1].K = (int64_t)j * nb;
+    const size_t e_t = prof_mark(h);
+    gemm(h, M, nbj, 2, tg, h->cold, n, epi_gen(h, kEpiDGenMinus, (int64_t)j * nb, (int64_t)j * nb), nullptr, true);
+    prof_add(h, TLR_K_UPDATE, e_t, 4.0 * M * nbj * (double)tg[0].K,
+             16.0 * ((double)M * tg[0].K + (double)nbj * tg[0].K) + 8.0 * M * nbj);
+    double* dpj = panel(h, h->Ldp, j);
+    tangent_diag(h, j, h->cold, n, pj, ldp, dpj, ldp);
+    if (M > nbj) {
+      // dL_below = (dC_below - L_below dL_jj^T) L_jj^{-T}
+      GemmSeg u{};
+      u.A = op_contig(pj + nbj, ldp, 0, 0);
+      u.B = op_contig(dpj, ldp, 0, 0);
+      u.K = nbj;
+      gemm(h, M - nbj, nbj, 1, &u, h->cold + nbj, n, epi_linear(-1.0, 1.0));
+      GemmSeg v{};
+      v.A = op_contig(h->cold, n, nbj, 0);
+      v.B = op_contig(dinv_tile(h, j), nb, 0, 0);
+      v.K = nbj;
+      gemm(h, M - nbj, nbj, 1, &v, dpj + nbj, ldp, epi_linear(1.0, 0.0));
+    }
+  }
+}
+
+void factor_tlr(tlr_handle_s* h, bool tangent) {
+  const int nt = h->nt, nb = h->nb;
+  reset_info(h);
+  std::fill(h->rk.begin(), h->rk.end(), 0);
+  std::fill(h->rkd.begin(), h->rkd.end(), 0);
+  meta_reset(h);
+  sync(h);
+  std::vector<int> pred(nt);
+  for (int j = 0; j < nt; ++j) {
+    const int nbj = tile_rows(h, j);
+    LRTerm tm{h->U, h->V, &h->rk, h->U, h->V, &h->rk};
+    tlr_column_update(h, j, 1, &tm, h->col, kEpiGenMinus);
+    const size_t e_d = prof_mark(h);
+    HIPCHK(launch_copy_block(h->col, h->n, diag_tile(h, j), nb, nbj, nbj, h->s));
+    HIPCHK(tile_potrf_inv(diag_tile(h, j), nb, nbj, dinv_tile(h, j), nb, h->info_d, (int64_t)j * nb, h->tw, h->s));
+    HIPCHK(launch_logdiag(diag_tile(h, j), nb, nbj, h->scal + j, h->s));
+    prof_add(h, TLR_K_DIAG, e_d, 2.0 / 3.0 * nbj * (double)nbj * nbj, 16.0 * nbj * (double)nbj);
+    const int T = nt - j - 1;
+    if (T > 0) {
+      for (int t = 0; t < T; ++t) {
+        const int i = j + 1 + t;
+        pred[t] = (j > 0) ? h->rk[(size_t)(i - 1) * nt + (j - 1)] : 48;
+      }
+      compress_column(h, h->col + nbj, h->n, j + 1, T, j, nbj, h->U, h->Vtmp, h->rk, pred, h->maxrank);
+      lowrank_trsm(h, j, j + 1, T, h->Vtmp, h->V, h->rk);
+    }
+    if (!tangent) continue;
+    // dC(:, j) = dSigma/dbeta - sum_k [dU_ik (dV_ik^T V_jk) U_jk^T + U_ik (V_ik^T dV_jk) dU_jk^T]
+    LRTerm tt[2] = {{h->Ud, h->Vd, &h->rkd, h->U, h->V, &h->rk}, {h->U, h->V, &h->rk, h->Ud, h->Vd, &h->rkd}};
+    tlr_column_update(h, j, 2, tt, h->cold, kEpiDGenMinus);
+    double* ddj = h->Dd + (int64_t)j * nb * nb;
+    tangent_diag(h, j, h->cold, h->n, diag_tile(h, j), nb, ddj, nb);
+    if (T > 0) {
+      // dC_ij <- dC_ij - U_ij (dL_jj V_ij)^T, then compress and V <- L_jj^{-1} V
+      std::vector<int> prim(T);
+      int kmax = 0;
+      for (int t = 0; t < T; ++t) {
+        prim[t] = h->rk[(size_t)(j + 1 + t) * nt + j];
+        kmax = std::max(kmax, prim[t]);
+      }
+      if (kmax > 0) {
+        int *m_d, *n_d, *k_d;
+        int* m_h = im_take(h, T, &m_d);
+        int* n_h = im_take(h, T, &n_d);
+        int* k_h = im_take(h, T, &k_d);
+        int64_t *a_d, *b_d, *c_d;
+        int64_t* a_h = lm_take(h, T, &a_d);
+        int64_t* b_h = lm_take(h, T, &b_d);
+        int64_t* c_h = lm_take(h, T, &c_d);
+        for (int t = 0; t < T; ++t) {
+          m_h[t] = nbj; n_h[t] = prim[t]; k_h[t] = nbj;
+          a_h[t] = 0;
+          b_h[t] = slot_of(h, j + 1 + t, j) * h->slot;
+          c_h[t] = (int64_t)t * h->slot;
+        }
+        im_push(h, m_h, m_d, 3 * (int64_t)T);
+        lm_push(h, a_h, a_d, 3 * (int64_t)T);
+        GemmSeg ps{};
+        ps.A = op_contig(ddj, nb, 0, 0);
+        ps.B = op_contigT(h->V, nb, 0, 0);
+        ps.K = nbj;
+        GemmBatch pb{};
+        pb.count = T; pb.m_of = m_d; pb.n_of = n_d; pb.k_of = k_d; pb.a_off = a_d; pb.b_off = b_d; pb.c_off = c_d;
+        gemm(h, nbj, kmax, 1, &ps, h->Vtmp, nb, epi_linear(1.0, 0.0), &pb);
+        int* m2_h = im_take(h, T, &m_d);
+        int* n2_h = im_take(h, T, &n_d);
+        int* k2_h = im_take(h, T, &k_d);
+        int64_t* a2_h = lm_take(h, T, &a_d);
+        int64_t* b2_h = lm_take(h, T, &b_d);
+        int64_t* c2_h = lm_take(h, T, &c_d);
+        int mmax = 1;
+        for (int t = 0; t < T; ++t) {
+          m2_h[t] = tile_rows(h, j + 1 + t); n2_h[t] = nbj; k2_h[t] = prim[t];
+          a2_h[t] = slot_of(h, j + 1 + t, j) * h->slot;
+          b2_h[t] = (int64_t)t * h->slot;
+          c2_h[t] = (int64_t)nbj + (int64_t)t * nb;
+          mmax = std::max(mmax, m2_h[t]);
+        }
+        im_push(h, m2_h, m_d, 3 * (int64_t)T);
+        lm_push(h, a2_h, a_d, 3 * (int64_t)T);
+        GemmSeg cs{};
+        cs.A = op_contig(h->U, nb, 0, 0);
+        cs.B = op_contig(h->Vtmp, nb, 0, 0);
+        cs.K = kmax;
+        GemmBatch cb{};
+        cb.count = T; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
+        gemm(h, mmax, nbj, 1, &cs, h->cold, h->n, epi_linear(-1.0, 1.0), &cb);
+      }
+      for (int t = 0; t < T; ++t) {
+        const int i = j + 1 + t;
+        pred[t] = (j > 0) ? h->rkd[(size_t)(i - 1) * nt + (j - 1)] : 48;
+      }
+      compress_column(h, h->cold + nbj, h->n, j + 1, T, j, nbj, h->Ud, h->Vtmp, h->rkd, pred, h->maxrank_t);
+      lowrank_trsm(h, j, j + 1, T, h->Vtmp, h->Vd, h->rkd);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(h->rk_d, h->rk.data(), (size_t)nt * nt * sizeof(int), hipMemcpyHostToDevice, h->s));
+  sync(h);
+}
+
+// log|Sigma~| and y = L^{-1} z (into vec[1]); returns (logdet, quad)
+void solve_forward(tlr_handle_s* h, const double* z, double* logdet, double* quad) {
+  const int nt = h->nt, nb = h->nb;
+  const int64_t n = h->n;
+  double* w = h->vec;
+  double* ys = h->vec + n;
+  HIPCHK(launch_copy_block(z, n, w, n, n, 1, h->s));
+  for (int j = 0; j < nt; ++j) {
+    const int nbj = tile_rows(h, j);
+    const int64_t r0 = (int64_t)j * nb;
+    HIPCHK(launch_gemv_n(dinv_tile(h, j), nb, nbj, nbj, w + r0, 1.0, 0.0, ys + r0, h->s));
+    if (j + 1 < nt) {
+      if (h->dense) {
+        const int64_t ldp = n - r0;
+        HIPCHK(launch_gemv_n(panel(h, h->Lp, j) + nbj, ldp, n - r0 - nbj, nbj, ys + r0, -1.0, 1.0, w + r0 + nbj,
+                             h->s));
+      } else {
+        LowRankApply a{};
+        a.U = h->U; a.V = h->V; a.slot = h->slot; a.ranks = h->rk_d;
+        a.n = n; a.nb = nb; a.nt = nt; a.fixed = j; a.forward = 1; a.v = ys; a.out = w; a.scale = -1.0;
+        HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s));
+      }
+    }
+  }
+  HIPCHK(launch_dot(ys, ys, n, h->scal + 2 * nt, h->s));
+  HIPCHK(hipMemcpyAsync(h->h_scal, h->scal, (2 * nt + 1) * sizeof(double), hipMemcpyDeviceToHost, h->s));
+  sync(h);
+  double ld = 0.0;
+  for (int j = 0; j < nt; ++j) ld += h->h_scal[j];
+  *logdet = 2.0 * ld;
+  *quad = h->h_scal[2 * nt];
+}
+
+// a = L^{-T} y with y = vec[1] (from solve_forward); result in vec[2]
+void solve_backward(tlr_handle_s* h) {
+  const int nt = h->nt, nb = h->nb;
+  const int64_t n = h->n;
+  double* ys = h->vec + n;
+  double* al = h->vec + 2 * n;
+  double* r = h->vec + 3 * n;
+  HIPCHK(launch_copy_block(ys, n, r, n, n, 1, h->s));
+  for (int i = nt - 1; i >= 0; --i) {
+    const int nbi = tile_rows(h, i);
+    const int64_t r0 = (int64_t)i * nb;
+    if (h->dense && i + 1 < nt) {
+      const int64_t ldp = n - r0;
+      HIPCHK(launch_gemv_t(panel(h, h->Lp, i) + nbi, ldp, n - r0 - nbi, nbi, al + r0 + nbi, -1.0, 1.0, r + r0, h->s));
+    }
+    HIPCHK(launch_gemv_t(dinv_tile(h, i), nb, nbi, nbi, r + r0, 1.0, 0.0, al + r0, h->s));
+    if (!h->dense && i > 0) {
+      LowRankApply a{};
+      a.U = h->U; a.V = h->V; a.slot = h->slot; a.ranks = h->rk_d;
+      a.n = n; a.nb = nb; a.nt = nt; a.fixed = i; a.forward = 0; a.v = al; a.out = r; a.scale = -1.0;
+      HIPCHK(launch_lowrank_apply(a, i, h->s));
+    }
+  }
+}
+
+tlr_status check_info(tlr_handle_s* h, int64_t* info) {
+  HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
+  sync(h);
+  const unsigned long long v = *h->h_info;
+  if (v != ~0ull) {
+    if (info) *info = (int64_t)v;
+    return TLR_ENOTSPD;
+  }
+  if (info) *info = 0;
+  return TLR_OK;
+}
+
+void rank_stats(tlr_handle_s* h) {
+  int64_t sum = 0;
+  int mx = 0;
+  for (int i = 0; i < h->nt; ++i)
+    for (int j = 0; j < i; ++j) {
+      sum += h->rk[(size_t)i * h->nt + j];
+      mx = std::max(mx, h->rk[(size_t)i * h->nt + j]);
+    }
+  h->info.rank_sum = sum;
+  h->info.rank_max = mx;
+}
+
+template <class F>
+tlr_status guarded(tlr_handle_s* h, F&& f) {
+  try {
+    return f();
+  } catch (const Fail& e) {
+    if (h && e.st == TLR_ERANK) {
+      h->info.bad_tile_i = h->bad_i;
+      h->info.bad_tile_j = h->bad_j;
+    }
+    if (h && e.st != TLR_ENOMEM) (void)hipStreamSynchronize(h->s);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return TLR_ENOMEM;
+  }
+}
+
+void free_all(tlr_handle_s* h) {
+  if (h->s) (void)hipStreamSynchronize(h->s);
+  for (void* p : h->dev_allocs) (void)hipFree(p);
+  for (void* p : h->host_allocs) (void)hipHostFree(p);
+  for (hipEvent_t& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t& e : h->evpool) (void)hipEventDestroy(e);
+  h->evpool.clear();
+  h->dev_allocs.clear();
+  h->host_allocs.clear();
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char* tlr_last_error(void) { return g_last_error; }
+
+tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
+  if (!out || !o) return TLR_EINVAL;
+  *out = nullptr;
+  if (o->n < 1 || o->nb < 32 || o->nb > kQrMaxRows || o->nb % 16 != 0) return TLR_EINVAL;
+  if (o->mode != TLR_MODE_TLR && o->mode != TLR_MODE_DENSE) return TLR_EINVAL;
+  if (o->prec != TLR_PREC_FP64 && o->prec != TLR_PREC_FP32_UPDATES) return TLR_EINVAL;
+  if (o->mode == TLR_MODE_TLR && !(o->tol > 0.0 && std::isfinite(o->tol))) return TLR_EINVAL;
+  if (o->prec == TLR_PREC_FP32_UPDATES && o->mode != TLR_MODE_TLR) return TLR_EINVAL;
+  tlr_handle_s* h = new (std::nothrow) tlr_handle_s();
+  if (!h) return TLR_ENOMEM;
+  tlr_status st = guarded(h, [&]() -> tlr_status {
+    h->o = *o;
+    h->s = (hipStream_t)stream;
+    HIPCHK(hipGetDevice(&h->device));
+    h->n = o->n;
+    h->nb = o->nb;
+    h->nt = (int)((o->n + o->nb - 1) / o->nb);
+    h->dense = (o->mode == TLR_MODE_DENSE);
+    h->grad = o->want_grad != 0;
+    int mr = o->maxrank > 0 ? o->maxrank : o->nb / 2;
+    mr = std::min(mr, o->nb);
+    mr = std::min(mr, kQrMaxCols - 64);
+    h->maxrank = mr;
+    h->maxrank_t = h->grad ? std::min(std::min(o->nb, mr + mr / 2), kQrMaxCols - 64) : mr;
+    const int mslot = std::max(mr, h->maxrank_t);
+    h->smax = (int)std::min<int64_t>(kQrMaxCols, pad16(mslot + 64));
+    h->slot = (int64_t)o->nb * mslot;
+    h->ntiles = (int64_t)h->nt * (h->nt - 1) / 2;
+    const int64_t n = h->n, nb = h->nb, nt = h->nt;
+    const int nterms = h->grad ? 2 : 1;
+    h->d_tab = dalloc<double>(h, kTabSize);
+    h->h_tab.assign(kTabSize, 0.0);
+    h->Dinv = dalloc<double>(h, nt * nb * nb);
+    h->col = dalloc<double>(h, n * nb);
+    if (h->grad) h->cold = dalloc<double>(h, n * nb);
+    h->tw = dalloc<double>(h, 64 * nb + 3 * nb * nb);
+    h->vec = dalloc<double>(h, 4 * n);
+    h->scal = dalloc<double>(h, 4 * nt + 16);
+    h->h_scal = halloc<double>(h, 4 * nt + 16);
+    h->info_d = dalloc<unsigned long long>(h, 1);
+    h->h_info = halloc<unsigned long long>(h, 1);
+    h->sk_cap = std::min<int64_t>(64ll << 20, 32 * std::max<int64_t>(n, 1024) * nb);
+    h->skw = dalloc<double>(h, h->sk_cap);
+    if (h->dense) {
+      h->Lp = dalloc<double>(h, panels_size(n, nb));
+      if (h->grad) h->Ldp = dalloc<double>(h, panels_size(n, nb));
+    } else {
+      h->D = dalloc<double>(h, nt * nb * nb);
+      h->U = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
+      h->V = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
+      h->rk_d = dalloc<int>(h, nt * nt);
+      h->rk.assign((size_t)nt * nt, 0);
+      if (h->grad) {
+        h->Dd = dalloc<double>(h, nt * nb * nb);
+        h->Ud = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
+        h->Vd = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
+        h->rkd_d = dalloc<int>(h, nt * nt);
+      }
+      h->rkd.assign((size_t)nt * nt, 0);
+      h->omega = dalloc<double>(h, nb * h->smax);
+      h->Ybuf = dalloc<double>(h, n * h->smax);
+      h->Q1 = dalloc<double>(h, n * h->smax);
+      h->Bt = dalloc<double>(h, nt * nb * h->smax);
+      h->Vtmp = dalloc<double>(h, nt * h->slot);
+      h->Zb = dalloc<double>(h, nt * h->smax * (mslot + 1));
+      const int64_t rmax = nterms * nt * pad16(mslot);
+      h->urow_cap = nb * rmax;
+      h->Urow = dalloc<double>(h, h->urow_cap);
+      int64_t wworst = 0, xworst = 0;
+      for (int64_t j = 0; j < nt; ++j) {
+        wworst = std::max(wworst, (nt - j) * nb * nterms * j * pad16(mslot));
+        xworst = std::max(xworst, (nt - j) * nterms * j * (int64_t)mslot * pad16(mslot));
+      }
+      h->w_cap = std::max<int64_t>(std::min<int64_t>(wworst, 512ll << 20), nb * rmax);
+      h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * mslot * pad16(mslot));
+      h->Wb = dalloc<double>(h, h->w_cap);
+      h->Xb = dalloc<double>(h, h->x_cap);
+      h->im_cap = h->lm_cap = std::max<int64_t>(1 << 16, 16 * nt * nt * nterms + 64 * nt);
+      h->im_d = dalloc<int>(h, h->im_cap);
+      h->im_h = halloc<int>(h, h->im_cap);
+      h->lm_d = dalloc<int64_t>(h, h->lm_cap);
+      h->lm_h = halloc<int64_t>(h, h->lm_cap);
+      h->tk_cap = (int)nt;
+      h->tk_d = dalloc<QrcpTask>(h, nt);
+      h->tk_h = halloc<QrcpTask>(h, nt);
+      h->qr_d = dalloc<int>(h, 2 * nt);
+      h->qr_h = halloc<int>(h, 2 * nt);
+      HIPCHK(launch_gaussian(h->omega, nb * h->smax, (uint32_t)o->seed, h->s));
+    }
+    for (hipEvent_t& e : h->ev) HIPCHK(hipEventCreate(&e));
+    reset_info(h);
+    HIPCHK(hipStreamSynchronize(h->s));
+    h->info.n = n;
+    h->info.nb = (int)nb;
+    h->info.nt = (int)nt;
+    h->info.maxrank = mr;
+    h->info.mode = o->mode;
+    h->info.device_bytes = h->bytes;
+    h->info.bad_tile_i = h->info.bad_tile_j = -1;
+    return TLR_OK;
+  });
+  if (st != TLR_OK) {
+    free_all(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return TLR_OK;
+}
+
+tlr_status tlr_destroy(tlr_handle_t h) {
+  if (!h) return TLR_OK;
+  free_all(h);
+  delete h;
+  return TLR_OK;
+}
+
+tlr_status tlr_generate(tlr_handle_t h, const double* d_x, const double* d_y, const double theta[3]) {
+  if (!h || !d_x || !d_y || !theta) return TLR_EINVAL;
+  return guarded(h, [&]() -> tlr_status {
+    MaternParams p{};
+    if (!matern_setup(theta[0], theta[1], theta[2], &p, h->h_tab.data())) return TLR_EINVAL;
+    HIPCHK(hipMemcpyAsync(h->d_tab, h->h_tab.data(), kTabSize * sizeof(double), hipMemcpyHostToDevice, h->s));
+    sync(h);
+    p.tab = h->d_tab;
+    h->mp = p;
+    h->x = d_x;
+    h->y = d_y;
+    for (int i = 0; i < 3; ++i) h->theta[i] = theta[i];
+    h->bound = true;
+    h->state = 0;
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_compress(tlr_handle_t h) {
+  if (!h) return TLR_EINVAL;
+  if (h->dense) return TLR_ENOTIMPL;
+  if (!h->bound) return TLR_ESTATE;
+  return guarded(h, [&]() -> tlr_status {
+    const int nt = h->nt, nb = h->nb;
+    std::fill(h->rk.begin(), h->rk.end(), 0);
+    reset_info(h);
+    sync(h);
+    meta_reset(h);
+    std::vector<int> pred(nt);
+    for (int j = 0; j < nt; ++j) {
+      const int nbj = tile_rows(h, j);
+      HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)j * nb, nbj, (int64_t)j * nb, nbj, diag_tile(h, j), nb,
+                                 false, h->s));
+      const int T = nt - j - 1;
+      if (T <= 0) continue;
+      const int64_t rows = h->n - (int64_t)(j + 1) * nb;
+      HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)(j + 1) * nb, rows, (int64_t)j * nb, nbj, h->col,
+                                 h->n, false, h->s));
+      for (int t = 0; t < T; ++t) pred[t] = (j > 0) ? h->rk[(size_t)(j + t) * nt + (j - 1)] : 48;
+      compress_column(h, h->col, h->n, j + 1, T, j, nbj, h->U, h->Vtmp, h->rk, pred, h->maxrank);
+      // V slots <- V~
+      int *m_d, *k_d;
+      int* m_h = im_take(h, T, &m_d);
+      int* k_h = im_take(h, T, &k_d);
+      int64_t *so_d, *do_d;
+      int64_t* so_h = lm_take(h, T, &so_d);
+      int64_t* do_h = lm_take(h, T, &do_d);
+      int64_t maxe = 0;
+      for (int t = 0; t < T; ++t) {
+        m_h[t] = nbj;
+        k_h[t] = h->rk[(size_t)(j + 1 + t) * nt + j];
+        so_h[t] = (int64_t)t * h->slot;
+        do_h[t] = slot_of(h, j + 1 + t, j) * h->slot;
+        maxe = std::max<int64_t>(maxe, (int64_t)nbj * k_h[t]);
+      }
+      im_push(h, m_h, m_d, 2 * (int64_t)T);
+      lm_push(h, so_h, so_d, 2 * (int64_t)T);
+      HIPCHK(launch_batched_copy(h->Vtmp, nb, so_d, h->V, nb, do_d, m_d, k_d, maxe, T, h->s));
+    }
+    sync(h);
+    rank_stats(h);
+    h->state = 1;
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_potrf(tlr_handle_t h, int64_t* info) {
+  if (!h) return TLR_EINVAL;
+  if (!h->bound) return TLR_ESTATE;
+  if (info) *info = 0;
+  return guarded(h, [&]() -> tlr_status {
+    prof_reset_pool(h);
+    h->state = 0;
+    HIPCHK(hipEventRecord(h->ev[0], h->s));
+    try {
+      if (h->dense) factor_dense(h, false); else factor_tlr(h, false);
+    } catch (const Fail& f) {
+      if (f.st == TLR_ENOTSPD) return check_info(h, info);
+      throw;
+    }
+    HIPCHK(hipEventRecord(h->ev[1], h->s));
+    const tlr_status st = check_info(h, info);
+    h->info.t_factor_ms = elapsed(h->ev[0], h->ev[1]);
+    if (!h->dense) rank_stats(h);
+    if (st != TLR_OK) return st;
+    h->state = 2;
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_loglik(tlr_handle_t h, const double* d_z, double* ll, double* logdet, double* quad) {
+  if (!h || !d_z) return TLR_EINVAL;
+  if (h->state < 2) return TLR_ESTATE;
+  return guarded(h, [&]() -> tlr_status {
+    double ld = 0.0, q = 0.0;
+    HIPCHK(hipEventRecord(h->ev[2], h->s));
+    solve_forward(h, d_z, &ld, &q);
+    HIPCHK(hipEventRecord(h->ev[3], h->s));
+    sync(h);
+    h->info.t_solve_ms = elapsed(h->ev[2], h->ev[3]);
+    const double n = (double)h->n;
+    if (ll) *ll = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * ld - 0.5 * q;
+    if (logdet) *logdet = ld;
+    if (quad) *quad = q;
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z) {
+  if (!h || !d_eps || !d_z || d_eps == d_z) return TLR_EINVAL;
+  if (h->state < 2) return TLR_ESTATE;
+  return guarded(h, [&]() -> tlr_status {
+    const int nt = h->nt, nb = h->nb;
+    const int64_t n = h->n;
+    for (int j = 0; j < nt; ++j) {
+      const int nbj = tile_rows(h, j);
+      const int64_t r0 = (int64_t)j * nb;
+      const double* Ljj = h->dense ? panel(h, h->Lp, j) : diag_tile(h, j);
+      const int64_t ldl = h->dense ? n - r0 : nb;
+      HIPCHK(launch_gemv_n(Ljj, ldl, nbj, nbj, d_eps + r0, 1.0, 0.0, d_z + r0, h->s));
+    }
+    for (int j = 0; j < nt - 1; ++j) {
+      const int nbj = tile_rows(h, j);
+      const int64_t r0 = (int64_t)j * nb;
+      if (h->dense) {
+        HIPCHK(launch_gemv_n(panel(h, h->Lp, j) + nbj, n - r0, n - r0 - nbj, nbj, d_eps + r0, 1.0, 1.0,
+                             d_z + r0 + nbj, h->s));
+      } else {
+        LowRankApply a{};
+        a.U = h->U; a.V = h->V; a.slot = h->slot; a.ranks = h->rk_d;
+        a.n = n; a.nb = nb; a.nt = nt; a.fixed = j; a.forward = 1; a.v = d_eps; a.out = d_z; a.scale = 1.0;
+        HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s));
+      }
+    }
+    sync(h);
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_profile(tlr_handle_t h, int32_t enable) {
+  if (!h) return TLR_EINVAL;
+  return guarded(h, [&]() -> tlr_status {
+    sync(h);
+    prof_reset_pool(h);
+    h->prof = enable != 0;
+    for (auto& k : h->kst) k = tlr_kstat{};
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_get_kstats(tlr_handle_t h, tlr_kstat* out) {
+  if (!h || !out) return TLR_EINVAL;
+  for (int i = 0; i < TLR_K_COUNT; ++i) out[i] = h->kst[i];
+  return TLR_OK;
+}
+
+tlr_status tlr_get_ranks(tlr_handle_t h, int32_t* host_ranks) {
+  if (!h || !host_ranks) return TLR_EINVAL;
+  for (size_t i = 0; i < (size_t)h->nt * h->nt; ++i) host_ranks[i] = h->dense ? 0 : h->rk[i];
+  return TLR_OK;
+}
+
+tlr_status tlr_get_info(tlr_handle_t h, tlr_info* out) {
+  if (!h || !out) return TLR_EINVAL;
+  *out = h->info;
+  return TLR_OK;
+}
+
+tlr_status tlr_get_tile(tlr_handle_t h, int32_t i, int32_t j, double* d_out, int64_t ld) {
+  if (!h || !d_out || i < 0 || j < 0 || i >= h->nt || j > i) return TLR_EINVAL;
+  if (ld < tile_rows(h, i)) return TLR_EINVAL;
+  if (h->state < 1 || (h->dense && h->state < 2)) return TLR_ESTATE;
+  return guarded(h, [&]() -> tlr_status {
+    const int mi = tile_rows(h, i), mj = tile_rows(h, j);
+    if (h->dense) {
+      const int64_t ldp = h->n - (int64_t)j * h->nb;
+      HIPCHK(launch_copy_block(panel(h, h->Lp, j) + (int64_t)(i - j) * h->nb, ldp, d_out, ld, mi, mj, h->s));
+    } else if (i == j) {
+      HIPCHK(launch_copy_block(diag_tile(h, i), h->nb, d_out, ld, mi, mj, h->s));
+    } else {
+      const int k = h->rk[(size_t)i * h->nt + j];
+      GemmSeg sg{};
+      sg.A = op_contig(h->U + slot_of(h, i, j) * h->slot, h->nb, 0, 0);
+      sg.B = op_contig(h->V + slot_of(h, i, j) * h->slot, h->nb, 0, 0);
+      sg.K = k;
+      gemm(h, mi, mj, 1, &sg, d_out, ld, epi_linear(1.0, 0.0));
+    }
+    sync(h);
+    return TLR_OK;
+  });
+}
+
+tlr_status tlr_covariance_block(tlr_handle_t h, int64_t r0, int64_t m, int64_t c0, int64_t k, int32_t deriv,
+                                double* d_out, int64_t ld) {
+  if (!h || !d_out || m < 0 || k < 0 || r0 < 0 || c0 < 0 || r0 + m > h->n || c0 + k > h->n || ld < m)
+    return TLR_EINVAL;
+  if (!h->bound) return TLR_ESTATE;
+  return guarded(h, [&]() -> tlr_status {
+    HIPCHK(launch_matern_block(h->mp, h->x, h->y, r0, m, c0, k, d_out, ld, deriv != 0, h->s));
+    sync(h);
+    return TLR_OK;
+  });
+}
+
+}  // extern "C"
+
+extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
+                                      const double theta[3], double* ll, double grad[2], int64_t* info) {
+  if (!h || !d_x || !d_y || !d_z || !theta || !grad) return TLR_EINVAL;
+  if (!h->grad) return TLR_ESTATE;
+  if (info) *info = 0;
+  tlr_status st = tlr_generate(h, d_x, d_y, theta);
+  if (st != TLR_OK) return st;
+  return guarded(h, [&]() -> tlr_status {
+    prof_reset_pool(h);
+    h->state = 0;
+    HIPCHK(hipEventRecord(h->ev[0], h->s));
+    try {
+      if (h->dense) factor_dense(h, true); else factor_tlr(h, true);
+    } catch (const Fail& f) {
+      if (f.st == TLR_ENOTSPD) return check_info(h, info);
+      throw;
+    }
+    HIPCHK(hipEventRecord(h->ev[1], h->s));
+    const tlr_status fst = check_info(h, info);
+    h->info.t_factor_ms = elapsed(h->ev[0], h->ev[1]);
+    if (!h->dense) rank_stats(h);
+    if (fst != TLR_OK) return fst;
+    h->state = 3;
+    double ld = 0.0, q = 0.0;
+    HIPCHK(hipEventRecord(h->ev[2], h->s));
+    const size_t e_s = prof_mark(h);
+    solve_forward(h, d_z, &ld, &q);
+    solve_backward(h);
+    prof_add(h, TLR_K_SOLVE, e_s, 0.0, 0.0);
+    HIPCHK(hipEventRecord(h->ev[3], h->s));
+    const size_t e_q = prof_mark(h);
+    // a^T dSigma/dbeta a over all pairs; partial sums in the split-K workspace
+    const int64_t nblk = pair_quad_blocks(h->n);
+    if (nblk > h->sk_cap) throw Fail{TLR_ENOMEM};
+    HIPCHK(launch_pair_quad(h->mp, h->x, h->y, h->vec + 2 * h->n, h->n, h->skw, h->scal + 2 * h->nt + 1, h->s));
+    prof_add(h, TLR_K_GRADQ, e_q, (double)h->n * (double)(h->n - 1) / 2.0, 24.0 * h->n);
+    HIPCHK(hipEventRecord(h->ev[1], h->s));
+    HIPCHK(hipMemcpyAsync(h->h_scal, h->scal, (2 * h->nt + 2) * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    sync(h);
+    h->info.t_solve_ms = elapsed(h->ev[2], h->ev[3]);
+    h->info.t_grad_ms = elapsed(h->ev[3], h->ev[1]);
+    double trace = 0.0;
+    for (int j = 0; j < h->nt; ++j) trace += h->h_scal[h->nt + j];
+    const double qf = h->h_scal[2 * h->nt + 1];
+    const double n = (double)h->n;
+    if (ll) *ll = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * ld - 0.5 * q;
+    grad[0] = (q - n) / (2.0 * h->theta[0]);
+    grad[1] = -0.5 * trace + 0.5 * qf;
+    return TLR_OK;
+  });
+}

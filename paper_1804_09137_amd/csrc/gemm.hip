@@ -1,0 +1,312 @@
+// FP64 MFMA GEMM for gfx950: C = epilogue(sum_s A_s B_s^T).
+//
+// One workgroup of 256 threads (4 wave64s) computes a BM x BN block of C with
+// v_mfma_f64_16x16x4f64.  K is consumed in BK = 16 slices staged through LDS;
+// the next slice is fetched into registers while the current one is used.
+// The operand roles are swapped inside the MFMA (B feeds the 16-row side) so
+// that each output register holds 16 consecutive rows of one column of the
+// column-major C: stores are 128-byte runs.
+//
+// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950):
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+//   D[i][j] in lane j + 16 (i mod 4), register i / 4.
+//
+// Workgroups are remapped so that the tiles sharing a row panel of A run
+// consecutively on one XCD (the 8 XCDs each have their own L2; hardware hands
+// workgroup w to XCD w mod 8).
+#include "kernels.h"
+#include "matern.h"
+
+namespace tlrk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;
+constexpr int PAD = 16;
+constexpr int kXcds = 8;
+
+struct GemmArgs {
+  int64_t M, N;
+  int nseg;
+  GemmSeg seg[2];
+  int64_t kt[2];       // BK-slices per segment (K padded up to BK)
+  int64_t kt_total;
+  double* C;
+  int64_t ldc;
+  GemmEpi ep;
+  GemmBatch batch;
+  int splitk;
+  double* work;
+  int64_t gx, gy;      // tile grid
+};
+
+// Per-slice column addressing of an operand: element (row gr, slice column kk)
+// lives at colbase(kk) + gr (kContig / kPanels) or rowbase(gr) + kk (kContigT).
+struct SliceAddr {
+  const double* base;
+  int64_t ld;
+  int64_t col0;   // first column of the slice in the operand's own frame
+  int64_t rofs;   // row offset added to gr
+};
+
+__device__ inline SliceAddr slice_addr(const Operand& o, int64_t bofs, int64_t kc) {
+  SliceAddr s;
+  if (o.layout == kPanels) {
+    const int64_t c = o.c0 + kc;               // global column of the slice start
+    const int64_t p = c / o.nb;                 // one panel holds the whole slice
+    s.base = o.base + bofs + panel_offset(o.n, o.nb, p);
+    s.ld = o.n - p * o.nb;
+    s.col0 = c - p * o.nb;
+    s.rofs = o.r0 - p * o.nb;
+  } else {
+    s.base = o.base + bofs;
+    s.ld = o.ld;
+    s.col0 = o.c0 + kc;
+    s.rofs = o.r0;
+  }
+  return s;
+}
+
+template <int ROWS>
+__device__ inline void load_slice(const Operand& o, const SliceAddr& sa, int64_t row0, int64_t R, int64_t kc,
+                                  int64_t K, double (&v)[ROWS * BK / 256], int tid) {
+  constexpr int NE = ROWS * BK / 256;
+  if (o.layout == kContigT) {
+    const int kk = tid % BK;
+    const bool kin = (kc + kk) < K;
+#pragma unroll
+    for (int p = 0; p < NE; ++p) {
+      const int r = tid / BK + (256 / BK) * p;
+      const int64_t gr = row0 + r;
+      v[p] = (kin && gr < R) ? sa.base[(sa.rofs + gr) * sa.ld + sa.col0 + kk] : 0.0;
+    }
+  } else {
+    const int r = tid % ROWS;
+    const int64_t gr = row0 + r;
+    const bool rin = gr < R;
+#pragma unroll
+    for (int p = 0; p < NE; ++p) {
+      const int kk = tid / ROWS + (256 / ROWS) * p;
+      v[p] = (rin && (kc + kk) < K) ? sa.base[(sa.col0 + kk) * sa.ld + sa.rofs + gr] : 0.0;
+    }
+  }
+}
+
+template <int ROWS>
+__device__ inline void store_slice(int layout, double (*s)[ROWS + PAD], const double (&v)[ROWS * BK / 256],
+                                   int tid) {
+  constexpr int NE = ROWS * BK / 256;
+  if (layout == kContigT) {
+    const int kk = tid % BK;
+#pragma unroll
+    for (int p = 0; p < NE; ++p) s[kk][tid / BK + (256 / BK) * p] = v[p];
+  } else {
+    const int r = tid % ROWS;
+#pragma unroll
+    for (int p = 0; p < NE; ++p) s[tid / ROWS + (256 / ROWS) * p][r] = v[p];
+  }
+}
+
+__device__ inline void epi_store(const GemmEpi& ep, double* C, int64_t ldc, int64_t m, int64_t n, double v,
+                                 int64_t grow0) {
+  double* c = C + n * ldc + m;
+  if (ep.kind == kEpiLinear) {
+    double o = ep.alpha * v;
+    if (ep.beta != 0.0) o += ep.beta * (*c);
+    *c = o;
+  } else {
+    const double r = loc_dist(ep.x, ep.y, grow0 + m, ep.gcol0 + n);
+    double cv, dv;
+    if (ep.kind == kEpiGenMinus) {
+      matern_eval<false>(ep.mp, r, cv, dv);
+      *c = cv - v;
+    } else {
+      matern_eval<true>(ep.mp, r, cv, dv);
+      *c = dv - v;
+    }
+  }
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  __shared__ double sA[BK][BM + PAD];
+  __shared__ double sB[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wm = w % WM;
+  const int wn = w / WM;
+
+  // XCD-aware remap of the 1-D grid (padded to a multiple of kXcds).
+  const int64_t total = g.gx * g.gy;
+  const int64_t per = (total + kXcds - 1) / kXcds;
+  const int64_t wid = blockIdx.x;
+  const int64_t logical = (wid % kXcds) * per + wid / kXcds;
+  if (logical >= total) return;
+  const int64_t tm = logical / g.gy;
+  const int64_t tn = logical - tm * g.gy;
+  const int z = blockIdx.y;
+
+  int64_t M = g.M, N = g.N;
+  int64_t Kb[2] = {g.seg[0].K, g.nseg > 1 ? g.seg[1].K : 0};
+  int64_t c_off = 0, grow0 = g.ep.grow0;
+  int64_t aofs[2] = {0, 0}, bofs[2] = {0, 0};
+  int64_t ks = 0, ke = g.kt_total;
+  if (g.splitk > 1) {
+    const int64_t chunk = (g.kt_total + g.splitk - 1) / g.splitk;
+    ks = z * chunk;
+    ke = ks + chunk < g.kt_total ? ks + chunk : g.kt_total;
+  } else if (g.batch.count > 1 || g.batch.a_off || g.batch.m_of) {
+    c_off = g.batch.c_off ? g.batch.c_off[z] : z * g.batch.c_bstride;
+    grow0 += z * g.ep.grow_bstride;
+    for (int s = 0; s < g.nseg; ++s) {
+      aofs[s] = z * g.seg[s].a_bstride;
+      bofs[s] = z * g.seg[s].b_bstride;
+    }
+    if (g.batch.a_off) aofs[0] = g.batch.a_off[z];
+    if (g.batch.b_off) bofs[0] = g.batch.b_off[z];
+    if (g.batch.m_of) M = g.batch.m_of[z];
+    if (g.batch.n_of) N = g.batch.n_of[z];
+    if (g.batch.k_of) { Kb[0] = g.batch.k_of[z]; }
+  }
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double va[BM * BK / 256], vb[BN * BK / 256];
+  auto fetch = [&](int64_t t) {
+    int s = 0;
+    int64_t tl = t;
+    if (g.nseg > 1 && tl >= g.kt[0]) { s = 1; tl -= g.kt[0]; }
+    const GemmSeg& sg = g.seg[s];
+    const int64_t kc = tl * BK;
+    const SliceAddr saA = slice_addr(sg.A, aofs[s], kc);
+    const SliceAddr saB = slice_addr(sg.B, bofs[s], kc);
+    load_slice<BM>(sg.A, saA, m0, M, kc, Kb[s], va, tid);
+    load_slice<BN>(sg.B, saB, n0, N, kc, Kb[s], vb, tid);
+    return s;
+  };
+
+  if (ks < ke) {
+    int sc = fetch(ks);
+    for (int64_t t = ks; t < ke; ++t) {
+      store_slice<BM>(g.seg[sc].A.layout, sA, va, tid);
+      store_slice<BN>(g.seg[sc].B.layout, sB, vb, tid);
+      __syncthreads();
+      if (t + 1 < ke) sc = fetch(t + 1);
+#pragma unroll
+      for (int k4 = 0; k4 < BK / 4; ++k4) {
+        const int kr = k4 * 4 + (lane >> 4);
+        double a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = sA[kr][wm * (BM / WM) + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = sB[kr][wn * (BN / WN) + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+
+  // epilogue: lane holds rows m = .. + (lane & 15), columns n = .. + (lane >> 4) + 4 r
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int64_t m = m0 + wm * (BM / WM) + i * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t n = n0 + wn * (BN / WN) + j * 16 + (lane >> 4) + 4 * r;
+        if (m < M && n < N) {
+          const double v = acc[i][j][r];
+          if (g.splitk > 1)
+            g.work[(int64_t)z * g.M * g.N + n * g.M + m] = v;
+          else
+            epi_store(g.ep, g.C + c_off, g.ldc, m, n, v, grow0);
+        }
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= g.M * g.N) return;
+  const int64_t n = idx / g.M;
+  const int64_t m = idx - n * g.M;
+  double v = 0.0;
+  for (int z = 0; z < g.splitk; ++z) v += g.work[(int64_t)z * g.M * g.N + idx];
+  epi_store(g.ep, g.C, g.ldc, m, n, v, g.ep.grow0);
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t run(GemmArgs& g, int zdim, hipStream_t s) {
+  g.gx = (g.M + BM - 1) / BM;
+  g.gy = (g.N + BN - 1) / BN;
+  const int64_t total = g.gx * g.gy;
+  const int64_t grid = ((total + kXcds - 1) / kXcds) * kXcds;
+  if (grid > 0x7fffffff || zdim > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN>), dim3((unsigned)grid, (unsigned)zdim), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
+                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s) {
+  if (M < 0 || N < 0 || nseg < 1 || nseg > 2 || splitk < 1) return hipErrorInvalidValue;
+  if (M == 0 || N == 0) return hipSuccess;
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.nseg = nseg;
+  g.kt_total = 0;
+  for (int i = 0; i < nseg; ++i) {
+    g.seg[i] = segs[i];
+    if (segs[i].K < 0) return hipErrorInvalidValue;
+    for (const Operand* o : {&segs[i].A, &segs[i].B})
+      if (o->layout == kPanels && (o->nb % BK != 0 || o->c0 % BK != 0)) return hipErrorInvalidValue;
+    g.kt[i] = (segs[i].K + BK - 1) / BK;
+    g.kt_total += g.kt[i];
+  }
+  g.C = C;
+  g.ldc = ldc;
+  g.ep = ep;
+  if (batch) g.batch = *batch; else { g.batch = GemmBatch{}; g.batch.count = 1; }
+  if (g.batch.count < 1) return hipErrorInvalidValue;
+  if (splitk > 1 && (g.batch.count > 1 || work == nullptr)) return hipErrorInvalidValue;
+  if (g.kt_total == 0) splitk = 1;
+  if (splitk > g.kt_total && g.kt_total > 0) splitk = (int)g.kt_total;
+  g.splitk = splitk;
+  g.work = work;
+  const int zdim = splitk > 1 ? splitk : g.batch.count;
+  hipError_t e;
+  const int bm = (M <= 32) ? 32 : (M <= 64) ? 64 : 128;
+  const int bn = (N <= 32) ? 32 : (N <= 64) ? 64 : 128;
+  switch (bm * 1000 + bn) {
+    case 32032: e = run<32, 32, 2, 2>(g, zdim, s); break;
+    case 32064: e = run<32, 64, 2, 2>(g, zdim, s); break;
+    case 32128: e = run<32, 128, 2, 2>(g, zdim, s); break;
+    case 64032: e = run<64, 32, 2, 2>(g, zdim, s); break;
+    case 64064: e = run<64, 64, 2, 2>(g, zdim, s); break;
+    case 64128: e = run<64, 128, 2, 2>(g, zdim, s); break;
+    case 128032: e = run<128, 32, 2, 2>(g, zdim, s); break;
+    case 128064: e = run<128, 64, 2, 2>(g, zdim, s); break;
+    default: e = run<128, 128, 2, 2>(g, zdim, s); break;
+  }
+  if (e != hipSuccess || splitk == 1) return e;
+  const int64_t tot = M * N;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace tlrk

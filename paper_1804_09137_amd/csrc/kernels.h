@@ -1,0 +1,55 @@
+// Launch wrappers of the HIP kernels (host-callable, stream-ordered).
+#pragma once
+#include "common.h"
+
+namespace tlrk {
+
+// ---------------------------------------------------------------- matern.hip
+hipError_t launch_matern_block(const MaternParams& p, const double* x, const double* y, int64_t r0, int64_t m,
+                               int64_t c0, int64_t ncol, double* out, int64_t ld, bool deriv, hipStream_t s);
+
+// ------------------------------------------------------------------ gemm.hip
+// C[M x N] = epilogue( sum_s A_s[M x K_s] * B_s[N x K_s]^T ), FP64 MFMA.
+// Operand layouts: kContig (rows contiguous), kContigT (columns contiguous,
+// i.e. X[r, c] = base[(r0 + r) * ld + c0 + c]) and kPanels.
+enum : int { kContigT = 2 };
+
+enum EpiKind : int {
+  kEpiLinear = 0,    // C = alpha * acc + beta * C_in
+  kEpiGenMinus = 1,  // C = Matérn(theta)(rows, cols) - acc
+  kEpiDGenMinus = 2, // C = dMatérn/dbeta(rows, cols) - acc
+};
+
+struct GemmSeg {
+  Operand A, B;
+  int64_t K;
+  int64_t a_bstride, b_bstride;  // element offset of batch z
+};
+
+struct GemmEpi {
+  int kind;
+  double alpha, beta;
+  MaternParams mp;
+  const double* x;  // locations (kEpiGen*)
+  const double* y;
+  int64_t grow0, gcol0;     // global point index of output row 0 / col 0
+  int64_t grow_bstride;     // per-batch shift of grow0
+};
+
+struct GemmBatch {
+  int count;                 // >= 1
+  int64_t c_bstride;         // element offset of batch z in C
+  const int* m_of;           // optional device arrays: per-batch M, N, K (<= the launch M, N, K)
+  const int* n_of;
+  const int* k_of;
+  const int64_t* a_off;      // optional device arrays: per-batch element offsets of
+  const int64_t* b_off;      //   segment 0's A and B and of C (replace the strides)
+  const int64_t* c_off;
+};
+
+// Returns hipErrorInvalidValue on bad shapes.  work (may be null) must hold
+// splitk * M * N doubles when splitk > 1 (batch count must be 1 then).
+hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
+                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s);
+
+}  // namespace tlrk

@@ -1,0 +1,66 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, validates arguments before touching the GPU, and its host Morton
+helper reproduces the oracle's ordering bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ordering as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1804_09137_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libtlrmle.so not built (run __graft_entry__.build())")
+    return _lib, _lib.load()
+
+
+def test_header_symbols_exported():
+    _m, lib = _lib()
+    header = open(os.path.join(ROOT, "include", "tlr.h")).read()
+    declared = set(re.findall(r"^(?:tlr_status|const char\*)\s+(tlr_\w+)\s*\(", header, flags=re.M))
+    assert declared == set(_m.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_create_rejects_bad_options_without_gpu():
+    m, lib = _lib()
+    h = ctypes.c_void_p()
+    bad = [dict(n=0, nb=64, tol=1e-9), dict(n=100, nb=40, tol=1e-9), dict(n=100, nb=2048, tol=1e-9),
+           dict(n=100, nb=64, tol=0.0), dict(n=100, nb=64, tol=float("nan")),
+           dict(n=100, nb=64, tol=1e-9, mode=7), dict(n=100, nb=64, tol=1e-9, mode=1, prec=1)]
+    for kw in bad:
+        o = m.Opts()
+        o.n, o.nb, o.tol = kw["n"], kw["nb"], kw["tol"]
+        o.mode, o.prec = kw.get("mode", 0), kw.get("prec", 0)
+        assert lib.tlr_create(ctypes.byref(h), ctypes.byref(o), None) == m.TLR_EINVAL
+    assert lib.tlr_create(None, None, None) == m.TLR_EINVAL
+    assert lib.tlr_destroy(None) == m.TLR_OK
+    assert lib.tlr_potrf(None, None) == m.TLR_EINVAL
+    assert lib.tlr_loglik(None, None, None, None, None) == m.TLR_EINVAL
+
+
+@pytest.mark.parametrize("m,seed", [(40, 0), (57, 3), (200, 0)])
+def test_morton_matches_oracle(m, seed):
+    from paper_1804_09137_amd import morton_order
+    _lib()
+    x, y = synth.jittered_grid(m, seed)
+    np.testing.assert_array_equal(morton_order(x, y), O.morton_order(x, y))
+
+
+def test_morton_edge_cases():
+    from paper_1804_09137_amd import morton_order
+    _lib()
+    assert morton_order(np.array([0.3]), np.array([0.7])).tolist() == [0]
+    x = np.array([0.5, 0.5, 0.5, 0.5])
+    y = np.array([0.2, 0.1, 0.2, 0.1])
+    np.testing.assert_array_equal(morton_order(x, y), O.morton_order(x, y))
+    x, y = synth.jittered_subset(2345, seed=4)
+    np.testing.assert_array_equal(morton_order(x, y), O.morton_order(x, y))
