@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=5000)
+    ap.add_argument("--z-white", action="store_true",
+                    help="z = eps (skips the dense comparator; for profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -105,7 +107,10 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic"}
     dense = None
-    if not args.no_dense:
+    if args.z_white:
+        args.no_dense = True
+        zd = ed.clone()
+    elif not args.no_dense:
         log(f"[bench] dense FP64 handle n={n} nb={args.dense_nb}")
         hd = P.Handle(n, args.dense_nb, mode="dense", want_grad=True)
         hd.generate(xd, yd, th)
@@ -125,7 +130,7 @@ def main():
         hd.close()
         del hd
         torch.cuda.empty_cache()
-    else:
+    if args.no_dense and not args.z_white:
         log("[bench] --no-dense: z from a TLR factor at eps=1e-10")
         hz = P.Handle(n, args.nb, tol=1e-10, maxrank=args.nb // 2)
         hz.generate(xd, yd, th)

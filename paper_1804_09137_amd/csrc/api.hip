@@ -299,14 +299,14 @@ int choose_splitk(const tlr_handle_s* h, int64_t M, int64_t N, int64_t K) {
 }
 
 void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
-          const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false) {
+          const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false, int tm = 0, int tn = 0) {
   int sk = 1;
   if (allow_split && !b) {
     int64_t K = 0;
     for (int i = 0; i < nseg; ++i) K += segs[i].K;
     sk = choose_splitk(h, M, N, K);
   }
-  HIPCHK(launch_gemm(M, N, nseg, segs, C, ldc, ep, b, sk, sk > 1 ? h->skw : nullptr, h->s));
+  HIPCHK(launch_gemm(M, N, nseg, segs, C, ldc, ep, b, sk, sk > 1 ? h->skw : nullptr, h->s, tm, tn));
 }
 
 // ---------------------------------------------------------------------------
@@ -327,63 +327,99 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
   const int nb = h->nb;
   const size_t e_c = prof_mark(h);
   double cflops = 0.0;
-  int s = 32;
-  for (int t = 0; t < T; ++t) s = std::max(s, (int)pad16(pred[t] + 24));
-  s = std::min(s, h->smax);
   const double tol = h->o.tol;
   const double tol_range = 0.05 * tol;  // range finder residual target (Frobenius of the samples)
   const double tol_trunc = 0.9 * tol;
-  std::vector<int> t1(T);
-  for (;;) {
-    // 1. sketch Y = C Omega for all tiles at once
-    int64_t rows = 0;
-    for (int t = 0; t < T; ++t) rows += tile_rows(h, i_first + t);
-    GemmSeg sg{};
-    sg.A = op_contig(src, ld, 0, 0);
-    sg.B = op_contigT(h->omega, nb, 0, 0);
-    sg.K = ncols;
-    gemm(h, rows, s, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0));
-    // 2. pivoted QR of each tile's samples: orthonormal range basis Q1
-    for (int t = 0; t < T; ++t) {
-      QrcpTask& q = h->tk_h[t];
-      q = QrcpTask{};
-      q.Y = h->Ybuf + (int64_t)t * nb;
-      q.ldy = h->n;
-      q.m = tile_rows(h, i_first + t);
-      q.q = s;
-      q.tol = tol_range * std::sqrt((double)s);
-      q.max_rank = s;
-      q.min_tail = 8;
-      q.Q = h->Q1 + (int64_t)t * nb;
-      q.ldq = h->n;
-      q.rank = h->qr_d + t;
-      q.flag = h->qr_d + h->nt + t;
+  // per-tile sketch widths from the predicted ranks; a tile whose samples are
+  // not exhausted (fewer than 8 unused columns left) is sketched again, alone,
+  // with twice the width
+  std::vector<int> sz(T), t1(T), todo;
+  for (int t = 0; t < T; ++t) {
+    sz[t] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred[t] + 16)));
+    todo.push_back(t);
+  }
+  bool first = true;
+  while (!todo.empty()) {
+    int swide = 0;
+    for (int t : todo) swide = std::max(swide, sz[t]);
+    const int cnt = (int)todo.size();
+    if (first) {  // 1. sketch Y = C Omega for all tiles at once
+      int64_t rows = 0;
+      for (int t = 0; t < T; ++t) rows += tile_rows(h, i_first + t);
+      GemmSeg sg{};
+      sg.A = op_contig(src, ld, 0, 0);
+      sg.B = op_contigT(h->omega, nb, 0, 0);
+      sg.K = ncols;
+      gemm(h, rows, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0));
+    } else {      // re-sketch only the tiles in todo
+      int *m_d, *n_d;
+      int* m_h = im_take(h, cnt, &m_d);
+      int* n_h = im_take(h, cnt, &n_d);
+      int64_t *a_d, *c_d;
+      int64_t* a_h = lm_take(h, cnt, &a_d);
+      int64_t* c_h = lm_take(h, cnt, &c_d);
+      int maxm = 1;
+      for (int q = 0; q < cnt; ++q) {
+        const int t = todo[q];
+        m_h[q] = tile_rows(h, i_first + t);
+        n_h[q] = sz[t];
+        a_h[q] = (int64_t)t * nb;
+        c_h[q] = (int64_t)t * nb;
+        maxm = std::max(maxm, m_h[q]);
+      }
+      im_push(h, m_h, m_d, 2 * (int64_t)cnt);
+      lm_push(h, a_h, a_d, 2 * (int64_t)cnt);
+      GemmSeg sg{};
+      sg.A = op_contig(src, ld, 0, 0);
+      sg.B = op_contigT(h->omega, nb, 0, 0);
+      sg.K = ncols;
+      GemmBatch bt{};
+      bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
+      gemm(h, maxm, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0), &bt);
     }
-    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, T * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_qrcp(h->tk_d, T, h->s));
+    // 2. pivoted QR of each tile's samples: orthonormal range basis Q1
+    for (int q = 0; q < cnt; ++q) {
+      const int t = todo[q];
+      QrcpTask& tk = h->tk_h[q];
+      tk = QrcpTask{};
+      tk.Y = h->Ybuf + (int64_t)t * nb;
+      tk.ldy = h->n;
+      tk.m = tile_rows(h, i_first + t);
+      tk.q = sz[t];
+      tk.tol = tol_range * std::sqrt((double)sz[t]);
+      tk.max_rank = sz[t];
+      tk.min_tail = 8;
+      tk.Q = h->Q1 + (int64_t)t * nb;
+      tk.ldq = h->n;
+      tk.rank = h->qr_d + t;
+      tk.flag = h->qr_d + h->nt + t;
+    }
+    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, cnt * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_qrcp(h->tk_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
     sync(h);
+    meta_reset(h);
     throw_if_not_spd(h);
-    bool redo = false;
-    for (int t = 0; t < T; ++t) {
+    std::vector<int> next;
+    for (int q = 0; q < cnt; ++q) {
+      const int t = todo[q];
       t1[t] = h->qr_h[t];
-      if (h->qr_h[h->nt + t]) redo = true;
       const double m = tile_rows(h, i_first + t);
-      cflops += 2.0 * m * s * ncols + 4.0 * m * s * t1[t] + 2.0 * m * t1[t] * t1[t];
+      cflops += 2.0 * m * sz[t] * ncols + 4.0 * m * sz[t] * t1[t] + 2.0 * m * t1[t] * t1[t];
+      if (h->qr_h[h->nt + t]) {
+        if (sz[t] >= h->smax) {
+          h->bad_i = i_first + t;
+          h->bad_j = col;
+          throw Fail{TLR_ERANK};
+        }
+        sz[t] = std::min(h->smax, 2 * sz[t]);
+        next.push_back(t);
+      }
     }
-    if (!redo) break;
-    if (s >= h->smax) {
-      int worst = 0;
-      for (int t = 0; t < T; ++t)
-        if (h->qr_h[h->nt + t]) { worst = t; break; }
-      h->bad_i = i_first + worst;
-      h->bad_j = col;
-      throw Fail{TLR_ERANK};
-    }
-    s = std::min(h->smax, 2 * s);
+    todo.swap(next);
+    first = false;
   }
-  meta_reset(h);
   // 3. project: Bt_t = C_t^T Q1_t (ncols x t1)
   int *m_d, *n_d, *k_d;
   int* m_h = im_take(h, T, &m_d);
@@ -418,7 +454,7 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     bt.a_off = a_d;
     bt.b_off = b_d;
     bt.c_off = c_d;
-    gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt);
+    gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
   }
   // 4. truncation by pivoted QR of Bt: V~ = Q2[:, :k], Z = Pi R2[:k, :]^T
   for (int t = 0; t < T; ++t) {
@@ -493,7 +529,7 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
   bt.a_off = a_d;
   bt.b_off = b_d;
   bt.c_off = c_d;
-  gemm(h, maxm, maxk, 1, &sg, Uslots, nb, epi_linear(1.0, 0.0), &bt);
+  gemm(h, maxm, maxk, 1, &sg, Uslots, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
   prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
 }
 
@@ -537,7 +573,7 @@ void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt
   bt.b_off = b_d;
   bt.c_off = c_d;
   const size_t e_t = prof_mark(h);
-  gemm(h, nbj, maxk, 1, &sg, Vslots, h->nb, epi_linear(1.0, 0.0), &bt);
+  gemm(h, nbj, maxk, 1, &sg, Vslots, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
   double kt = 0.0;
   for (int t = 0; t < T; ++t) kt += n_h[t];
   prof_add(h, TLR_K_LOWRANK, e_t, 2.0 * nbj * nbj * kt, 8.0 * (2.0 * nbj * kt + (double)nbj * nbj));
@@ -686,7 +722,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
         xb.count = cnt;
         xb.m_of = xm_d; xb.n_of = xn_d; xb.k_of = xk_d;
         xb.a_off = xa_d; xb.b_off = xb_d; xb.c_off = xc_d;
-        gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb);
+        gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb, false, 32, 32);
         GemmSeg ws{};
         ws.A = op_contig(T.Ui, nb, 0, 0);
         ws.B = op_contigT(h->Xb, maxa, 0, 0);
@@ -695,7 +731,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
         wb.count = cnt;
         wb.m_of = wm_d; wb.n_of = wn_d; wb.k_of = wk_d;
         wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
-        gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb);
+        gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32);
       }
     }
     prof_add(h, TLR_K_LOWRANK, e_w, wflops, wbytes);
@@ -836,7 +872,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     if (T > 0) {
       for (int t = 0; t < T; ++t) {
         const int i = j + 1 + t;
-        pred[t] = (j > 0) ? h->rk[(size_t)(i - 1) * nt + (j - 1)] : 48;
+        pred[t] = (j > 0) ? std::max(h->rk[(size_t)(i - 1) * nt + (j - 1)], h->rk[(size_t)i * nt + (j - 1)]) : 48;
       }
       compress_column(h, h->col + nbj, h->n, j + 1, T, j, nbj, h->U, h->Vtmp, h->rk, pred, h->maxrank);
       lowrank_trsm(h, j, j + 1, T, h->Vtmp, h->V, h->rk);
@@ -878,7 +914,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         ps.K = nbj;
         GemmBatch pb{};
         pb.count = T; pb.m_of = m_d; pb.n_of = n_d; pb.k_of = k_d; pb.a_off = a_d; pb.b_off = b_d; pb.c_off = c_d;
-        gemm(h, nbj, kmax, 1, &ps, h->Vtmp, nb, epi_linear(1.0, 0.0), &pb);
+        gemm(h, nbj, kmax, 1, &ps, h->Vtmp, nb, epi_linear(1.0, 0.0), &pb, false, 128, 32);
         int* m2_h = im_take(h, T, &m_d);
         int* n2_h = im_take(h, T, &n_d);
         int* k2_h = im_take(h, T, &k_d);
@@ -905,7 +941,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       }
       for (int t = 0; t < T; ++t) {
         const int i = j + 1 + t;
-        pred[t] = (j > 0) ? h->rkd[(size_t)(i - 1) * nt + (j - 1)] : 48;
+        pred[t] = (j > 0) ? std::max(h->rkd[(size_t)(i - 1) * nt + (j - 1)], h->rkd[(size_t)i * nt + (j - 1)]) : 48;
       }
       compress_column(h, h->cold + nbj, h->n, j + 1, T, j, nbj, h->Ud, h->Vtmp, h->rkd, pred, h->maxrank_t);
       lowrank_trsm(h, j, j + 1, T, h->Vtmp, h->Vd, h->rkd);

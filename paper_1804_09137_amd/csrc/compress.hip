@@ -12,15 +12,15 @@
 //   5. assemble     U = Q1 Pi2 R2[:k, :]^T, V = Q2[:, :k]
 // so ||C - U V^T||_2 <= ||(I - Q1 Q1^T) C||_2 + ||R2[k:, k:]||_F.
 //
-// qrcp_kernel is one 1024-thread workgroup per matrix; the matrix stays in
-// global memory (L2-resident), each of the 16 waves owns a set of columns and
-// keeps its column slice in registers during a Householder application.
+// qrcp_kernel is one 512-thread workgroup per matrix; the matrix stays in
+// global memory (L2-resident), each of the 8 waves owns a set of columns and
+// keeps two column slices in registers during a Householder application.
 #include "kernels.h"
 #include "compress.h"
 
 namespace tlrk {
 
-constexpr int kQrThreads = 1024;
+constexpr int kQrThreads = 512;
 constexpr int kQrWaves = kQrThreads / 64;
 
 __device__ inline double wave_sum(double v) {
@@ -28,15 +28,23 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Column-pivoted Householder QR, one workgroup per matrix.  Columns are never
+// moved: piv[t] records the physical column chosen at step t and step_of[]
+// its inverse.  Each step: (1) the pivot column's reflector (block reduction),
+// (2) every live column is reflected and its norm over rows > t recomputed
+// exactly; the per-wave partial sums and maxima of those norms feed the next
+// step's stopping test and pivot choice.  Three barriers per step.
 __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __restrict__ tasks) {
   const QrcpTask tk = tasks[blockIdx.x];
   __shared__ double nrm[kQrMaxCols];
   __shared__ double tau[kQrMaxCols];
-  __shared__ int perm[kQrMaxCols];
+  __shared__ int piv[kQrMaxCols];
+  __shared__ int step_of[kQrMaxCols];
   __shared__ double vs[kQrMaxRows];
   __shared__ double red[kQrWaves];
-  __shared__ int sh_piv, sh_stop;
-  __shared__ double sh_beta, sh_tau, sh_scale;
+  __shared__ double wsum[kQrWaves], wmax[kQrWaves];
+  __shared__ int widx[kQrWaves];
+  __shared__ double sh_alpha;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m = tk.m, q = tk.q;
@@ -49,123 +57,126 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
     }
     return;
   }
+  constexpr int RPL = kQrMaxRows / 64;   // rows per lane
 
-  for (int c = wv; c < q; c += kQrWaves) {
-    double s = 0.0;
-    for (int r = lane; r < m; r += 64) {
-      const double v = Y[c * ld + r];
-      s += v * v;
+  // initial norms and per-wave partials
+  {
+    double ls = 0.0, lm = -1.0;
+    int li = 0x7fffffff;
+    for (int c = wv; c < q; c += kQrWaves) {
+      double sacc = 0.0;
+      for (int r = lane; r < m; r += 64) {
+        const double v = Y[(int64_t)c * ld + r];
+        sacc += v * v;
+      }
+      sacc = wave_sum(sacc);
+      if (lane == 0) nrm[c] = sacc;
+      ls += sacc;
+      if (sacc > lm || (sacc == lm && c < li)) { lm = sacc; li = c; }
     }
-    s = wave_sum(s);
-    if (lane == 0) nrm[c] = s;
+    if (lane == 0) { wsum[wv] = ls; wmax[wv] = lm; widx[wv] = li; }
+    for (int c = tid; c < q; c += kQrThreads) step_of[c] = 0x7fffffff;
   }
-  for (int c = tid; c < q; c += kQrThreads) perm[c] = c;
   __syncthreads();
 
   const int tmax = m < q ? m : q;
   const double tol2 = tk.tol * tk.tol;
   int t = 0;
   for (; t < tmax; ++t) {
-    if (wv == 0) {
-      double s = 0.0, best = -1.0;
-      int bi = t;
-      for (int c = t + lane; c < q; c += 64) {
-        const double v = nrm[c];
-        s += v;
-        if (v > best) { best = v; bi = c; }
-      }
-      s = wave_sum(s);
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) {
-        sh_stop = (s <= tol2 || t >= tk.max_rank) ? 1 : 0;
-        sh_piv = bi;
-      }
-    }
-    __syncthreads();
-    if (sh_stop) break;
-    const int p = sh_piv;
-    if (p != t) {
-      for (int r = tid; r < m; r += kQrThreads) {
-        const double a = Y[(int64_t)t * ld + r];
-        Y[(int64_t)t * ld + r] = Y[(int64_t)p * ld + r];
-        Y[(int64_t)p * ld + r] = a;
-      }
-      if (tid == 0) {
-        const double a = nrm[t]; nrm[t] = nrm[p]; nrm[p] = a;
-        const int b = perm[t]; perm[t] = perm[p]; perm[p] = b;
-      }
-    }
-    __syncthreads();
-    // Householder vector of column t (rows t..m-1)
-    {
-      double s = 0.0;
-      for (int r = t + 1 + tid; r < m; r += kQrThreads) {
-        const double v = Y[(int64_t)t * ld + r];
-        s += v * v;
-      }
-      s = wave_sum(s);
-      if (lane == 0) red[wv] = s;
-      __syncthreads();
-      if (tid == 0) {
-        double sig = 0.0;
-        for (int w = 0; w < kQrWaves; ++w) sig += red[w];
-        const double alpha = Y[(int64_t)t * ld + t];
-        if (sig == 0.0) {
-          sh_tau = 0.0; sh_beta = alpha; sh_scale = 0.0;
-        } else {
-          const double nx = sqrt(alpha * alpha + sig);
-          const double beta = alpha >= 0.0 ? -nx : nx;
-          sh_tau = (beta - alpha) / beta;
-          sh_scale = 1.0 / (alpha - beta);
-          sh_beta = beta;
-        }
-        tau[t] = sh_tau;
-      }
-      __syncthreads();
-      const double sc = sh_scale;
-      for (int r = t + tid; r < m; r += kQrThreads) {
-        double v;
-        if (r == t) {
-          v = 1.0;
-          Y[(int64_t)t * ld + t] = sh_beta;
-        } else {
-          v = Y[(int64_t)t * ld + r] * sc;
-          Y[(int64_t)t * ld + r] = v;
-        }
-        vs[r] = v;
-      }
-      __syncthreads();
-    }
-    // apply H_t to columns t+1..q-1 and refresh their norms over rows > t
-    const double ta = sh_tau;
-    for (int c = t + 1 + wv; c < q; c += kQrWaves) {
-      double* col = Y + (int64_t)c * ld;
-      double yv[kQrMaxRows / 64];
-      double w = 0.0;
+    // every thread reduces the 16 wave partials identically
+    double total = 0.0, best = -1.0;
+    int p = 0x7fffffff;
 #pragma unroll
-      for (int i = 0; i < kQrMaxRows / 64; ++i) {
-        const int r = t + lane + 64 * i;
-        yv[i] = (r < m) ? col[r] : 0.0;
-        if (r < m) w += vs[r] * yv[i];
-      }
-      w = wave_sum(w) * ta;
-      double s = 0.0;
+    for (int w = 0; w < kQrWaves; ++w) {
+      total += wsum[w];
+      if (wmax[w] > best || (wmax[w] == best && widx[w] < p)) { best = wmax[w]; p = widx[w]; }
+    }
+    if (total <= tol2 || t >= tk.max_rank || p >= q) break;
+    // reflector of column p, rows t..m-1 (two rows per thread: m <= 1024)
+    double* colp = Y + (int64_t)p * ld;
+    const int r = t + tid;
+    const int r2 = r + kQrThreads;
+    double x = 0.0, x2 = 0.0;
+    if (r < m) x = colp[r];
+    if (r2 < m) x2 = colp[r2];
+    if (r == t) sh_alpha = x;
+    double sp = (r > t && r < m) ? x * x : 0.0;
+    sp += (r2 < m) ? x2 * x2 : 0.0;
+    sp = wave_sum(sp);
+    if (lane == 0) red[wv] = sp;
+    if (tid == 0) { piv[t] = p; step_of[p] = t; }
+    __syncthreads();
+    double sig = 0.0;
 #pragma unroll
-      for (int i = 0; i < kQrMaxRows / 64; ++i) {
-        const int r = t + lane + 64 * i;
-        if (r < m) {
-          const double nv = yv[i] - w * vs[r];
-          col[r] = nv;
-          if (r > t) s += nv * nv;
+    for (int w = 0; w < kQrWaves; ++w) sig += red[w];
+    const double alpha = sh_alpha;
+    double ta, beta, sc;
+    if (sig == 0.0) {
+      ta = 0.0; beta = alpha; sc = 0.0;
+    } else {
+      const double nx = sqrt(alpha * alpha + sig);
+      beta = alpha >= 0.0 ? -nx : nx;
+      ta = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    if (r < m) {
+      if (r == t) { vs[r] = 1.0; colp[r] = beta; }
+      else { const double v = x * sc; vs[r] = v; colp[r] = v; }
+    }
+    if (r2 < m) { const double v = x2 * sc; vs[r2] = v; colp[r2] = v; }
+    if (tid == 0) tau[t] = ta;
+    __syncthreads();
+    // reflect the live columns, two per wave at a time
+    double ls = 0.0, lm = -1.0;
+    int li = 0x7fffffff;
+    for (int c0 = wv; c0 < q; c0 += 2 * kQrWaves) {
+      const int c1 = c0 + kQrWaves;
+      const bool a0 = (step_of[c0] > t) && (c0 != p);
+      const bool a1 = (c1 < q) && (step_of[c1] > t) && (c1 != p);
+      if (!a0 && !a1) continue;
+      double* y0 = Y + (int64_t)c0 * ld;
+      double* y1 = Y + (int64_t)(a1 ? c1 : c0) * ld;
+      double v0[RPL], v1[RPL];
+      double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int rr = t + lane + 64 * i;
+        const bool in = rr < m;
+        v0[i] = (in && a0) ? y0[rr] : 0.0;
+        v1[i] = (in && a1) ? y1[rr] : 0.0;
+        const double vv = in ? vs[rr] : 0.0;
+        w0 += vv * v0[i];
+        w1 += vv * v1[i];
+      }
+      w0 = wave_sum(w0) * ta;
+      w1 = wave_sum(w1) * ta;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int rr = t + lane + 64 * i;
+        if (rr < m) {
+          const double vv = vs[rr];
+          const double n0 = v0[i] - w0 * vv;
+          const double n1 = v1[i] - w1 * vv;
+          if (a0) y0[rr] = n0;
+          if (a1) y1[rr] = n1;
+          if (rr > t) { s0 += n0 * n0; s1 += n1 * n1; }
         }
       }
-      s = wave_sum(s);
-      if (lane == 0) nrm[c] = s;
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (a0) {
+        if (lane == 0) nrm[c0] = s0;
+        ls += s0;
+        if (s0 > lm || (s0 == lm && c0 < li)) { lm = s0; li = c0; }
+      }
+      if (a1) {
+        if (lane == 0) nrm[c1] = s1;
+        ls += s1;
+        if (s1 > lm || (s1 == lm && c1 < li)) { lm = s1; li = c1; }
+      }
     }
+    if (lane == 0) { wsum[wv] = ls; wmax[wv] = lm; widx[wv] = li; }
     __syncthreads();
   }
   const int rank = t;
@@ -174,41 +185,56 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
     if (tk.flag) *tk.flag = (q - rank < tk.min_tail) ? 1 : 0;
   }
 
-  // Z[perm[c], r] = R[r, c] for r < rank, c < q
+  // Z[c, r] = R[r, step_of[c]] for r < rank: column c holds its R entries in
+  // rows <= step_of[c] (all rows < rank if c was never chosen)
   if (tk.Z) {
     for (int e = tid; e < q * rank; e += kQrThreads) {
-      const int c = e % q, r = e / q;
-      tk.Z[(int64_t)r * tk.ldz + perm[c]] = (c >= r) ? Y[(int64_t)c * ld + r] : 0.0;
+      const int c = e % q, rr = e / q;
+      tk.Z[(int64_t)rr * tk.ldz + c] = (step_of[c] >= rr) ? Y[(int64_t)c * ld + rr] : 0.0;
     }
   }
   if (!tk.Q) return;
-  // explicit Q = H_0 ... H_{rank-1} [I; 0]  (m x rank)
+  // explicit Q = H_0 ... H_{rank-1} [I; 0]  (m x rank); reflector s lives in
+  // column piv[s], rows > s
   double* Q = tk.Q;
   const int64_t ldq = tk.ldq;
   for (int e = tid; e < m * rank; e += kQrThreads) {
-    const int r = e % m, c = e / m;
-    Q[(int64_t)c * ldq + r] = (r == c) ? 1.0 : 0.0;
+    const int rr = e % m, c = e / m;
+    Q[(int64_t)c * ldq + rr] = (rr == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int s = rank - 1; s >= 0; --s) {
-    for (int r = s + tid; r < m; r += kQrThreads) vs[r] = (r == s) ? 1.0 : Y[(int64_t)s * ld + r];
+  for (int st = rank - 1; st >= 0; --st) {
+    const double* vcol = Y + (int64_t)piv[st] * ld;
+    for (int rr = st + tid; rr < m; rr += kQrThreads) vs[rr] = (rr == st) ? 1.0 : vcol[rr];
     __syncthreads();
-    const double ta = tau[s];
-    for (int c = s + wv; c < rank; c += kQrWaves) {
-      double* col = Q + (int64_t)c * ldq;
-      double yv[kQrMaxRows / 64];
-      double w = 0.0;
+    const double ta = tau[st];
+    for (int c0 = st + wv; c0 < rank; c0 += 2 * kQrWaves) {
+      const int c1 = c0 + kQrWaves;
+      const bool a1 = c1 < rank;
+      double* y0 = Q + (int64_t)c0 * ldq;
+      double* y1 = Q + (int64_t)(a1 ? c1 : c0) * ldq;
+      double v0[RPL], v1[RPL];
+      double w0 = 0.0, w1 = 0.0;
 #pragma unroll
-      for (int i = 0; i < kQrMaxRows / 64; ++i) {
-        const int r = s + lane + 64 * i;
-        yv[i] = (r < m) ? col[r] : 0.0;
-        if (r < m) w += vs[r] * yv[i];
+      for (int i = 0; i < RPL; ++i) {
+        const int rr = st + lane + 64 * i;
+        const bool in = rr < m;
+        v0[i] = in ? y0[rr] : 0.0;
+        v1[i] = (in && a1) ? y1[rr] : 0.0;
+        const double vv = in ? vs[rr] : 0.0;
+        w0 += vv * v0[i];
+        w1 += vv * v1[i];
       }
-      w = wave_sum(w) * ta;
+      w0 = wave_sum(w0) * ta;
+      w1 = wave_sum(w1) * ta;
 #pragma unroll
-      for (int i = 0; i < kQrMaxRows / 64; ++i) {
-        const int r = s + lane + 64 * i;
-        if (r < m) col[r] = yv[i] - w * vs[r];
+      for (int i = 0; i < RPL; ++i) {
+        const int rr = st + lane + 64 * i;
+        if (rr < m) {
+          const double vv = vs[rr];
+          y0[rr] = v0[i] - w0 * vv;
+          if (a1) y1[rr] = v1[i] - w1 * vv;
+        }
       }
     }
     __syncthreads();

@@ -262,7 +262,8 @@ static hipError_t run(GemmArgs& g, int zdim, hipStream_t s) {
 }
 
 hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
-                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s) {
+                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
+                       int tile_m, int tile_n) {
   if (M < 0 || N < 0 || nseg < 1 || nseg > 2 || splitk < 1) return hipErrorInvalidValue;
   if (M == 0 || N == 0) return hipSuccess;
   GemmArgs g{};
@@ -290,8 +291,8 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
   g.work = work;
   const int zdim = splitk > 1 ? splitk : g.batch.count;
   hipError_t e;
-  const int bm = (M <= 32) ? 32 : (M <= 64) ? 64 : 128;
-  const int bn = (N <= 32) ? 32 : (N <= 64) ? 64 : 128;
+  const int bm = tile_m ? tile_m : (M <= 32) ? 32 : (M <= 64) ? 64 : 128;
+  const int bn = tile_n ? tile_n : (N <= 32) ? 32 : (N <= 64) ? 64 : 128;
   switch (bm * 1000 + bn) {
     case 32032: e = run<32, 32, 2, 2>(g, zdim, s); break;
     case 32064: e = run<32, 64, 2, 2>(g, zdim, s); break;

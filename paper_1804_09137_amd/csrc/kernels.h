@@ -49,7 +49,11 @@ struct GemmBatch {
 
 // Returns hipErrorInvalidValue on bad shapes.  work (may be null) must hold
 // splitk * M * N doubles when splitk > 1 (batch count must be 1 then).
+// tile_m / tile_n (32, 64 or 128; 0 = by M and N) choose the workgroup tile:
+// batched calls whose per-batch sizes are far below the launch maxima use
+// small tiles so that the workgroups of small problems stay short.
 hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
-                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s);
+                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
+                       int tile_m = 0, int tile_n = 0);
 
 }  // namespace tlrk
