@@ -57,23 +57,32 @@ typedef enum {
   TLR_PREC_FP32_UPDATES = 1   /* TLR only: low-rank update products in FP32, everything else FP64 */
 } tlr_prec;
 
+/* tlr_opts.flags */
+#define TLR_FLAG_STRICT_RANK 1  /* a tile needing rank > maxrank is an error (TLR_ERANK) instead of
+                                   being kept dense */
+
 typedef struct {
   int64_t n;          /* number of locations (>= 1) */
   int32_t nb;         /* tile size (multiple of 16, 32 <= nb <= 1024) */
-  int32_t maxrank;    /* TLR: largest rank a tile may take; 0 selects nb / 2 */
+  int32_t maxrank;    /* TLR: largest rank of a low-rank tile (<= 416); 0 selects nb / 4.  A tile
+                         that needs more is kept dense (U = tile, V = L_jj^{-1}) unless
+                         TLR_FLAG_STRICT_RANK is set */
   double tol;         /* TLR: absolute per-tile accuracy threshold (spectral norm), > 0 */
   int32_t mode;       /* tlr_mode */
   int32_t prec;       /* tlr_prec */
   int32_t want_grad;  /* non-zero: also allocate what tlr_loglik_grad needs */
   int32_t seed;       /* seed of the Gaussian sketch matrix used by TLR compression */
+  int32_t flags;      /* TLR_FLAG_* */
+  int32_t reserved;   /* must be 0 */
 } tlr_opts;
 
 typedef struct {
   int64_t n;
   int32_t nb, nt, maxrank, mode;
   int64_t device_bytes;       /* device memory held by the handle */
-  int64_t rank_sum;           /* sum of the ranks of the strictly-lower tiles of the last factor */
-  int32_t rank_max;
+  int64_t rank_sum;           /* sum of the ranks of the strictly-lower low-rank tiles of the last factor */
+  int32_t rank_max;           /* largest rank of a low-rank tile */
+  int32_t dense_tiles;        /* strictly-lower tiles kept dense */
   int32_t bad_tile_i, bad_tile_j; /* TLR_ERANK: offending tile */
   double t_factor_ms;         /* device time of the last factorisation (hipEvents) */
   double t_solve_ms;          /* device time of the last log-det + solves */
@@ -155,7 +164,8 @@ tlr_status tlr_profile(tlr_handle_t h, int32_t enable);
 tlr_status tlr_get_kstats(tlr_handle_t h, tlr_kstat* out);
 
 /* Rank table of the last tlr_compress or tlr_potrf: host_ranks[i * nt + j]
- * for i > j (other entries 0).  nt = ceil(n / nb). */
+ * for i > j (other entries 0); a tile kept dense reports its width.
+ * nt = ceil(n / nb). */
 tlr_status tlr_get_ranks(tlr_handle_t h, int32_t* host_ranks);
 
 /* Sizes, memory, rank statistics and timings of the handle. */

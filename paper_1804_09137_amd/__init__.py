@@ -18,7 +18,7 @@ __all__ = ["TLRError", "NotSPDError", "RankError", "Handle", "morton_order", "TL
 class TLRError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         detail = ""
-        if status == _lib.TLR_EHIP:
+        if status in (_lib.TLR_EHIP, _lib.TLR_ENOMEM):
             detail = " [" + _lib.load().tlr_last_error().decode(errors="replace") + "]"
         super().__init__(f"{what}: {_lib.status_name(status)}{detail}")
         self.status = status
@@ -54,7 +54,8 @@ class Handle:
     """One problem size n on the current GPU.  mode: 'tlr' or 'dense'."""
 
     def __init__(self, n: int, nb: int, tol: float = 1e-9, maxrank: int = 0, mode: str = "tlr",
-                 prec: str = "fp64", want_grad: bool = False, seed: int = 0, stream=None):
+                 prec: str = "fp64", want_grad: bool = False, seed: int = 0, strict_rank: bool = False,
+                 stream=None):
         import torch
         self._lib = _lib.load()
         o = _lib.Opts()
@@ -63,6 +64,7 @@ class Handle:
         o.prec = {"fp64": _lib.PREC_FP64, "fp32_updates": _lib.PREC_FP32_UPDATES}[prec]
         o.want_grad = 1 if want_grad else 0
         o.seed = int(seed)
+        o.flags = _lib.FLAG_STRICT_RANK if strict_rank else 0
         self.n, self.nb, self.mode = int(n), int(nb), mode
         self.nt = (self.n + self.nb - 1) // self.nb
         if stream is None:

@@ -25,6 +25,7 @@ MODE_TLR = 0
 MODE_DENSE = 1
 PREC_FP64 = 0
 PREC_FP32_UPDATES = 1
+FLAG_STRICT_RANK = 1
 
 _NAMES = {0: "TLR_OK", 1: "TLR_ENOTSPD", -1: "TLR_EINVAL", -2: "TLR_ENOMEM", -3: "TLR_EHIP",
           -4: "TLR_ERANK", -5: "TLR_ENOTIMPL", -6: "TLR_ESTATE"}
@@ -33,13 +34,15 @@ _NAMES = {0: "TLR_OK", 1: "TLR_ENOTSPD", -1: "TLR_EINVAL", -2: "TLR_ENOMEM", -3:
 class Opts(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nb", ctypes.c_int32), ("maxrank", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("want_grad", ctypes.c_int32), ("seed", ctypes.c_int32)]
+                ("want_grad", ctypes.c_int32), ("seed", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nb", ctypes.c_int32), ("nt", ctypes.c_int32),
                 ("maxrank", ctypes.c_int32), ("mode", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("rank_sum", ctypes.c_int64), ("rank_max", ctypes.c_int32), ("bad_tile_i", ctypes.c_int32),
+                ("rank_sum", ctypes.c_int64), ("rank_max", ctypes.c_int32), ("dense_tiles", ctypes.c_int32),
+                ("bad_tile_i", ctypes.c_int32),
                 ("bad_tile_j", ctypes.c_int32), ("t_factor_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_grad_ms", ctypes.c_double)]
 

@@ -43,9 +43,11 @@ struct tlr_handle_s {
   int device = 0;
   int64_t n = 0;
   int nb = 0, nt = 0, maxrank = 0, smax = 0;
-  int maxrank_t = 0;     // tangent tiles (gradient) may take up to 1.5 maxrank
-  bool dense = false, grad = false;
-  int64_t slot = 0;      // doubles per low-rank slot (nb * max(maxrank, maxrank_t))
+  bool dense = false, grad = false, strict = false;
+  int64_t slot = 0;      // doubles per low-rank slot (nb * maxrank)
+  int64_t vslot = 0;     // doubles per V~ staging block (nb * (maxrank + 1)): the
+                         // truncating QR may produce maxrank + 1 columns before
+                         // the tile is turned dense
   int64_t ntiles = 0;    // strictly-lower tiles
 
   const double* x = nullptr;
@@ -66,14 +68,24 @@ struct tlr_handle_s {
   double* Ldp = nullptr;  // DENSE: tangent
   double* D = nullptr;    // TLR: diagonal tiles nt x (nb x nb)
   double* Dd = nullptr;   // TLR tangent diagonal tiles
-  double* Dinv = nullptr; // both: inverses of the diagonal tiles
-  double* U = nullptr;
-  double* V = nullptr;
-  double* Ud = nullptr;
-  double* Vd = nullptr;
-  int* rk_d = nullptr;    // device rank tables (nt*nt), primal and tangent
-  int* rkd_d = nullptr;
-  std::vector<int> rk, rkd;
+  double* Dinv = nullptr; // both: inverses of the diagonal tiles (inside the arena for TLR)
+  // TLR off-diagonal tiles: L_ij = U V^T with U, V (ld nb) anywhere in one
+  // arena; family 0 is the factor, family 1 its tangent (gradient).  A
+  // low-rank tile uses its fixed slots; a tile whose rank would exceed
+  // maxrank is kept dense: U = the tile itself, V = Dinv_j (or the identity
+  // for the compressed Sigma of tlr_compress), rank = tile width.
+  double* arena = nullptr;
+  int64_t dinv_off = 0, ident_off = 0, dense_off = 0;
+  int64_t dense_cap = 0, dense_used = 0;
+  struct Family {
+    int64_t u_base = 0, v_base = 0;      // arena offsets of the slot regions
+    std::vector<int> rk;                 // nt*nt (i * nt + j)
+    std::vector<int64_t> uoff, voff;     // arena offsets of U_ij, V_ij
+    std::vector<char> isdense;
+    int* rk_d = nullptr;
+    int64_t* uoff_d = nullptr;
+    int64_t* voff_d = nullptr;
+  } fam[2];
 
   // scratch
   double* col = nullptr;   // n x nb, ld n
@@ -82,7 +94,8 @@ struct tlr_handle_s {
   double* Ybuf = nullptr;  // n x smax, ld n
   double* Q1 = nullptr;    // n x smax, ld n
   double* Bt = nullptr;    // nt x (nb x smax)
-  double* Vtmp = nullptr;  // nt x slot
+  double* Vtmp = nullptr;  // nt x vslot
+  double* Ptmp = nullptr;  // nt x nb x nb (gradient: dL_jj V_ij products)
   double* Zb = nullptr;    // nt x (smax x maxrank)
   double* Wb = nullptr;
   int64_t w_cap = 0;
@@ -138,6 +151,12 @@ thread_local char g_last_error[256] = "";
   throw Fail{TLR_EHIP};
 }
 
+[[noreturn]] void nomem(const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "capacity exceeded: %s at api.hip:%d", what, line);
+  throw Fail{TLR_ENOMEM};
+}
+#define NOMEM(what) nomem(what, __LINE__)
+
 #define HIPCHK(x)                                    \
   do {                                               \
     hipError_t e_ = (x);                             \
@@ -175,17 +194,19 @@ inline int tile_rows(const tlr_handle_s* h, int i) {
 inline int64_t slot_of(const tlr_handle_s* h, int i, int j) {  // i > j
   return (int64_t)j * h->nt - (int64_t)j * (j + 1) / 2 + (i - j - 1);
 }
+inline double* dinv_tile(tlr_handle_s* h, int j) { return h->Dinv + (int64_t)j * h->nb * h->nb; }
+inline double* diag_tile(tlr_handle_s* h, int j) { return h->D + (int64_t)j * h->nb * h->nb; }
 
 // ---- metadata staging (pinned host -> device, one column at a time) ----
 int* im_take(tlr_handle_s* h, int64_t cnt, int** dptr) {
-  if (h->im_use + cnt > h->im_cap) throw Fail{TLR_ENOMEM};
+  if (h->im_use + cnt > h->im_cap) NOMEM("int metadata");
   int* hp = h->im_h + h->im_use;
   *dptr = h->im_d + h->im_use;
   h->im_use += cnt;
   return hp;
 }
 int64_t* lm_take(tlr_handle_s* h, int64_t cnt, int64_t** dptr) {
-  if (h->lm_use + cnt > h->lm_cap) throw Fail{TLR_ENOMEM};
+  if (h->lm_use + cnt > h->lm_cap) NOMEM("offset metadata");
   int64_t* hp = h->lm_h + h->lm_use;
   *dptr = h->lm_d + h->lm_use;
   h->lm_use += cnt;
@@ -206,6 +227,16 @@ void prof_harvest(tlr_handle_s* h);
 void sync(tlr_handle_s* h) {
   HIPCHK(hipStreamSynchronize(h->s));
   prof_harvest(h);
+}
+
+// Make room for a group of metadata takes: when the staging buffers would
+// overflow, wait for the stream (every queued copy has then been consumed)
+// and recycle them.  Called before a group, never inside one.
+void meta_reserve(tlr_handle_s* h, int64_t ints, int64_t longs) {
+  if (h->im_use + ints <= h->im_cap && h->lm_use + longs <= h->lm_cap) return;
+  sync(h);
+  meta_reset(h);
+  if (ints > h->im_cap || longs > h->lm_cap) NOMEM("metadata of one launch group");
 }
 
 // ---- per-kernel-class timing: an event pair around each launch group ----
@@ -310,48 +341,78 @@ void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, 
 }
 
 // ---------------------------------------------------------------------------
-// Compression of the tiles below the diagonal of one column held densely in
-// src (ld), rows [row0, row0 + sum m_i); tile t (0 .. T-1) is global tile
-// i = i_first + t.  Results: U slots of (i, col), V~ in vt (per tile slot,
-// ld nb), ranks into rk_out[i * nt + col].  pred holds predicted ranks.
+// Tile bookkeeping of a TLR family
 // ---------------------------------------------------------------------------
+using Family = tlr_handle_s::Family;
+
+inline size_t tid_of(const tlr_handle_s* h, int i, int j) { return (size_t)i * h->nt + j; }
+
+void family_reset(tlr_handle_s* h, Family& F) {
+  std::fill(F.rk.begin(), F.rk.end(), 0);
+  std::fill(F.isdense.begin(), F.isdense.end(), 0);
+  for (int i = 0; i < h->nt; ++i)
+    for (int j = 0; j < i; ++j) {
+      F.uoff[tid_of(h, i, j)] = F.u_base + slot_of(h, i, j) * h->slot;
+      F.voff[tid_of(h, i, j)] = F.v_base + slot_of(h, i, j) * h->slot;
+    }
+}
+
+// device copies of the rank and offset tables (for the solves)
+void family_upload(tlr_handle_s* h, Family& F) {
+  const size_t nn = (size_t)h->nt * h->nt;
+  HIPCHK(hipMemcpyAsync(F.rk_d, F.rk.data(), nn * sizeof(int), hipMemcpyHostToDevice, h->s));
+  HIPCHK(hipMemcpyAsync(F.uoff_d, F.uoff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
+  HIPCHK(hipMemcpyAsync(F.voff_d, F.voff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
+}
+
+int64_t take_dense_block(tlr_handle_s* h) {
+  if (h->dense_used >= h->dense_cap) NOMEM("dense tile pool");
+  return h->dense_off + (h->dense_used++) * (int64_t)h->nb * h->nb;
+}
+
 void throw_if_not_spd(tlr_handle_s* h) {
   // *h_info was copied back before the last synchronisation
   if (*h->h_info != ~0ull) throw Fail{TLR_ENOTSPD};
 }
 
-void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first, int T, int col,
-                     int ncols, double* Uslots, double* vt, std::vector<int>& rk_out, const std::vector<int>& pred,
-                     int maxrank) {
+// ---------------------------------------------------------------------------
+// Compression of the T tiles below the diagonal of column `col`, held densely
+// in src (ld); tile t is global tile i = i_first + t (rows t*nb .. of src).
+// Low-rank tiles: U written to F's slot, V~ (before the TRSM) to vt + t*slot,
+// F.rk = rank.  Tiles whose rank would exceed maxrank are copied to a dense
+// block: F.uoff = block, F.voff = dense_voff, F.rk = ncols (unless strict).
+// pred: predicted ranks (sketch widths, and the early dense decision).
+// ---------------------------------------------------------------------------
+void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first, int T, int col, int ncols,
+                     Family& F, double* vt, const std::vector<int>& pred, int64_t dense_voff) {
   if (T <= 0) return;
   const int nb = h->nb;
+  const int maxrank = h->maxrank;
   const size_t e_c = prof_mark(h);
   double cflops = 0.0;
   const double tol = h->o.tol;
   const double tol_range = 0.05 * tol;  // range finder residual target (Frobenius of the samples)
   const double tol_trunc = 0.9 * tol;
-  // per-tile sketch widths from the predicted ranks; a tile whose samples are
-  // not exhausted (fewer than 8 unused columns left) is sketched again, alone,
-  // with twice the width
-  std::vector<int> sz(T), t1(T), todo;
+  std::vector<char> dense(T, 0);
+  std::vector<int> sz(T), t1(T, 0), todo;
   for (int t = 0; t < T; ++t) {
+    if (!h->strict && pred[t] > maxrank) {
+      dense[t] = 1;
+      continue;
+    }
     sz[t] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred[t] + 16)));
     todo.push_back(t);
   }
+  // 1-2. sketch Y = C Omega and orthonormal range basis Q1 by pivoted QR; a
+  // tile whose samples are not exhausted (fewer than 8 unused columns) is
+  // sketched again, alone, twice as wide
   bool first = true;
   while (!todo.empty()) {
     int swide = 0;
     for (int t : todo) swide = std::max(swide, sz[t]);
     const int cnt = (int)todo.size();
-    if (first) {  // 1. sketch Y = C Omega for all tiles at once
-      int64_t rows = 0;
-      for (int t = 0; t < T; ++t) rows += tile_rows(h, i_first + t);
-      GemmSeg sg{};
-      sg.A = op_contig(src, ld, 0, 0);
-      sg.B = op_contigT(h->omega, nb, 0, 0);
-      sg.K = ncols;
-      gemm(h, rows, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0));
-    } else {      // re-sketch only the tiles in todo
+    meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
+    {
       int *m_d, *n_d;
       int* m_h = im_take(h, cnt, &m_d);
       int* n_h = im_take(h, cnt, &n_d);
@@ -373,11 +434,16 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       sg.A = op_contig(src, ld, 0, 0);
       sg.B = op_contigT(h->omega, nb, 0, 0);
       sg.K = ncols;
-      GemmBatch bt{};
-      bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
-      gemm(h, maxm, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0), &bt);
+      if (first && cnt == T) {  // every tile: one plain GEMM over the stacked rows
+        int64_t rows = 0;
+        for (int t = 0; t < T; ++t) rows += tile_rows(h, i_first + t);
+        gemm(h, rows, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0));
+      } else {
+        GemmBatch bt{};
+        bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
+        gemm(h, maxm, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0), &bt);
+      }
     }
-    // 2. pivoted QR of each tile's samples: orthonormal range basis Q1
     for (int q = 0; q < cnt; ++q) {
       const int t = todo[q];
       QrcpTask& tk = h->tk_h[q];
@@ -409,188 +475,232 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       cflops += 2.0 * m * sz[t] * ncols + 4.0 * m * sz[t] * t1[t] + 2.0 * m * t1[t] * t1[t];
       if (h->qr_h[h->nt + t]) {
         if (sz[t] >= h->smax) {
-          h->bad_i = i_first + t;
-          h->bad_j = col;
-          throw Fail{TLR_ERANK};
+          if (h->strict) {
+            h->bad_i = i_first + t;
+            h->bad_j = col;
+            throw Fail{TLR_ERANK};
+          }
+          dense[t] = 1;
+          continue;
         }
         sz[t] = std::min(h->smax, 2 * sz[t]);
         next.push_back(t);
+      } else if (!h->strict && t1[t] > maxrank + maxrank / 2 + 16) {
+        dense[t] = 1;  // the truncation cannot get below maxrank
       }
     }
     todo.swap(next);
     first = false;
   }
-  // 3. project: Bt_t = C_t^T Q1_t (ncols x t1)
-  int *m_d, *n_d, *k_d;
-  int* m_h = im_take(h, T, &m_d);
-  int* n_h = im_take(h, T, &n_d);
-  int* k_h = im_take(h, T, &k_d);
-  int64_t *a_d, *b_d, *c_d;
-  int64_t* a_h = lm_take(h, T, &a_d);
-  int64_t* b_h = lm_take(h, T, &b_d);
-  int64_t* c_h = lm_take(h, T, &c_d);
-  int maxn = 1;
-  for (int t = 0; t < T; ++t) {
-    m_h[t] = ncols;
-    n_h[t] = t1[t];
-    k_h[t] = tile_rows(h, i_first + t);
-    a_h[t] = (int64_t)t * nb;                       // row offset of tile t in src (contigT frame)
-    b_h[t] = (int64_t)t * nb;                       // Q1 rows
-    c_h[t] = (int64_t)t * nb * h->smax;             // Bt block
-    maxn = std::max(maxn, t1[t]);
-  }
-  im_push(h, m_h, m_d, 3 * T);
-  lm_push(h, a_h, a_d, 3 * T);
-  {
-    GemmSeg sg{};
-    sg.A = op_contigT(src, ld, 0, 0);
-    sg.B = op_contigT(h->Q1, h->n, 0, 0);
-    sg.K = nb;
-    GemmBatch bt{};
-    bt.count = T;
-    bt.m_of = m_d;
-    bt.n_of = n_d;
-    bt.k_of = k_d;
-    bt.a_off = a_d;
-    bt.b_off = b_d;
-    bt.c_off = c_d;
-    gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
-  }
-  // 4. truncation by pivoted QR of Bt: V~ = Q2[:, :k], Z = Pi R2[:k, :]^T
-  for (int t = 0; t < T; ++t) {
-    QrcpTask& q = h->tk_h[t];
-    q = QrcpTask{};
-    q.Y = h->Bt + (int64_t)t * nb * h->smax;
-    q.ldy = nb;
-    q.m = ncols;
-    q.q = t1[t];
-    q.tol = tol_trunc;
-    q.max_rank = maxrank + 1;
-    q.min_tail = 0;
-    q.Q = vt + (int64_t)t * h->slot;
-    q.ldq = nb;
-    q.Z = h->Zb + (int64_t)t * h->smax * (h->slot / h->nb + 1);
-    q.ldz = h->smax;
-    q.rank = h->qr_d + t;
-    q.flag = h->qr_d + h->nt + t;
-  }
-  HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, T * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
-  HIPCHK(launch_qrcp(h->tk_d, T, h->s));
-  HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
-  sync(h);
-  meta_reset(h);
-  std::vector<int> k2(T);
-  int maxk = 0;
-  for (int t = 0; t < T; ++t) {
-    k2[t] = h->qr_h[t];
-    if (k2[t] > maxrank) {
-      h->bad_i = i_first + t;
-      h->bad_j = col;
-      throw Fail{TLR_ERANK};
+  std::vector<int> lr;  // tiles still headed for a low-rank form
+  for (int t = 0; t < T; ++t)
+    if (!dense[t]) lr.push_back(t);
+  const int L = (int)lr.size();
+  std::vector<int> k2(T, 0);
+  if (L > 0) {
+    meta_reserve(h, 3 * (int64_t)L, 3 * (int64_t)L);
+    // 3. project: Bt_t = C_t^T Q1_t (ncols x t1)
+    int *m_d, *n_d, *k_d;
+    int* m_h = im_take(h, L, &m_d);
+    int* n_h = im_take(h, L, &n_d);
+    int* k_h = im_take(h, L, &k_d);
+    int64_t *a_d, *b_d, *c_d;
+    int64_t* a_h = lm_take(h, L, &a_d);
+    int64_t* b_h = lm_take(h, L, &b_d);
+    int64_t* c_h = lm_take(h, L, &c_d);
+    int maxn = 1;
+    for (int q = 0; q < L; ++q) {
+      const int t = lr[q];
+      m_h[q] = ncols;
+      n_h[q] = std::max(1, t1[t]);
+      k_h[q] = tile_rows(h, i_first + t);
+      a_h[q] = (int64_t)t * nb;                       // row offset of tile t in src (contigT frame)
+      b_h[q] = (int64_t)t * nb;                       // Q1 rows
+      c_h[q] = (int64_t)t * nb * h->smax;             // Bt block
+      maxn = std::max(maxn, n_h[q]);
     }
-    rk_out[(size_t)(i_first + t) * h->nt + col] = k2[t];
-    maxk = std::max(maxk, k2[t]);
-    const double m = tile_rows(h, i_first + t);
-    cflops += 2.0 * ncols * t1[t] * m + 4.0 * ncols * t1[t] * k2[t] + 2.0 * ncols * k2[t] * k2[t] +
-              2.0 * m * t1[t] * k2[t];
+    im_push(h, m_h, m_d, 3 * (int64_t)L);
+    lm_push(h, a_h, a_d, 3 * (int64_t)L);
+    {
+      GemmSeg sg{};
+      sg.A = op_contigT(src, ld, 0, 0);
+      sg.B = op_contigT(h->Q1, h->n, 0, 0);
+      sg.K = nb;
+      GemmBatch bt{};
+      bt.count = L; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
+      gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
+    }
+    // 4. truncation by pivoted QR of Bt: V~ = Q2[:, :k], Z = Pi R2[:k, :]^T
+    for (int q = 0; q < L; ++q) {
+      const int t = lr[q];
+      QrcpTask& tk = h->tk_h[q];
+      tk = QrcpTask{};
+      tk.Y = h->Bt + (int64_t)t * nb * h->smax;
+      tk.ldy = nb;
+      tk.m = ncols;
+      tk.q = t1[t];
+      tk.tol = tol_trunc;
+      tk.max_rank = maxrank + 1;
+      tk.min_tail = 0;
+      tk.Q = vt + (int64_t)t * h->vslot;
+      tk.ldq = nb;
+      tk.Z = h->Zb + (int64_t)t * h->smax * (maxrank + 1);
+      tk.ldz = h->smax;
+      tk.rank = h->qr_d + t;
+      tk.flag = h->qr_d + h->nt + t;
+    }
+    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_qrcp(h->tk_d, L, h->s));
+    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    sync(h);
+    meta_reset(h);
+    for (int q = 0; q < L; ++q) {
+      const int t = lr[q];
+      k2[t] = h->qr_h[t];
+      const double m = tile_rows(h, i_first + t);
+      cflops += 2.0 * ncols * t1[t] * m + 4.0 * ncols * t1[t] * k2[t] + 2.0 * ncols * k2[t] * k2[t] +
+                2.0 * m * t1[t] * k2[t];
+      if (k2[t] > maxrank) {
+        if (h->strict) {
+          h->bad_i = i_first + t;
+          h->bad_j = col;
+          throw Fail{TLR_ERANK};
+        }
+        dense[t] = 1;
+      }
+    }
   }
-  if (maxk == 0) {
-    prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
-    return;
-  }
-  // 5. U_t = Q1_t Z_t  (m_t x k_t)
-  m_h = im_take(h, T, &m_d);
-  n_h = im_take(h, T, &n_d);
-  k_h = im_take(h, T, &k_d);
-  a_h = lm_take(h, T, &a_d);
-  b_h = lm_take(h, T, &b_d);
-  c_h = lm_take(h, T, &c_d);
-  int maxm = 1;
+  // record the outcome
+  int maxk = 0, nlr = 0, ndense = 0;
   for (int t = 0; t < T; ++t) {
-    m_h[t] = tile_rows(h, i_first + t);
-    n_h[t] = k2[t];
-    k_h[t] = t1[t];
-    a_h[t] = (int64_t)t * nb;
-    b_h[t] = (int64_t)t * h->smax * (h->slot / h->nb + 1);
-    c_h[t] = slot_of(h, i_first + t, col) * h->slot;
-    maxm = std::max(maxm, m_h[t]);
+    const size_t id = tid_of(h, i_first + t, col);
+    F.isdense[id] = dense[t];
+    if (dense[t]) {
+      F.rk[id] = ncols;
+      F.uoff[id] = take_dense_block(h);
+      F.voff[id] = dense_voff;
+      ++ndense;
+    } else {
+      F.rk[id] = k2[t];
+      F.uoff[id] = F.u_base + slot_of(h, i_first + t, col) * h->slot;
+      F.voff[id] = F.v_base + slot_of(h, i_first + t, col) * h->slot;
+      maxk = std::max(maxk, k2[t]);
+      if (k2[t] > 0) ++nlr;
+    }
   }
-  im_push(h, m_h, m_d, 3 * T);
-  lm_push(h, a_h, a_d, 3 * T);
-  GemmSeg sg{};
-  sg.A = op_contig(h->Q1, h->n, 0, 0);
-  sg.B = op_contigT(h->Zb, h->smax, 0, 0);
-  sg.K = h->smax;
-  GemmBatch bt{};
-  bt.count = T;
-  bt.m_of = m_d;
-  bt.n_of = n_d;
-  bt.k_of = k_d;
-  bt.a_off = a_d;
-  bt.b_off = b_d;
-  bt.c_off = c_d;
-  gemm(h, maxm, maxk, 1, &sg, Uslots, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
+  // 5. U_t = Q1_t Z_t  (m_t x k_t) for the low-rank tiles
+  meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
+  if (nlr > 0) {
+    int *m_d, *n_d, *k_d;
+    int* m_h = im_take(h, nlr, &m_d);
+    int* n_h = im_take(h, nlr, &n_d);
+    int* k_h = im_take(h, nlr, &k_d);
+    int64_t *a_d, *b_d, *c_d;
+    int64_t* a_h = lm_take(h, nlr, &a_d);
+    int64_t* b_h = lm_take(h, nlr, &b_d);
+    int64_t* c_h = lm_take(h, nlr, &c_d);
+    int maxm = 1, q = 0;
+    for (int t = 0; t < T; ++t) {
+      if (dense[t] || k2[t] == 0) continue;
+      m_h[q] = tile_rows(h, i_first + t);
+      n_h[q] = k2[t];
+      k_h[q] = t1[t];
+      a_h[q] = (int64_t)t * nb;
+      b_h[q] = (int64_t)t * h->smax * (maxrank + 1);
+      c_h[q] = F.uoff[tid_of(h, i_first + t, col)];
+      maxm = std::max(maxm, m_h[q]);
+      ++q;
+    }
+    im_push(h, m_h, m_d, 3 * (int64_t)nlr);
+    lm_push(h, a_h, a_d, 3 * (int64_t)nlr);
+    GemmSeg sg{};
+    sg.A = op_contig(h->Q1, h->n, 0, 0);
+    sg.B = op_contigT(h->Zb, h->smax, 0, 0);
+    sg.K = h->smax;
+    GemmBatch bt{};
+    bt.count = nlr; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
+    gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
+  }
+  // dense tiles: copy the tile into its block
+  if (ndense > 0) {
+    int *m_d, *k_d;
+    int* m_h = im_take(h, ndense, &m_d);
+    int* k_h = im_take(h, ndense, &k_d);
+    int64_t *so_d, *do_d;
+    int64_t* so_h = lm_take(h, ndense, &so_d);
+    int64_t* do_h = lm_take(h, ndense, &do_d);
+    int q = 0;
+    for (int t = 0; t < T; ++t) {
+      if (!dense[t]) continue;
+      m_h[q] = tile_rows(h, i_first + t);
+      k_h[q] = ncols;
+      so_h[q] = (int64_t)t * nb;
+      do_h[q] = F.uoff[tid_of(h, i_first + t, col)];
+      ++q;
+    }
+    im_push(h, m_h, m_d, 2 * (int64_t)ndense);
+    lm_push(h, so_h, so_d, 2 * (int64_t)ndense);
+    HIPCHK(launch_batched_copy(src, ld, so_d, h->arena, nb, do_d, m_d, k_d, (int64_t)nb * ncols, ndense, h->s));
+  }
   prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
 }
 
-// V(i, col) = Dinv_col * V~_i  for the T tiles below the diagonal
-void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt, double* Vslots,
-                  const std::vector<int>& rks) {
+// V(i, col) = Dinv_col * V~_i for the low-rank tiles below the diagonal
+void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt, Family& F) {
   if (T <= 0) return;
+  std::vector<int> ts;
+  for (int t = 0; t < T; ++t) {
+    const size_t id = tid_of(h, i_first + t, col);
+    if (!F.isdense[id] && F.rk[id] > 0) ts.push_back(t);
+  }
+  const int cnt = (int)ts.size();
+  if (cnt == 0) return;
+  meta_reserve(h, 3 * (int64_t)cnt, 3 * (int64_t)cnt);
   int *m_d, *n_d, *k_d;
-  int* m_h = im_take(h, T, &m_d);
-  int* n_h = im_take(h, T, &n_d);
-  int* k_h = im_take(h, T, &k_d);
+  int* m_h = im_take(h, cnt, &m_d);
+  int* n_h = im_take(h, cnt, &n_d);
+  int* k_h = im_take(h, cnt, &k_d);
   int64_t *a_d, *b_d, *c_d;
-  int64_t* a_h = lm_take(h, T, &a_d);
-  int64_t* b_h = lm_take(h, T, &b_d);
-  int64_t* c_h = lm_take(h, T, &c_d);
+  int64_t* a_h = lm_take(h, cnt, &a_d);
+  int64_t* b_h = lm_take(h, cnt, &b_d);
+  int64_t* c_h = lm_take(h, cnt, &c_d);
   const int nbj = tile_rows(h, col);
   int maxk = 0;
-  for (int t = 0; t < T; ++t) {
-    const int i = i_first + t;
-    m_h[t] = nbj;
-    n_h[t] = rks[(size_t)i * h->nt + col];
-    k_h[t] = nbj;
-    a_h[t] = 0;
-    b_h[t] = (int64_t)t * h->slot;
-    c_h[t] = slot_of(h, i, col) * h->slot;
-    maxk = std::max(maxk, n_h[t]);
+  double kt = 0.0;
+  for (int q = 0; q < cnt; ++q) {
+    const int t = ts[q];
+    const size_t id = tid_of(h, i_first + t, col);
+    m_h[q] = nbj;
+    n_h[q] = F.rk[id];
+    k_h[q] = nbj;
+    a_h[q] = 0;
+    b_h[q] = (int64_t)t * h->vslot;
+    c_h[q] = F.voff[id];
+    maxk = std::max(maxk, n_h[q]);
+    kt += n_h[q];
   }
-  if (maxk == 0) return;
-  im_push(h, m_h, m_d, 3 * T);
-  lm_push(h, a_h, a_d, 3 * T);
+  im_push(h, m_h, m_d, 3 * (int64_t)cnt);
+  lm_push(h, a_h, a_d, 3 * (int64_t)cnt);
   GemmSeg sg{};
-  sg.A = op_contig(h->Dinv + (int64_t)col * h->nb * h->nb, h->nb, 0, 0);
+  sg.A = op_contig(dinv_tile(h, col), h->nb, 0, 0);
   sg.B = op_contigT(vt, h->nb, 0, 0);
   sg.K = nbj;
   GemmBatch bt{};
-  bt.count = T;
-  bt.m_of = m_d;
-  bt.n_of = n_d;
-  bt.k_of = k_d;
-  bt.a_off = a_d;
-  bt.b_off = b_d;
-  bt.c_off = c_d;
+  bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
   const size_t e_t = prof_mark(h);
-  gemm(h, nbj, maxk, 1, &sg, Vslots, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
-  double kt = 0.0;
-  for (int t = 0; t < T; ++t) kt += n_h[t];
+  gemm(h, nbj, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
   prof_add(h, TLR_K_LOWRANK, e_t, 2.0 * nbj * nbj * kt, 8.0 * (2.0 * nbj * kt + (double)nbj * nbj));
 }
 
 // ---------------------------------------------------------------------------
-// W-build and column GEMM of the TLR factorisation (primal):
-// C(i, j) = Sigma(i, j) - sum_k U_ik (V_ik^T V_jk) U_jk^T, i in [j, nt)
-// written to h->col (row offset (i - j) nb, ld n).
+// W-build and column GEMM of the TLR factorisation:
+// C(i, j) = Gen(i, j) - sum_terms sum_k L1(i,k) L2(j,k)^T, i in [j, nt),
+// L1(i,k) L2(j,k)^T = U1_ik (V1_ik^T V2_jk) U2_jk^T, written to out (row
+// offset (i - j) nb, ld n).  Gen is Sigma (primal) or dSigma/dbeta (tangent).
 // ---------------------------------------------------------------------------
-struct LRTerm {           // one low-rank product family  L1(i,k) L2(j,k)^T
-  const double* Ui;       // left factor slots of L1: U
-  const double* Vi;       //                          V
-  const std::vector<int>* rki;
-  const double* Uj;       // right factor slots of L2 (row j)
-  const double* Vj;
-  const std::vector<int>* rkj;
+struct LRTerm {
+  const Family* Fi;   // left factor family (tiles of rows i)
+  const Family* Fj;   // right factor family (tiles of row j)
 };
 
 void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind) {
@@ -602,41 +712,43 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
   for (int tm = 0; tm < nterms; ++tm)
     for (int k = 0; k < j; ++k) {
       off[(size_t)tm * j + k] = R;
-      R += pad16((*terms[tm].rkj)[(size_t)j * nt + k]);
-      Ktrue += (*terms[tm].rkj)[(size_t)j * nt + k];
+      const int r = terms[tm].Fj->rk[tid_of(h, j, k)];
+      R += pad16(r);
+      Ktrue += r;
     }
   const size_t e_urow = prof_mark(h);
   // U_row (nb_j x R): zero, then copy the right factors of row j
   if (R > 0) {
-    if ((int64_t)nb * R > h->urow_cap) throw Fail{TLR_ENOMEM};
+    if ((int64_t)nb * R > h->urow_cap) NOMEM("row factor buffer");
     HIPCHK(launch_fill(h->Urow, nb, nb, R, 0.0, h->s));
-    for (int tm = 0; tm < nterms; ++tm) {
-      int cnt = 0;
+    int cnt = 0;
+    for (int tm = 0; tm < nterms; ++tm)
       for (int k = 0; k < j; ++k)
-        if ((*terms[tm].rkj)[(size_t)j * nt + k] > 0) ++cnt;
-      if (cnt == 0) continue;
-      int *m_d, *k_d;
-      int* m_h = im_take(h, cnt, &m_d);
-      int* k_h = im_take(h, cnt, &k_d);
-      int64_t *so_d, *do_d;
-      int64_t* so_h = lm_take(h, cnt, &so_d);
-      int64_t* do_h = lm_take(h, cnt, &do_d);
-      int c = 0;
-      int64_t maxe = 0;
+        if (terms[tm].Fj->rk[tid_of(h, j, k)] > 0) ++cnt;
+    meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
+    int *m_d, *k_d;
+    int* m_h = im_take(h, cnt, &m_d);
+    int* k_h = im_take(h, cnt, &k_d);
+    int64_t *so_d, *do_d;
+    int64_t* so_h = lm_take(h, cnt, &so_d);
+    int64_t* do_h = lm_take(h, cnt, &do_d);
+    int c = 0;
+    int64_t maxe = 0;
+    for (int tm = 0; tm < nterms; ++tm)
       for (int k = 0; k < j; ++k) {
-        const int r = (*terms[tm].rkj)[(size_t)j * nt + k];
+        const size_t id = tid_of(h, j, k);
+        const int r = terms[tm].Fj->rk[id];
         if (r <= 0) continue;
         m_h[c] = nbj;
         k_h[c] = r;
-        so_h[c] = slot_of(h, j, k) * h->slot;
+        so_h[c] = terms[tm].Fj->uoff[id];
         do_h[c] = off[(size_t)tm * j + k] * nb;
         maxe = std::max<int64_t>(maxe, (int64_t)nbj * r);
         ++c;
       }
-      im_push(h, m_h, m_d, 2 * (int64_t)cnt);
-      lm_push(h, so_h, so_d, 2 * (int64_t)cnt);
-      HIPCHK(launch_batched_copy(terms[tm].Uj, nb, so_d, h->Urow, nb, do_d, m_d, k_d, maxe, cnt, h->s));
-    }
+    im_push(h, m_h, m_d, 2 * (int64_t)cnt);
+    lm_push(h, so_h, so_d, 2 * (int64_t)cnt);
+    HIPCHK(launch_batched_copy(h->arena, nb, so_d, h->Urow, nb, do_d, m_d, k_d, maxe, cnt, h->s));
   }
   prof_add(h, TLR_K_LOWRANK, e_urow, 0.0, 16.0 * nbj * (double)Ktrue);
   // chunks of row tiles [i0, i1) such that W and X fit
@@ -648,91 +760,97 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       const int64_t wrows = (int64_t)(i1 + 1 - i0) * nb;
       int64_t xadd = 0;
       for (int tm = 0; tm < nterms; ++tm)
-        for (int k = 0; k < j; ++k)
-          xadd += (int64_t)(h->slot / nb) * pad16((*terms[tm].rkj)[(size_t)j * nt + k]);
+        for (int k = 0; k < j; ++k) {
+          const int a = terms[tm].Fi->rk[tid_of(h, i1, k)];
+          xadd += (int64_t)(a > h->maxrank ? nb : h->maxrank) * pad16(terms[tm].Fj->rk[tid_of(h, j, k)]);
+        }
       if (wrows * std::max<int64_t>(R, 1) > h->w_cap || xneed + xadd > h->x_cap) break;
       xneed += xadd;
       ++i1;
     }
-    if (i1 == i0) throw Fail{TLR_ENOMEM};
+    if (i1 == i0) NOMEM("W/X workspace for one row of tiles");
     int64_t mrows = 0;
     for (int i = i0; i < i1; ++i) mrows += tile_rows(h, i);
     const int64_t ldw = (int64_t)(i1 - i0) * nb;
     const size_t e_w = prof_mark(h);
     double wflops = 0.0, wbytes = 0.0;
     if (R > 0) {
+      const int64_t pairs = (int64_t)nterms * (i1 - i0) * j;
+      meta_reserve(h, 6 * pairs, 6 * pairs);
       HIPCHK(launch_fill(h->Wb, ldw, ldw, R, 0.0, h->s));
       int64_t xoff = 0;
-      for (int tm = 0; tm < nterms; ++tm) {
-        const LRTerm& T = terms[tm];
-        int cnt = 0, maxa = 1, maxb = 1;
-        for (int i = i0; i < i1; ++i)
-          for (int k = 0; k < j; ++k) {
-            const int a = (*T.rki)[(size_t)i * nt + k];
-            const int b = (*T.rkj)[(size_t)j * nt + k];
-            if (a <= 0 || b <= 0) continue;
-            ++cnt;
-            maxa = std::max(maxa, a);
-            maxb = std::max(maxb, b);
-          }
-        if (cnt == 0) continue;
-        int *xm_d, *xn_d, *xk_d, *wm_d, *wn_d, *wk_d;
-        int* xm_h = im_take(h, cnt, &xm_d);
-        int* xn_h = im_take(h, cnt, &xn_d);
-        int* xk_h = im_take(h, cnt, &xk_d);
-        int* wm_h = im_take(h, cnt, &wm_d);
-        int* wn_h = im_take(h, cnt, &wn_d);
-        int* wk_h = im_take(h, cnt, &wk_d);
-        int64_t *xa_d, *xb_d, *xc_d, *wa_d, *wb_d, *wc_d;
-        int64_t* xa_h = lm_take(h, cnt, &xa_d);
-        int64_t* xb_h = lm_take(h, cnt, &xb_d);
-        int64_t* xc_h = lm_take(h, cnt, &xc_d);
-        int64_t* wa_h = lm_take(h, cnt, &wa_d);
-        int64_t* wb_h = lm_take(h, cnt, &wb_d);
-        int64_t* wc_h = lm_take(h, cnt, &wc_d);
-        int c = 0, maxrows = 1;
-        for (int i = i0; i < i1; ++i)
-          for (int k = 0; k < j; ++k) {
-            const int a = (*T.rki)[(size_t)i * nt + k];
-            const int b = (*T.rkj)[(size_t)j * nt + k];
-            if (a <= 0 || b <= 0) continue;
-            const int64_t si = slot_of(h, i, k) * h->slot;   // i >= j > k
-            xm_h[c] = a; xn_h[c] = b; xk_h[c] = nb;
-            xa_h[c] = si;
-            xb_h[c] = slot_of(h, j, k) * h->slot;
-            xc_h[c] = xoff;                                  // X_ik: a x b, ld maxa
-            wm_h[c] = tile_rows(h, i); wn_h[c] = b; wk_h[c] = a;
-            wa_h[c] = si;
-            wb_h[c] = xoff;
-            wc_h[c] = (int64_t)(i - i0) * nb + off[(size_t)tm * j + k] * ldw;
-            xoff += (int64_t)maxa * b;
-            maxrows = std::max(maxrows, wm_h[c]);
-            wflops += 2.0 * a * b * ((double)nb + wm_h[c]);
-            wbytes += 8.0 * ((double)nb * (a + b) + (double)wm_h[c] * (a + b));
-            ++c;
-          }
-        if (xoff > h->x_cap) throw Fail{TLR_ENOMEM};
-        im_push(h, xm_h, xm_d, 6 * (int64_t)cnt);
-        lm_push(h, xa_h, xa_d, 6 * (int64_t)cnt);
-        GemmSeg xs{};
-        xs.A = op_contigT(T.Vi, nb, 0, 0);
-        xs.B = op_contigT(T.Vj, nb, 0, 0);
-        xs.K = nb;
-        GemmBatch xb{};
-        xb.count = cnt;
-        xb.m_of = xm_d; xb.n_of = xn_d; xb.k_of = xk_d;
-        xb.a_off = xa_d; xb.b_off = xb_d; xb.c_off = xc_d;
-        gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb, false, 32, 32);
-        GemmSeg ws{};
-        ws.A = op_contig(T.Ui, nb, 0, 0);
-        ws.B = op_contigT(h->Xb, maxa, 0, 0);
-        ws.K = maxa;
-        GemmBatch wb{};
-        wb.count = cnt;
-        wb.m_of = wm_d; wb.n_of = wn_d; wb.k_of = wk_d;
-        wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
-        gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32);
-      }
+      // pairs grouped by the kind of the left tile: low-rank (a <= maxrank) and dense
+      for (int tm = 0; tm < nterms; ++tm)
+        for (int grp = 0; grp < 2; ++grp) {
+          const Family& Fi = *terms[tm].Fi;
+          const Family& Fj = *terms[tm].Fj;
+          int cnt = 0, maxa = 1, maxb = 1;
+          for (int i = i0; i < i1; ++i)
+            for (int k = 0; k < j; ++k) {
+              const size_t ik = tid_of(h, i, k), jk = tid_of(h, j, k);
+              const int a = Fi.rk[ik], b = Fj.rk[jk];
+              if (a <= 0 || b <= 0 || (int)Fi.isdense[ik] != grp) continue;
+              ++cnt;
+              maxa = std::max(maxa, a);
+              maxb = std::max(maxb, b);
+            }
+          if (cnt == 0) continue;
+          int *xm_d, *xn_d, *xk_d, *wm_d, *wn_d, *wk_d;
+          int* xm_h = im_take(h, cnt, &xm_d);
+          int* xn_h = im_take(h, cnt, &xn_d);
+          int* xk_h = im_take(h, cnt, &xk_d);
+          int* wm_h = im_take(h, cnt, &wm_d);
+          int* wn_h = im_take(h, cnt, &wn_d);
+          int* wk_h = im_take(h, cnt, &wk_d);
+          int64_t *xa_d, *xb_d, *xc_d, *wa_d, *wb_d, *wc_d;
+          int64_t* xa_h = lm_take(h, cnt, &xa_d);
+          int64_t* xb_h = lm_take(h, cnt, &xb_d);
+          int64_t* xc_h = lm_take(h, cnt, &xc_d);
+          int64_t* wa_h = lm_take(h, cnt, &wa_d);
+          int64_t* wb_h = lm_take(h, cnt, &wb_d);
+          int64_t* wc_h = lm_take(h, cnt, &wc_d);
+          int c = 0, maxrows = 1;
+          for (int i = i0; i < i1; ++i)
+            for (int k = 0; k < j; ++k) {
+              const size_t ik = tid_of(h, i, k), jk = tid_of(h, j, k);
+              const int a = Fi.rk[ik], b = Fj.rk[jk];
+              if (a <= 0 || b <= 0 || (int)Fi.isdense[ik] != grp) continue;
+              xm_h[c] = a; xn_h[c] = b; xk_h[c] = nb;
+              xa_h[c] = Fi.voff[ik];
+              xb_h[c] = Fj.voff[jk];
+              xc_h[c] = xoff;                                  // X_ik: a x b, ld maxa
+              wm_h[c] = tile_rows(h, i); wn_h[c] = b; wk_h[c] = a;
+              wa_h[c] = Fi.uoff[ik];
+              wb_h[c] = xoff;
+              wc_h[c] = (int64_t)(i - i0) * nb + off[(size_t)tm * j + k] * ldw;
+              xoff += (int64_t)maxa * b;
+              maxrows = std::max(maxrows, wm_h[c]);
+              wflops += 2.0 * a * b * ((double)nb + wm_h[c]);
+              wbytes += 8.0 * ((double)nb * (a + b) + (double)wm_h[c] * (a + b));
+              ++c;
+            }
+          if (xoff > h->x_cap) NOMEM("X workspace");
+          im_push(h, xm_h, xm_d, 6 * (int64_t)cnt);
+          lm_push(h, xa_h, xa_d, 6 * (int64_t)cnt);
+          GemmSeg xs{};
+          xs.A = op_contigT(h->arena, nb, 0, 0);
+          xs.B = op_contigT(h->arena, nb, 0, 0);
+          xs.K = nb;
+          GemmBatch xb{};
+          xb.count = cnt;
+          xb.m_of = xm_d; xb.n_of = xn_d; xb.k_of = xk_d;
+          xb.a_off = xa_d; xb.b_off = xb_d; xb.c_off = xc_d;
+          gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb, false, grp ? 128 : 32, 32);
+          GemmSeg ws{};
+          ws.A = op_contig(h->arena, nb, 0, 0);
+          ws.B = op_contigT(h->Xb, maxa, 0, 0);
+          ws.K = maxa;
+          GemmBatch wb{};
+          wb.count = cnt;
+          wb.m_of = wm_d; wb.n_of = wn_d; wb.k_of = wk_d;
+          wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
+          gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32);
+        }
     }
     prof_add(h, TLR_K_LOWRANK, e_w, wflops, wbytes);
     // column GEMM with generation epilogue
@@ -761,8 +879,7 @@ void reset_info(tlr_handle_s* h) {
   HIPCHK(hipMemcpyAsync(h->info_d, h->h_info, sizeof(unsigned long long), hipMemcpyHostToDevice, h->s));
 }
 
-double* dinv_tile(tlr_handle_s* h, int j) { return h->Dinv + (int64_t)j * h->nb * h->nb; }
-double* diag_tile(tlr_handle_s* h, int j) { return h->D + (int64_t)j * h->nb * h->nb; }
+
 double* panel(tlr_handle_s* h, double* base, int j) { return base + panel_offset(h->n, h->nb, j); }
 
 // Tangent of the diagonal step: C_jj = L_jj L_jj^T  =>
@@ -851,17 +968,30 @@ void factor_dense(tlr_handle_s* h, bool tangent) {
   }
 }
 
+std::vector<int> predict_ranks(const tlr_handle_s* h, const Family& F, int j, int T) {
+  // the tile up-left on the same diagonal and the tile to the left
+  std::vector<int> pred(T);
+  for (int t = 0; t < T; ++t) {
+    const int i = j + 1 + t;
+    pred[t] = (j > 0) ? std::max(F.rk[tid_of(h, i - 1, j - 1)], F.rk[tid_of(h, i, j - 1)]) : 48;
+  }
+  return pred;
+}
+
 void factor_tlr(tlr_handle_s* h, bool tangent) {
   const int nt = h->nt, nb = h->nb;
   reset_info(h);
-  std::fill(h->rk.begin(), h->rk.end(), 0);
-  std::fill(h->rkd.begin(), h->rkd.end(), 0);
+  family_reset(h, h->fam[0]);
+  family_reset(h, h->fam[1]);
+  h->dense_used = 0;
   meta_reset(h);
   sync(h);
-  std::vector<int> pred(nt);
+  Family& P = h->fam[0];
+  Family& G = h->fam[1];
   for (int j = 0; j < nt; ++j) {
     const int nbj = tile_rows(h, j);
-    LRTerm tm{h->U, h->V, &h->rk, h->U, h->V, &h->rk};
+    const int64_t dinv_j = h->dinv_off + (int64_t)j * nb * nb;
+    LRTerm tm{&P, &P};
     tlr_column_update(h, j, 1, &tm, h->col, kEpiGenMinus);
     const size_t e_d = prof_mark(h);
     HIPCHK(launch_copy_block(h->col, h->n, diag_tile(h, j), nb, nbj, nbj, h->s));
@@ -870,84 +1000,93 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     prof_add(h, TLR_K_DIAG, e_d, 2.0 / 3.0 * nbj * (double)nbj * nbj, 16.0 * nbj * (double)nbj);
     const int T = nt - j - 1;
     if (T > 0) {
-      for (int t = 0; t < T; ++t) {
-        const int i = j + 1 + t;
-        pred[t] = (j > 0) ? std::max(h->rk[(size_t)(i - 1) * nt + (j - 1)], h->rk[(size_t)i * nt + (j - 1)]) : 48;
-      }
-      compress_column(h, h->col + nbj, h->n, j + 1, T, j, nbj, h->U, h->Vtmp, h->rk, pred, h->maxrank);
-      lowrank_trsm(h, j, j + 1, T, h->Vtmp, h->V, h->rk);
+      compress_column(h, h->col + nbj, h->n, j + 1, T, j, nbj, P, h->Vtmp, predict_ranks(h, P, j, T), dinv_j);
+      lowrank_trsm(h, j, j + 1, T, h->Vtmp, P);
     }
     if (!tangent) continue;
-    // dC(:, j) = dSigma/dbeta - sum_k [dU_ik (dV_ik^T V_jk) U_jk^T + U_ik (V_ik^T dV_jk) dU_jk^T]
-    LRTerm tt[2] = {{h->Ud, h->Vd, &h->rkd, h->U, h->V, &h->rk}, {h->U, h->V, &h->rk, h->Ud, h->Vd, &h->rkd}};
+    // dC(:, j) = dSigma/dbeta - sum_k [dL_ik L_jk^T + L_ik dL_jk^T]
+    LRTerm tt[2] = {{&G, &P}, {&P, &G}};
     tlr_column_update(h, j, 2, tt, h->cold, kEpiDGenMinus);
     double* ddj = h->Dd + (int64_t)j * nb * nb;
+    const size_t e_td = prof_mark(h);
     tangent_diag(h, j, h->cold, h->n, diag_tile(h, j), nb, ddj, nb);
+    prof_add(h, TLR_K_DIAG, e_td, 6.0 * nbj * (double)nbj * nbj, 32.0 * nbj * (double)nbj);
     if (T > 0) {
-      // dC_ij <- dC_ij - U_ij (dL_jj V_ij)^T, then compress and V <- L_jj^{-1} V
-      std::vector<int> prim(T);
-      int kmax = 0;
+      // dC_ij <- dC_ij - L_ij dL_jj^T = dC_ij - U_ij (dL_jj V_ij)^T, then compress;
+      // dL_ij = (that) L_jj^{-T}: low-rank V <- L_jj^{-1} V, dense V = L_jj^{-1}
+      int kmax = 0, cnt = 0;
       for (int t = 0; t < T; ++t) {
-        prim[t] = h->rk[(size_t)(j + 1 + t) * nt + j];
-        kmax = std::max(kmax, prim[t]);
+        const int r = P.rk[tid_of(h, j + 1 + t, j)];
+        kmax = std::max(kmax, r);
+        if (r > 0) ++cnt;
       }
-      if (kmax > 0) {
+      const size_t e_c = prof_mark(h);
+      double cf = 0.0;
+      if (cnt > 0) {
+        meta_reserve(h, 6 * (int64_t)cnt, 6 * (int64_t)cnt);
         int *m_d, *n_d, *k_d;
-        int* m_h = im_take(h, T, &m_d);
-        int* n_h = im_take(h, T, &n_d);
-        int* k_h = im_take(h, T, &k_d);
+        int* m_h = im_take(h, cnt, &m_d);
+        int* n_h = im_take(h, cnt, &n_d);
+        int* k_h = im_take(h, cnt, &k_d);
         int64_t *a_d, *b_d, *c_d;
-        int64_t* a_h = lm_take(h, T, &a_d);
-        int64_t* b_h = lm_take(h, T, &b_d);
-        int64_t* c_h = lm_take(h, T, &c_d);
+        int64_t* a_h = lm_take(h, cnt, &a_d);
+        int64_t* b_h = lm_take(h, cnt, &b_d);
+        int64_t* c_h = lm_take(h, cnt, &c_d);
+        int q = 0;
         for (int t = 0; t < T; ++t) {
-          m_h[t] = nbj; n_h[t] = prim[t]; k_h[t] = nbj;
-          a_h[t] = 0;
-          b_h[t] = slot_of(h, j + 1 + t, j) * h->slot;
-          c_h[t] = (int64_t)t * h->slot;
+          const size_t id = tid_of(h, j + 1 + t, j);
+          if (P.rk[id] <= 0) continue;
+          m_h[q] = nbj; n_h[q] = P.rk[id]; k_h[q] = nbj;
+          a_h[q] = 0;
+          b_h[q] = P.voff[id];
+          c_h[q] = (int64_t)t * nb * nb;
+          cf += 2.0 * nbj * nbj * P.rk[id];
+          ++q;
         }
-        im_push(h, m_h, m_d, 3 * (int64_t)T);
-        lm_push(h, a_h, a_d, 3 * (int64_t)T);
+        im_push(h, m_h, m_d, 3 * (int64_t)cnt);
+        lm_push(h, a_h, a_d, 3 * (int64_t)cnt);
         GemmSeg ps{};
         ps.A = op_contig(ddj, nb, 0, 0);
-        ps.B = op_contigT(h->V, nb, 0, 0);
+        ps.B = op_contigT(h->arena, nb, 0, 0);
         ps.K = nbj;
         GemmBatch pb{};
-        pb.count = T; pb.m_of = m_d; pb.n_of = n_d; pb.k_of = k_d; pb.a_off = a_d; pb.b_off = b_d; pb.c_off = c_d;
-        gemm(h, nbj, kmax, 1, &ps, h->Vtmp, nb, epi_linear(1.0, 0.0), &pb, false, 128, 32);
-        int* m2_h = im_take(h, T, &m_d);
-        int* n2_h = im_take(h, T, &n_d);
-        int* k2_h = im_take(h, T, &k_d);
-        int64_t* a2_h = lm_take(h, T, &a_d);
-        int64_t* b2_h = lm_take(h, T, &b_d);
-        int64_t* c2_h = lm_take(h, T, &c_d);
+        pb.count = cnt; pb.m_of = m_d; pb.n_of = n_d; pb.k_of = k_d; pb.a_off = a_d; pb.b_off = b_d; pb.c_off = c_d;
+        gemm(h, nbj, kmax, 1, &ps, h->Ptmp, nb, epi_linear(1.0, 0.0), &pb, false, 128, kmax > 64 ? 128 : 32);
+        int* m2_h = im_take(h, cnt, &m_d);
+        int* n2_h = im_take(h, cnt, &n_d);
+        int* k2_h = im_take(h, cnt, &k_d);
+        int64_t* a2_h = lm_take(h, cnt, &a_d);
+        int64_t* b2_h = lm_take(h, cnt, &b_d);
+        int64_t* c2_h = lm_take(h, cnt, &c_d);
         int mmax = 1;
+        q = 0;
         for (int t = 0; t < T; ++t) {
-          m2_h[t] = tile_rows(h, j + 1 + t); n2_h[t] = nbj; k2_h[t] = prim[t];
-          a2_h[t] = slot_of(h, j + 1 + t, j) * h->slot;
-          b2_h[t] = (int64_t)t * h->slot;
-          c2_h[t] = (int64_t)nbj + (int64_t)t * nb;
-          mmax = std::max(mmax, m2_h[t]);
+          const size_t id = tid_of(h, j + 1 + t, j);
+          if (P.rk[id] <= 0) continue;
+          m2_h[q] = tile_rows(h, j + 1 + t); n2_h[q] = nbj; k2_h[q] = P.rk[id];
+          a2_h[q] = P.uoff[id];
+          b2_h[q] = (int64_t)t * nb * nb;
+          c2_h[q] = (int64_t)nbj + (int64_t)t * nb;
+          mmax = std::max(mmax, m2_h[q]);
+          cf += 2.0 * m2_h[q] * nbj * P.rk[id];
+          ++q;
         }
-        im_push(h, m2_h, m_d, 3 * (int64_t)T);
-        lm_push(h, a2_h, a_d, 3 * (int64_t)T);
+        im_push(h, m2_h, m_d, 3 * (int64_t)cnt);
+        lm_push(h, a2_h, a_d, 3 * (int64_t)cnt);
         GemmSeg cs{};
-        cs.A = op_contig(h->U, nb, 0, 0);
-        cs.B = op_contig(h->Vtmp, nb, 0, 0);
+        cs.A = op_contig(h->arena, nb, 0, 0);
+        cs.B = op_contig(h->Ptmp, nb, 0, 0);
         cs.K = kmax;
         GemmBatch cb{};
-        cb.count = T; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
+        cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
         gemm(h, mmax, nbj, 1, &cs, h->cold, h->n, epi_linear(-1.0, 1.0), &cb);
       }
-      for (int t = 0; t < T; ++t) {
-        const int i = j + 1 + t;
-        pred[t] = (j > 0) ? std::max(h->rkd[(size_t)(i - 1) * nt + (j - 1)], h->rkd[(size_t)i * nt + (j - 1)]) : 48;
-      }
-      compress_column(h, h->cold + nbj, h->n, j + 1, T, j, nbj, h->Ud, h->Vtmp, h->rkd, pred, h->maxrank_t);
-      lowrank_trsm(h, j, j + 1, T, h->Vtmp, h->Vd, h->rkd);
+      prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
+      compress_column(h, h->cold + nbj, h->n, j + 1, T, j, nbj, G, h->Vtmp, predict_ranks(h, G, j, T), dinv_j);
+      lowrank_trsm(h, j, j + 1, T, h->Vtmp, G);
     }
   }
-  HIPCHK(hipMemcpyAsync(h->rk_d, h->rk.data(), (size_t)nt * nt * sizeof(int), hipMemcpyHostToDevice, h->s));
+  family_upload(h, P);
   sync(h);
 }
 
@@ -969,7 +1108,7 @@ void solve_forward(tlr_handle_s* h, const double* z, double* logdet, double* qua
                              h->s));
       } else {
         LowRankApply a{};
-        a.U = h->U; a.V = h->V; a.slot = h->slot; a.ranks = h->rk_d;
+        a.arena = h->arena; a.uoff = h->fam[0].uoff_d; a.voff = h->fam[0].voff_d; a.ranks = h->fam[0].rk_d;
         a.n = n; a.nb = nb; a.nt = nt; a.fixed = j; a.forward = 1; a.v = ys; a.out = w; a.scale = -1.0;
         HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s));
       }
@@ -1002,7 +1141,7 @@ void solve_backward(tlr_handle_s* h) {
     HIPCHK(launch_gemv_t(dinv_tile(h, i), nb, nbi, nbi, r + r0, 1.0, 0.0, al + r0, h->s));
     if (!h->dense && i > 0) {
       LowRankApply a{};
-      a.U = h->U; a.V = h->V; a.slot = h->slot; a.ranks = h->rk_d;
+      a.arena = h->arena; a.uoff = h->fam[0].uoff_d; a.voff = h->fam[0].voff_d; a.ranks = h->fam[0].rk_d;
       a.n = n; a.nb = nb; a.nt = nt; a.fixed = i; a.forward = 0; a.v = al; a.out = r; a.scale = -1.0;
       HIPCHK(launch_lowrank_apply(a, i, h->s));
     }
@@ -1023,14 +1162,21 @@ tlr_status check_info(tlr_handle_s* h, int64_t* info) {
 
 void rank_stats(tlr_handle_s* h) {
   int64_t sum = 0;
-  int mx = 0;
+  int mx = 0, nd = 0;
+  const Family& F = h->fam[0];
   for (int i = 0; i < h->nt; ++i)
     for (int j = 0; j < i; ++j) {
-      sum += h->rk[(size_t)i * h->nt + j];
-      mx = std::max(mx, h->rk[(size_t)i * h->nt + j]);
+      const size_t id = (size_t)i * h->nt + j;
+      if (F.isdense[id]) {
+        ++nd;
+        continue;
+      }
+      sum += F.rk[id];
+      mx = std::max(mx, F.rk[id]);
     }
   h->info.rank_sum = sum;
   h->info.rank_max = mx;
+  h->info.dense_tiles = nd;
 }
 
 template <class F>
@@ -1098,20 +1244,23 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->nt = (int)((o->n + o->nb - 1) / o->nb);
     h->dense = (o->mode == TLR_MODE_DENSE);
     h->grad = o->want_grad != 0;
-    int mr = o->maxrank > 0 ? o->maxrank : o->nb / 2;
+    int mr = o->maxrank > 0 ? o->maxrank : o->nb / 4;
     mr = std::min(mr, o->nb);
-    mr = std::min(mr, kQrMaxCols - 64);
+    mr = std::min(mr, kQrMaxCols - 96);
     h->maxrank = mr;
-    h->maxrank_t = h->grad ? std::min(std::min(o->nb, mr + mr / 2), kQrMaxCols - 64) : mr;
-    const int mslot = std::max(mr, h->maxrank_t);
-    h->smax = (int)std::min<int64_t>(kQrMaxCols, pad16(mslot + 64));
+    h->strict = (o->flags & TLR_FLAG_STRICT_RANK) != 0;
+    const int mslot = mr;
+    // sketch width cap: a tile whose range finder needs more columns than
+    // this is (unless strict) kept dense
+    h->smax = (int)std::min<int64_t>(kQrMaxCols, pad16(mr + mr / 2 + 48));
     h->slot = (int64_t)o->nb * mslot;
+    h->vslot = (int64_t)o->nb * (mslot + 1);
     h->ntiles = (int64_t)h->nt * (h->nt - 1) / 2;
     const int64_t n = h->n, nb = h->nb, nt = h->nt;
     const int nterms = h->grad ? 2 : 1;
     h->d_tab = dalloc<double>(h, kTabSize);
     h->h_tab.assign(kTabSize, 0.0);
-    h->Dinv = dalloc<double>(h, nt * nb * nb);
+    if (h->dense) h->Dinv = dalloc<double>(h, nt * nb * nb);
     h->col = dalloc<double>(h, n * nb);
     if (h->grad) h->cold = dalloc<double>(h, n * nb);
     h->tw = dalloc<double>(h, 64 * nb + 3 * nb * nb);
@@ -1127,33 +1276,53 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       if (h->grad) h->Ldp = dalloc<double>(h, panels_size(n, nb));
     } else {
       h->D = dalloc<double>(h, nt * nb * nb);
-      h->U = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
-      h->V = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
-      h->rk_d = dalloc<int>(h, nt * nt);
-      h->rk.assign((size_t)nt * nt, 0);
-      if (h->grad) {
-        h->Dd = dalloc<double>(h, nt * nb * nb);
-        h->Ud = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
-        h->Vd = dalloc<double>(h, std::max<int64_t>(h->ntiles, 1) * h->slot);
-        h->rkd_d = dalloc<int>(h, nt * nt);
+      if (h->grad) h->Dd = dalloc<double>(h, nt * nb * nb);
+      // arena: [U0 | V0 | U1 | V1] slots, dense blocks, identity, Dinv tiles
+      const int nfam = h->grad ? 2 : 1;
+      const int64_t nslots = std::max<int64_t>(h->ntiles, 1);
+      // dense-tile pool: every tile when that fits in 24 GB, else as many blocks
+      const int64_t pool_budget = (24ll << 30) / (8 * nb * nb);
+      h->dense_cap = std::max<int64_t>(16, std::min<int64_t>(h->ntiles * nfam, pool_budget));
+      int64_t cur = 0;
+      for (int f = 0; f < 2; ++f) {
+        Family& F = h->fam[f];
+        if (f < nfam) {
+          F.u_base = cur; cur += nslots * h->slot;
+          F.v_base = cur; cur += nslots * h->slot;
+        }
+        F.rk.assign((size_t)nt * nt, 0);
+        F.uoff.assign((size_t)nt * nt, 0);
+        F.voff.assign((size_t)nt * nt, 0);
+        F.isdense.assign((size_t)nt * nt, 0);
+        F.rk_d = dalloc<int>(h, nt * nt);
+        F.uoff_d = dalloc<int64_t>(h, nt * nt);
+        F.voff_d = dalloc<int64_t>(h, nt * nt);
       }
-      h->rkd.assign((size_t)nt * nt, 0);
+      h->dense_off = cur; cur += h->dense_cap * nb * nb;
+      h->ident_off = cur; cur += nb * nb;
+      h->dinv_off = cur; cur += nt * nb * nb;
+      h->arena = dalloc<double>(h, cur);
+      h->Dinv = h->arena + h->dinv_off;
+      HIPCHK(launch_fill(h->arena + h->ident_off, nb, nb, nb, 0.0, h->s));
+      HIPCHK(launch_identity(h->arena + h->ident_off, nb, nb, h->s));
+      if (h->grad) h->Ptmp = dalloc<double>(h, nt * nb * nb);
       h->omega = dalloc<double>(h, nb * h->smax);
       h->Ybuf = dalloc<double>(h, n * h->smax);
       h->Q1 = dalloc<double>(h, n * h->smax);
       h->Bt = dalloc<double>(h, nt * nb * h->smax);
-      h->Vtmp = dalloc<double>(h, nt * h->slot);
+      h->Vtmp = dalloc<double>(h, nt * h->vslot);
       h->Zb = dalloc<double>(h, nt * h->smax * (mslot + 1));
-      const int64_t rmax = nterms * nt * pad16(mslot);
+      // a row of tiles may hold dense tiles (width nb) in every slot
+      const int64_t rmax = nterms * nt * nb;
       h->urow_cap = nb * rmax;
       h->Urow = dalloc<double>(h, h->urow_cap);
       int64_t wworst = 0, xworst = 0;
       for (int64_t j = 0; j < nt; ++j) {
-        wworst = std::max(wworst, (nt - j) * nb * nterms * j * pad16(mslot));
-        xworst = std::max(xworst, (nt - j) * nterms * j * (int64_t)mslot * pad16(mslot));
+        wworst = std::max(wworst, (nt - j) * nb * nterms * j * nb);
+        xworst = std::max(xworst, (nt - j) * nterms * j * nb * nb);
       }
       h->w_cap = std::max<int64_t>(std::min<int64_t>(wworst, 512ll << 20), nb * rmax);
-      h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * mslot * pad16(mslot));
+      h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * nb * nb);
       h->Wb = dalloc<double>(h, h->w_cap);
       h->Xb = dalloc<double>(h, h->x_cap);
       h->im_cap = h->lm_cap = std::max<int64_t>(1 << 16, 16 * nt * nt * nterms + 64 * nt);
@@ -1219,12 +1388,15 @@ tlr_status tlr_compress(tlr_handle_t h) {
   if (h->dense) return TLR_ENOTIMPL;
   if (!h->bound) return TLR_ESTATE;
   return guarded(h, [&]() -> tlr_status {
+    prof_reset_pool(h);
     const int nt = h->nt, nb = h->nb;
-    std::fill(h->rk.begin(), h->rk.end(), 0);
+    Family& F = h->fam[0];
+    family_reset(h, F);
+    h->dense_used = 0;
     reset_info(h);
     sync(h);
     meta_reset(h);
-    std::vector<int> pred(nt);
+    h->state = 0;
     for (int j = 0; j < nt; ++j) {
       const int nbj = tile_rows(h, j);
       HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)j * nb, nbj, (int64_t)j * nb, nbj, diag_tile(h, j), nb,
@@ -1234,27 +1406,38 @@ tlr_status tlr_compress(tlr_handle_t h) {
       const int64_t rows = h->n - (int64_t)(j + 1) * nb;
       HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)(j + 1) * nb, rows, (int64_t)j * nb, nbj, h->col,
                                  h->n, false, h->s));
-      for (int t = 0; t < T; ++t) pred[t] = (j > 0) ? h->rk[(size_t)(j + t) * nt + (j - 1)] : 48;
-      compress_column(h, h->col, h->n, j + 1, T, j, nbj, h->U, h->Vtmp, h->rk, pred, h->maxrank);
-      // V slots <- V~
-      int *m_d, *k_d;
-      int* m_h = im_take(h, T, &m_d);
-      int* k_h = im_take(h, T, &k_d);
-      int64_t *so_d, *do_d;
-      int64_t* so_h = lm_take(h, T, &so_d);
-      int64_t* do_h = lm_take(h, T, &do_d);
-      int64_t maxe = 0;
+      compress_column(h, h->col, h->n, j + 1, T, j, nbj, F, h->Vtmp, predict_ranks(h, F, j, T), h->ident_off);
+      // low-rank V slots <- V~ (no TRSM: this is Sigma itself)
+      int cnt = 0;
       for (int t = 0; t < T; ++t) {
-        m_h[t] = nbj;
-        k_h[t] = h->rk[(size_t)(j + 1 + t) * nt + j];
-        so_h[t] = (int64_t)t * h->slot;
-        do_h[t] = slot_of(h, j + 1 + t, j) * h->slot;
-        maxe = std::max<int64_t>(maxe, (int64_t)nbj * k_h[t]);
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (!F.isdense[id] && F.rk[id] > 0) ++cnt;
       }
-      im_push(h, m_h, m_d, 2 * (int64_t)T);
-      lm_push(h, so_h, so_d, 2 * (int64_t)T);
-      HIPCHK(launch_batched_copy(h->Vtmp, nb, so_d, h->V, nb, do_d, m_d, k_d, maxe, T, h->s));
+      if (cnt == 0) continue;
+      meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
+      int *m_d, *k_d;
+      int* m_h = im_take(h, cnt, &m_d);
+      int* k_h = im_take(h, cnt, &k_d);
+      int64_t *so_d, *do_d;
+      int64_t* so_h = lm_take(h, cnt, &so_d);
+      int64_t* do_h = lm_take(h, cnt, &do_d);
+      int64_t maxe = 0;
+      int q = 0;
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (F.isdense[id] || F.rk[id] <= 0) continue;
+        m_h[q] = nbj;
+        k_h[q] = F.rk[id];
+        so_h[q] = (int64_t)t * h->vslot;
+        do_h[q] = F.voff[id];
+        maxe = std::max<int64_t>(maxe, (int64_t)nbj * k_h[q]);
+        ++q;
+      }
+      im_push(h, m_h, m_d, 2 * (int64_t)cnt);
+      lm_push(h, so_h, so_d, 2 * (int64_t)cnt);
+      HIPCHK(launch_batched_copy(h->Vtmp, nb, so_d, h->arena, nb, do_d, m_d, k_d, maxe, cnt, h->s));
     }
+    family_upload(h, F);
     sync(h);
     rank_stats(h);
     h->state = 1;
@@ -1325,7 +1508,7 @@ tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z) {
                              d_z + r0 + nbj, h->s));
       } else {
         LowRankApply a{};
-        a.U = h->U; a.V = h->V; a.slot = h->slot; a.ranks = h->rk_d;
+        a.arena = h->arena; a.uoff = h->fam[0].uoff_d; a.voff = h->fam[0].voff_d; a.ranks = h->fam[0].rk_d;
         a.n = n; a.nb = nb; a.nt = nt; a.fixed = j; a.forward = 1; a.v = d_eps; a.out = d_z; a.scale = 1.0;
         HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s));
       }
@@ -1354,7 +1537,7 @@ tlr_status tlr_get_kstats(tlr_handle_t h, tlr_kstat* out) {
 
 tlr_status tlr_get_ranks(tlr_handle_t h, int32_t* host_ranks) {
   if (!h || !host_ranks) return TLR_EINVAL;
-  for (size_t i = 0; i < (size_t)h->nt * h->nt; ++i) host_ranks[i] = h->dense ? 0 : h->rk[i];
+  for (size_t i = 0; i < (size_t)h->nt * h->nt; ++i) host_ranks[i] = h->dense ? 0 : h->fam[0].rk[i];
   return TLR_OK;
 }
 
@@ -1376,10 +1559,11 @@ tlr_status tlr_get_tile(tlr_handle_t h, int32_t i, int32_t j, double* d_out, int
     } else if (i == j) {
       HIPCHK(launch_copy_block(diag_tile(h, i), h->nb, d_out, ld, mi, mj, h->s));
     } else {
-      const int k = h->rk[(size_t)i * h->nt + j];
+      const size_t id = tid_of(h, i, j);
+      const int k = h->fam[0].rk[id];
       GemmSeg sg{};
-      sg.A = op_contig(h->U + slot_of(h, i, j) * h->slot, h->nb, 0, 0);
-      sg.B = op_contig(h->V + slot_of(h, i, j) * h->slot, h->nb, 0, 0);
+      sg.A = op_contig(h->arena + h->fam[0].uoff[id], h->nb, 0, 0);
+      sg.B = op_contig(h->arena + h->fam[0].voff[id], h->nb, 0, 0);
       sg.K = k;
       gemm(h, mi, mj, 1, &sg, d_out, ld, epi_linear(1.0, 0.0));
     }
@@ -1435,7 +1619,7 @@ extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const d
     const size_t e_q = prof_mark(h);
     // a^T dSigma/dbeta a over all pairs; partial sums in the split-K workspace
     const int64_t nblk = pair_quad_blocks(h->n);
-    if (nblk > h->sk_cap) throw Fail{TLR_ENOMEM};
+    if (nblk > h->sk_cap) NOMEM("pair-sum partials");
     HIPCHK(launch_pair_quad(h->mp, h->x, h->y, h->vec + 2 * h->n, h->n, h->skw, h->scal + 2 * h->nt + 1, h->s));
     prof_add(h, TLR_K_GRADQ, e_q, (double)h->n * (double)(h->n - 1) / 2.0, 24.0 * h->n);
     HIPCHK(hipEventRecord(h->ev[1], h->s));

@@ -15,6 +15,7 @@ hipError_t launch_gemv_n(const double* A, int64_t lda, int64_t m, int64_t k, con
 hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t k, const double* x, double alpha,
                          double beta, double* y, hipStream_t s);
 hipError_t launch_fill(double* A, int64_t lda, int64_t m, int64_t ncol, double value, hipStream_t s);
+hipError_t launch_identity(double* A, int64_t lda, int64_t m, hipStream_t s);
 hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s);
 
 // Lower Cholesky of the m x m tile T (column-major, ld) in place, blocked

@@ -210,3 +210,19 @@ hipError_t launch_fill(double* A, int64_t lda, int64_t m, int64_t ncol, double v
 }
 
 }  // namespace tlrk
+
+namespace tlrk {
+
+__global__ void identity_kernel(double* A, int64_t lda, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < m) A[i * lda + i] = 1.0;
+}
+
+// diagonal of the m x m block A set to 1 (the rest is left as is)
+hipError_t launch_identity(double* A, int64_t lda, int64_t m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A, lda, m);
+  return hipGetLastError();
+}
+
+}  // namespace tlrk

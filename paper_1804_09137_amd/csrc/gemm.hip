@@ -1,11 +1,17 @@
 // FP64 MFMA GEMM for gfx950: C = epilogue(sum_s A_s B_s^T).
 //
-// One workgroup of 256 threads (4 wave64s) computes a BM x BN block of C with
-// v_mfma_f64_16x16x4f64.  K is consumed in BK = 16 slices staged through LDS;
-// the next slice is fetched into registers while the current one is used.
-// The operand roles are swapped inside the MFMA (B feeds the 16-row side) so
+// A workgroup of WM x WN wave64s computes a BM x BN block of C with
+// v_mfma_f64_16x16x4f64.  K is consumed in BK-wide slices staged through LDS
+// (two stages for the large tiles, so one barrier per slice); the next slice
+// is fetched into registers while the current one feeds the MFMAs.  The
+// operand roles are swapped inside the MFMA (B feeds the 16-row side) so
 // that each output register holds 16 consecutive rows of one column of the
 // column-major C: stores are 128-byte runs.
+//
+// Generation epilogues (C = Matern - AB^T) are split off: a Matern kernel
+// writes the block first and the GEMM then accumulates with alpha = -1,
+// beta = 1.  Compiling the Matern evaluation into the MFMA kernel raised its
+// register use enough to halve throughput.
 //
 // Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950):
 //   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
@@ -21,9 +27,10 @@ namespace tlrk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 16;
-constexpr int PAD = 16;
 constexpr int kXcds = 8;
+#ifndef TLRK_GEMM_PAD
+#define TLRK_GEMM_PAD 16
+#endif
 
 struct GemmArgs {
   int64_t M, N;
@@ -67,16 +74,16 @@ __device__ inline SliceAddr slice_addr(const Operand& o, int64_t bofs, int64_t k
   return s;
 }
 
-template <int ROWS>
+template <int ROWS, int BK, int NT>
 __device__ inline void load_slice(const Operand& o, const SliceAddr& sa, int64_t row0, int64_t R, int64_t kc,
-                                  int64_t K, double (&v)[ROWS * BK / 256], int tid) {
-  constexpr int NE = ROWS * BK / 256;
+                                  int64_t K, double (&v)[ROWS * BK / NT], int tid) {
+  constexpr int NE = ROWS * BK / NT;
   if (o.layout == kContigT) {
     const int kk = tid % BK;
     const bool kin = (kc + kk) < K;
 #pragma unroll
     for (int p = 0; p < NE; ++p) {
-      const int r = tid / BK + (256 / BK) * p;
+      const int r = tid / BK + (NT / BK) * p;
       const int64_t gr = row0 + r;
       v[p] = (kin && gr < R) ? sa.base[(sa.rofs + gr) * sa.ld + sa.col0 + kk] : 0.0;
     }
@@ -86,24 +93,24 @@ __device__ inline void load_slice(const Operand& o, const SliceAddr& sa, int64_t
     const bool rin = gr < R;
 #pragma unroll
     for (int p = 0; p < NE; ++p) {
-      const int kk = tid / ROWS + (256 / ROWS) * p;
+      const int kk = tid / ROWS + (NT / ROWS) * p;
       v[p] = (rin && (kc + kk) < K) ? sa.base[(sa.col0 + kk) * sa.ld + sa.rofs + gr] : 0.0;
     }
   }
 }
 
-template <int ROWS>
-__device__ inline void store_slice(int layout, double (*s)[ROWS + PAD], const double (&v)[ROWS * BK / 256],
+template <int ROWS, int BK, int PAD, int NT>
+__device__ inline void store_slice(int layout, double (*s)[ROWS + PAD], const double (&v)[ROWS * BK / NT],
                                    int tid) {
-  constexpr int NE = ROWS * BK / 256;
+  constexpr int NE = ROWS * BK / NT;
   if (layout == kContigT) {
     const int kk = tid % BK;
 #pragma unroll
-    for (int p = 0; p < NE; ++p) s[kk][tid / BK + (256 / BK) * p] = v[p];
+    for (int p = 0; p < NE; ++p) s[kk][tid / BK + (NT / BK) * p] = v[p];
   } else {
     const int r = tid % ROWS;
 #pragma unroll
-    for (int p = 0; p < NE; ++p) s[tid / ROWS + (256 / ROWS) * p][r] = v[p];
+    for (int p = 0; p < NE; ++p) s[tid / ROWS + (NT / ROWS) * p][r] = v[p];
   }
 }
 
@@ -127,12 +134,16 @@ __device__ inline void epi_store(const GemmEpi& ep, double* C, int64_t ldc, int6
   }
 }
 
-template <int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+// EPI = 0: linear epilogue only (fewer registers); 1: any epilogue kind.
+// DB = 1: two LDS stages, one barrier per K slice.
+template <int BM, int BN, int WM, int WN, int BK, int PAD, int EPI, int DB>
+__global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
+  constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  __shared__ double sA[BK][BM + PAD];
-  __shared__ double sB[BK][BN + PAD];
+  constexpr int NS = DB ? 2 : 1;
+  __shared__ double sA[NS][BK][BM + PAD];
+  __shared__ double sB[NS][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -181,7 +192,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double va[BM * BK / 256], vb[BN * BK / 256];
+  double va[BM * BK / NT], vb[BN * BK / NT];
   auto fetch = [&](int64_t t) {
     int s = 0;
     int64_t tl = t;
@@ -190,36 +201,58 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     const int64_t kc = tl * BK;
     const SliceAddr saA = slice_addr(sg.A, aofs[s], kc);
     const SliceAddr saB = slice_addr(sg.B, bofs[s], kc);
-    load_slice<BM>(sg.A, saA, m0, M, kc, Kb[s], va, tid);
-    load_slice<BN>(sg.B, saB, n0, N, kc, Kb[s], vb, tid);
+    load_slice<BM, BK, NT>(sg.A, saA, m0, M, kc, Kb[s], va, tid);
+    load_slice<BN, BK, NT>(sg.B, saB, n0, N, kc, Kb[s], vb, tid);
     return s;
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = sA[buf][kr][wm * (BM / WM) + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = sB[buf][kr][wn * (BN / WN) + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+    }
   };
 
   if (ks < ke) {
     int sc = fetch(ks);
-    for (int64_t t = ks; t < ke; ++t) {
-      store_slice<BM>(g.seg[sc].A.layout, sA, va, tid);
-      store_slice<BN>(g.seg[sc].B.layout, sB, vb, tid);
+    if (DB) {
+      store_slice<BM, BK, PAD, NT>(g.seg[sc].A.layout, sA[0], va, tid);
+      store_slice<BN, BK, PAD, NT>(g.seg[sc].B.layout, sB[0], vb, tid);
       __syncthreads();
-      if (t + 1 < ke) sc = fetch(t + 1);
-#pragma unroll
-      for (int k4 = 0; k4 < BK / 4; ++k4) {
-        const int kr = k4 * 4 + (lane >> 4);
-        double a[TM], b[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = sA[kr][wm * (BM / WM) + i * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = sB[kr][wn * (BN / WN) + j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+      for (int64_t t = ks; t < ke; ++t) {
+        const int cur = (int)((t - ks) & 1);
+        const bool more = t + 1 < ke;
+        if (more) sc = fetch(t + 1);
+        compute(cur);
+        if (more) {
+          store_slice<BM, BK, PAD, NT>(g.seg[sc].A.layout, sA[cur ^ 1], va, tid);
+          store_slice<BN, BK, PAD, NT>(g.seg[sc].B.layout, sB[cur ^ 1], vb, tid);
+        }
+        __syncthreads();
       }
-      __syncthreads();
+    } else {
+      for (int64_t t = ks; t < ke; ++t) {
+        store_slice<BM, BK, PAD, NT>(g.seg[sc].A.layout, sA[0], va, tid);
+        store_slice<BN, BK, PAD, NT>(g.seg[sc].B.layout, sB[0], vb, tid);
+        __syncthreads();
+        if (t + 1 < ke) sc = fetch(t + 1);
+        compute(0);
+        __syncthreads();
+      }
     }
   }
 
   // epilogue: lane holds rows m = .. + (lane & 15), columns n = .. + (lane >> 4) + 4 r
+  GemmEpi ep = g.ep;
+  if (!EPI) ep.kind = kEpiLinear;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int64_t m = m0 + wm * (BM / WM) + i * 16 + (lane & 15);
@@ -232,8 +265,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
           const double v = acc[i][j][r];
           if (g.splitk > 1)
             g.work[(int64_t)z * g.M * g.N + n * g.M + m] = v;
-          else
-            epi_store(g.ep, g.C + c_off, g.ldc, m, n, v, grow0);
+          else if (!EPI) {
+            double* c = g.C + c_off + n * g.ldc + m;
+            double o = ep.alpha * v;
+            if (ep.beta != 0.0) o += ep.beta * (*c);
+            *c = o;
+          } else
+            epi_store(ep, g.C + c_off, g.ldc, m, n, v, grow0);
         }
       }
     }
@@ -250,59 +288,101 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g) {
   epi_store(g.ep, g.C, g.ldc, m, n, v, g.ep.grow0);
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int BK = 32, int PAD = TLRK_GEMM_PAD, int EPI = 1, int DB = 0>
 static hipError_t run(GemmArgs& g, int zdim, hipStream_t s) {
+  g.kt_total = 0;
+  for (int i = 0; i < g.nseg; ++i) {
+    g.kt[i] = (g.seg[i].K + BK - 1) / BK;
+    g.kt_total += g.kt[i];
+  }
+  for (int i = 0; i < g.nseg; ++i)
+    for (const Operand* o : {&g.seg[i].A, &g.seg[i].B})
+      if (o->layout == kPanels && (o->nb % BK != 0 || o->c0 % BK != 0)) return hipErrorInvalidValue;
   g.gx = (g.M + BM - 1) / BM;
   g.gy = (g.N + BN - 1) / BN;
   const int64_t total = g.gx * g.gy;
   const int64_t grid = ((total + kXcds - 1) / kXcds) * kXcds;
   if (grid > 0x7fffffff || zdim > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN>), dim3((unsigned)grid, (unsigned)zdim), dim3(256), 0, s, g);
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, BK, PAD, EPI, DB>), dim3((unsigned)grid, (unsigned)zdim),
+                     dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
-                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
+                       const GemmEpi& ep_in, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
                        int tile_m, int tile_n) {
   if (M < 0 || N < 0 || nseg < 1 || nseg > 2 || splitk < 1) return hipErrorInvalidValue;
   if (M == 0 || N == 0) return hipSuccess;
+  GemmEpi ep = ep_in;
+  if (ep.kind != kEpiLinear) {
+    // generation first (C = Matern or dMatern/dbeta entries), then C -= A B^T:
+    // keeping the Matern code out of the MFMA kernel keeps its register
+    // allocation and schedule lean
+    if (batch && (batch->count > 1 || batch->a_off || batch->m_of)) return hipErrorInvalidValue;
+    hipError_t e = launch_matern_block(ep.mp, ep.x, ep.y, ep.grow0, M, ep.gcol0, N, C, ldc, ep.kind == kEpiDGenMinus, s);
+    if (e != hipSuccess) return e;
+    ep.kind = kEpiLinear;
+    ep.alpha = -1.0;
+    ep.beta = 1.0;
+  }
   GemmArgs g{};
   g.M = M;
   g.N = N;
   g.nseg = nseg;
   g.kt_total = 0;
+  bool panels = false, bk32 = true;
   for (int i = 0; i < nseg; ++i) {
     g.seg[i] = segs[i];
     if (segs[i].K < 0) return hipErrorInvalidValue;
     for (const Operand* o : {&segs[i].A, &segs[i].B})
-      if (o->layout == kPanels && (o->nb % BK != 0 || o->c0 % BK != 0)) return hipErrorInvalidValue;
-    g.kt[i] = (segs[i].K + BK - 1) / BK;
+      if (o->layout == kPanels) {
+        panels = true;
+        if (o->nb % 16 != 0 || o->c0 % 16 != 0) return hipErrorInvalidValue;
+        if (o->nb % 32 != 0 || o->c0 % 32 != 0) bk32 = false;
+      }
+    g.kt[i] = (segs[i].K + 15) / 16;
     g.kt_total += g.kt[i];
   }
+  if (g.kt_total == 0 && ep.alpha == -1.0 && ep.beta == 1.0) return hipSuccess;  // C already final
   g.C = C;
   g.ldc = ldc;
   g.ep = ep;
   if (batch) g.batch = *batch; else { g.batch = GemmBatch{}; g.batch.count = 1; }
   if (g.batch.count < 1) return hipErrorInvalidValue;
   if (splitk > 1 && (g.batch.count > 1 || work == nullptr)) return hipErrorInvalidValue;
-  if (g.kt_total == 0) splitk = 1;
-  if (splitk > g.kt_total && g.kt_total > 0) splitk = (int)g.kt_total;
+  if (splitk > g.kt_total) splitk = g.kt_total > 0 ? (int)g.kt_total : 1;
   g.splitk = splitk;
   g.work = work;
   const int zdim = splitk > 1 ? splitk : g.batch.count;
   hipError_t e;
-  const int bm = tile_m ? tile_m : (M <= 32) ? 32 : (M <= 64) ? 64 : 128;
-  const int bn = tile_n ? tile_n : (N <= 32) ? 32 : (N <= 64) ? 64 : 128;
-  switch (bm * 1000 + bn) {
-    case 32032: e = run<32, 32, 2, 2>(g, zdim, s); break;
-    case 32064: e = run<32, 64, 2, 2>(g, zdim, s); break;
-    case 32128: e = run<32, 128, 2, 2>(g, zdim, s); break;
-    case 64032: e = run<64, 32, 2, 2>(g, zdim, s); break;
-    case 64064: e = run<64, 64, 2, 2>(g, zdim, s); break;
-    case 64128: e = run<64, 128, 2, 2>(g, zdim, s); break;
-    case 128032: e = run<128, 32, 2, 2>(g, zdim, s); break;
-    case 128064: e = run<128, 64, 2, 2>(g, zdim, s); break;
-    default: e = run<128, 128, 2, 2>(g, zdim, s); break;
+  if (tile_m || tile_n) {
+    // hinted small tiles (batched low-rank products): four waves, one LDS stage
+    const int bm = tile_m ? tile_m : 128, bn = tile_n ? tile_n : 128;
+    switch (bm * 1000 + bn) {
+      case 32032: e = run<32, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 32064: e = run<32, 64, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 32128: e = run<32, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 64032: e = run<64, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 64064: e = run<64, 64, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 64128: e = run<64, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 128032: e = run<128, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      case 128064: e = run<128, 64, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
+      default: e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s); break;
+    }
+  } else if (panels && !bk32) {
+    e = run<128, 128, 2, 4, 16, 4, 0, 1>(g, zdim, s);
+  } else if (M >= 2048 && N >= 1024) {
+    e = run<256, 128, 4, 2, 16, 4, 0, 1>(g, zdim, s);
+  } else if (N <= 32) {
+    e = run<128, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s);
+  } else if (N <= 64) {
+    e = run<128, 64, 2, 2, 32, 4, 0, 1>(g, zdim, s);
+  } else if (M <= 32) {
+    e = run<32, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s);
+  } else if (M <= 64) {
+    e = run<64, 128, 2, 2, 32, 4, 0, 1>(g, zdim, s);
+  } else {
+    e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s);
   }
   if (e != hipSuccess || splitk == 1) return e;
   const int64_t tot = M * N;

@@ -9,9 +9,9 @@ namespace tlrk {
 //   forward, column j:  out_i += scale U_ij (V_ij^T v_j)   for i = j+1 .. nt-1
 //   backward, row i:    out_j += scale V_ij (U_ij^T v_i)   for j = 0 .. i-1
 struct LowRankApply {
-  const double* U;
-  const double* V;
-  int64_t slot;        // doubles per slot (nb * maxrank); slot ld = nb
+  const double* arena; // U_ij = arena + uoff[i*nt+j], V_ij = arena + voff[...], both ld nb
+  const int64_t* uoff;
+  const int64_t* voff;
   const int* ranks;    // device rank table, ranks[i * nt + j]
   int64_t n;
   int nb, nt;

@@ -25,19 +25,19 @@ __global__ void __launch_bounds__(256) lowrank_apply_kernel(LowRankApply a) {
     ti = a.fixed;
     tj = b;
   }
-  const int64_t slot = (int64_t)tj * a.nt - (int64_t)tj * (tj + 1) / 2 + (ti - tj - 1);
-  const int k = a.ranks[ti * a.nt + tj];
+  const int64_t id = (int64_t)ti * a.nt + tj;
+  const int k = a.ranks[id];
   if (k <= 0) return;
   const int mi = (ti == a.nt - 1) ? (int)(a.n - (int64_t)ti * a.nb) : a.nb;
   const int mj = (tj == a.nt - 1) ? (int)(a.n - (int64_t)tj * a.nb) : a.nb;
   if (a.forward) {  // t = V^T y_j, z_i -= U t
-    Bm = a.V + slot * a.slot;
-    Am = a.U + slot * a.slot;
+    Bm = a.arena + a.voff[id];
+    Am = a.arena + a.uoff[id];
     src0 = (int64_t)tj * a.nb; msrc = mj;
     dst0 = (int64_t)ti * a.nb; mdst = mi;
   } else {          // t = U^T alpha_i, r_j -= V t
-    Bm = a.U + slot * a.slot;
-    Am = a.V + slot * a.slot;
+    Bm = a.arena + a.uoff[id];
+    Am = a.arena + a.voff[id];
     src0 = (int64_t)ti * a.nb; msrc = mi;
     dst0 = (int64_t)tj * a.nb; mdst = mj;
   }

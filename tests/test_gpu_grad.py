@@ -85,3 +85,18 @@ def test_tlr_loglik_grad_value_equals_potrf_path():
     h.potrf()
     ll, _, _ = h.loglik(zd)
     assert ll == ll_g
+
+
+def test_tlr_gradient_with_dense_tiles():
+    n, nb, eps = 1600, 320, 1e-9
+    th = (1.0, 0.1, 0.5)
+    x, y, z = field(n, 0, th)
+    ref = D.gradient(x, y, z, th)
+    h = _handle(n, nb, tol=eps, maxrank=40)
+    xd, yd, zd = to_dev(x, y, z)
+    ll, (gs, gb) = h.loglik_grad(xd, yd, zd, th)
+    scale = 0.5 * (abs(ref["tr_beta"]) + abs(ref["qf_beta"]))
+    log(f"grad with {h.info().dense_tiles} dense tiles: dbeta rel {abs(gb - ref['dbeta']) / scale:.2e}")
+    assert h.info().dense_tiles > 0
+    assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
+    assert abs(gb - ref["dbeta"]) <= 100 * eps * scale

@@ -144,7 +144,7 @@ def test_tlr_compress_meets_threshold():
     n, nb, eps = 1600, 320, 1e-7
     th = (1.0, 0.1, 0.5)
     x, y, _ = field(n, 0, th, with_z=False)
-    h = _handle(n, nb, tol=eps)
+    h = _handle(n, nb, tol=eps, maxrank=200, strict_rank=True)
     xd, yd = to_dev(x, y)
     h.generate(xd, yd, th)
     h.compress()
@@ -183,3 +183,54 @@ def test_sample_is_factor_times_vector(backend):
     z = h.sample(ed).cpu().numpy()
     tol = 1e-11 if backend == "dense" else 1e-7
     assert np.max(np.abs(z - want)) <= tol * np.max(np.abs(want))
+
+
+def test_dense_fallback_and_strict_rank():
+    # tiles that need more than maxrank are kept dense (exact); with the
+    # strict flag the same factorisation raises a rank error
+    import paper_1804_09137_amd as P
+    n, nb, eps = 2000, 256, 1e-9
+    th = (1.0, 0.1, 1.0)
+    x, y, z = field(n, 1, th)
+    ref = D.loglik(x, y, z, th)["ll"]
+    h = _handle(n, nb, tol=eps, maxrank=24)
+    xd, yd, zd = to_dev(x, y, z)
+    h.generate(xd, yd, th)
+    h.potrf()
+    ll, _, _ = h.loglik(zd)
+    info = h.info()
+    log(f"dense fallback: {info.dense_tiles} dense tiles, rel {abs(ll - ref) / abs(ref):.2e}")
+    assert info.dense_tiles > 0
+    assert info.rank_max <= 24
+    assert abs(ll - ref) <= 10 * eps * abs(ref)
+    hs = _handle(n, nb, tol=eps, maxrank=24, strict_rank=True)
+    hs.generate(xd, yd, th)
+    with pytest.raises(P.RankError):
+        hs.potrf()
+
+
+def test_tlr_mixed_dense_and_lowrank_tiles():
+    # maxrank low enough that some tiles go dense and most stay low rank:
+    # every factor tile within a small multiple of eps of the dense factor
+    n, nb, eps, mr = 6000, 256, 1e-8, 48
+    th = (1.0, 0.1, 0.5)
+    x, y, z = field(n, 0, th)
+    ref = D.loglik(x, y, z, th)["ll"]
+    L = D.cholesky_lower(M.covariance(x, y, th))
+    h = _handle(n, nb, tol=eps, maxrank=mr)
+    xd, yd, zd = to_dev(x, y, z)
+    h.generate(xd, yd, th)
+    h.potrf()
+    ll, _, _ = h.loglik(zd)
+    info = h.info()
+    log(f"mixed: {info.dense_tiles} dense tiles, rank_max {info.rank_max}, rel {abs(ll - ref) / abs(ref):.2e}")
+    nt = (n + nb - 1) // nb
+    assert 0 < info.dense_tiles < nt * (nt - 1) // 2
+    assert abs(ll - ref) <= 10 * eps * abs(ref)
+    worst = 0.0
+    for j in range(0, nt, 3):
+        for i in range(j, nt, 2):
+            T = h.tile(i, j).cpu().numpy()
+            worst = max(worst, np.abs(T - L[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]).max())
+    log(f"  worst factor tile error {worst:.2e}")
+    assert worst <= 1e3 * eps
