@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtlrmle.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-HIP_SOURCES = ["matern.hip", "gemm.hip", "chol.hip", "tile_chol.hip", "compress.hip", "solve.hip",
+HIP_SOURCES = ["matern.hip", "gemm.hip", "chol.hip", "tile_chol.hip", "compress.hip", "hqr.hip", "solve.hip",
                "grad.hip", "api.hip"]
 CPP_SOURCES = ["morton.cpp"]
 

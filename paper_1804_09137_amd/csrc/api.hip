@@ -122,6 +122,10 @@ struct tlr_handle_s {
   QrcpTask* tk_d = nullptr;
   QrcpTask* tk_h = nullptr;
   int tk_cap = 0;
+  HqrTask* hq_d = nullptr;  // 4 x nt: one region per launch between synchronisations
+  HqrTask* hq_h = nullptr;
+  double* Tw = nullptr;     // nt x tw_stride compact-WY factors
+  int64_t tw_stride = 0;
   int* qr_d = nullptr;  // 2 * nt: ranks, flags
   int* qr_h = nullptr;
 
@@ -382,6 +386,10 @@ void throw_if_not_spd(tlr_handle_s* h) {
 // F.rk = rank.  Tiles whose rank would exceed maxrank are copied to a dense
 // block: F.uoff = block, F.voff = dense_voff, F.rk = ncols (unless strict).
 // pred: predicted ranks (sketch widths, and the early dense decision).
+//
+//   Y = C Omega; Y = Q_y R_y (blocked Householder); t1 from R_y's column
+//   tails; Q1 = Q_y[:, :t1]; B^T = C^T Q1 = Q_b R_b; R_b Pi = Q_r R_r cut at
+//   k; V~ = Q_b [Q_r; 0]; U = Q1 Pi R_r[:k, :]^T.
 // ---------------------------------------------------------------------------
 void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first, int T, int col, int ncols,
                      Family& F, double* vt, const std::vector<int>& pred, int64_t dense_voff) {
@@ -391,8 +399,13 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
   const size_t e_c = prof_mark(h);
   double cflops = 0.0;
   const double tol = h->o.tol;
-  const double tol_range = 0.05 * tol;  // range finder residual target (Frobenius of the samples)
-  const double tol_trunc = 0.9 * tol;
+  const double tol_range = 0.05 * tol;  // per-sample residual of the range finder
+  const double tol_trunc = 0.9 * tol;   // Frobenius norm of the discarded block
+  const int nt = h->nt;
+  HqrTask* hq_fy = h->hq_h;           // factor Y (synchronised per round)
+  HqrTask* hq_ay = h->hq_h + nt;      // Q1 = Q_y [I; 0]
+  HqrTask* hq_fb = h->hq_h + 2 * nt;  // factor B^T
+  HqrTask* hq_ab = h->hq_h + 3 * nt;  // V~ = Q_b [Q_r; 0]
   std::vector<char> dense(T, 0);
   std::vector<int> sz(T), t1(T, 0), todo;
   for (int t = 0; t < T; ++t) {
@@ -403,9 +416,8 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     sz[t] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred[t] + 16)));
     todo.push_back(t);
   }
-  // 1-2. sketch Y = C Omega and orthonormal range basis Q1 by pivoted QR; a
-  // tile whose samples are not exhausted (fewer than 8 unused columns) is
-  // sketched again, alone, twice as wide
+  // 1-2. sketch and range rank; a tile with fewer than 8 samples beyond its
+  // rank estimate is sketched again, alone, twice as wide
   bool first = true;
   while (!todo.empty()) {
     int swide = 0;
@@ -446,22 +458,20 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     }
     for (int q = 0; q < cnt; ++q) {
       const int t = todo[q];
-      QrcpTask& tk = h->tk_h[q];
-      tk = QrcpTask{};
-      tk.Y = h->Ybuf + (int64_t)t * nb;
-      tk.ldy = h->n;
+      HqrTask& tk = hq_fy[q];
+      tk = HqrTask{};
+      tk.A = h->Ybuf + (int64_t)t * nb;
+      tk.lda = h->n;
       tk.m = tile_rows(h, i_first + t);
-      tk.q = sz[t];
-      tk.tol = tol_range * std::sqrt((double)sz[t]);
-      tk.max_rank = sz[t];
+      tk.s = sz[t];
+      tk.T = h->Tw + (int64_t)t * h->tw_stride;
+      tk.tol = tol_range;
       tk.min_tail = 8;
-      tk.Q = h->Q1 + (int64_t)t * nb;
-      tk.ldq = h->n;
       tk.rank = h->qr_d + t;
       tk.flag = h->qr_d + h->nt + t;
     }
-    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, cnt * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_qrcp(h->tk_d, cnt, h->s));
+    HIPCHK(hipMemcpyAsync(h->hq_d, hq_fy, cnt * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
     sync(h);
@@ -472,7 +482,7 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       const int t = todo[q];
       t1[t] = h->qr_h[t];
       const double m = tile_rows(h, i_first + t);
-      cflops += 2.0 * m * sz[t] * ncols + 4.0 * m * sz[t] * t1[t] + 2.0 * m * t1[t] * t1[t];
+      cflops += 2.0 * m * sz[t] * ncols + 2.0 * m * sz[t] * sz[t];
       if (h->qr_h[h->nt + t]) {
         if (sz[t] >= h->smax) {
           if (h->strict) {
@@ -492,12 +502,30 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     todo.swap(next);
     first = false;
   }
-  std::vector<int> lr;  // tiles still headed for a low-rank form
+  std::vector<int> lr;  // tiles still headed for a low-rank form, t1 > 0
   for (int t = 0; t < T; ++t)
-    if (!dense[t]) lr.push_back(t);
+    if (!dense[t] && t1[t] > 0) lr.push_back(t);
   const int L = (int)lr.size();
   std::vector<int> k2(T, 0);
   if (L > 0) {
+    // Q1 = Q_y [I_t1; 0]
+    for (int q = 0; q < L; ++q) {
+      const int t = lr[q];
+      HqrTask& tk = hq_ay[q];
+      tk = HqrTask{};
+      tk.A = h->Ybuf + (int64_t)t * nb;
+      tk.lda = h->n;
+      tk.m = tile_rows(h, i_first + t);
+      tk.s = sz[t];
+      tk.T = h->Tw + (int64_t)t * h->tw_stride;
+      tk.X = h->Q1 + (int64_t)t * nb;
+      tk.ldx = h->n;
+      tk.kx = t1[t];
+      tk.identity = 1;
+      cflops += 2.0 * tk.m * t1[t] * t1[t];
+    }
+    HIPCHK(hipMemcpyAsync(h->hq_d + nt, hq_ay, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_apply(h->hq_d + nt, L, h->s));
     meta_reserve(h, 3 * (int64_t)L, 3 * (int64_t)L);
     // 3. project: Bt_t = C_t^T Q1_t (ncols x t1)
     int *m_d, *n_d, *k_d;
@@ -512,12 +540,13 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     for (int q = 0; q < L; ++q) {
       const int t = lr[q];
       m_h[q] = ncols;
-      n_h[q] = std::max(1, t1[t]);
+      n_h[q] = t1[t];
       k_h[q] = tile_rows(h, i_first + t);
       a_h[q] = (int64_t)t * nb;                       // row offset of tile t in src (contigT frame)
       b_h[q] = (int64_t)t * nb;                       // Q1 rows
       c_h[q] = (int64_t)t * nb * h->smax;             // Bt block
       maxn = std::max(maxn, n_h[q]);
+      cflops += 2.0 * ncols * t1[t] * k_h[q];
     }
     im_push(h, m_h, m_d, 3 * (int64_t)L);
     lm_push(h, a_h, a_d, 3 * (int64_t)L);
@@ -530,14 +559,34 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       bt.count = L; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
       gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
     }
-    // 4. truncation by pivoted QR of Bt: V~ = Q2[:, :k], Z = Pi R2[:k, :]^T
+    // 4. B^T = Q_b R_b
     for (int q = 0; q < L; ++q) {
       const int t = lr[q];
-      QrcpTask& tk = h->tk_h[q];
-      tk = QrcpTask{};
-      tk.Y = h->Bt + (int64_t)t * nb * h->smax;
-      tk.ldy = nb;
+      HqrTask& tk = hq_fb[q];
+      tk = HqrTask{};
+      tk.A = h->Bt + (int64_t)t * nb * h->smax;
+      tk.lda = nb;
       tk.m = ncols;
+      tk.s = t1[t];
+      tk.T = h->Tw + (int64_t)t * h->tw_stride;
+      cflops += 2.0 * ncols * t1[t] * t1[t];
+    }
+    HIPCHK(hipMemcpyAsync(h->hq_d + 2 * nt, hq_fb, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_factor(h->hq_d + 2 * nt, L, h->s));
+    // 5. truncation by pivoted QR of R_b (t1 x t1): Q_r into vt, Z = Pi R_r[:k, :]^T.
+    // Small factors stay in registers; larger ones are copied out and pivoted
+    // in place (reflectors in the Y workspace, which Q1 no longer needs).
+    std::vector<int> big;
+    int nsmall = 0;
+    for (int q = 0; q < L; ++q)
+      if (t1[lr[q]] <= kRegQrMax) ++nsmall;
+    int qs = 0, qb = nsmall;
+    for (int q = 0; q < L; ++q) {
+      const int t = lr[q];
+      const bool small = t1[t] <= kRegQrMax;
+      QrcpTask& tk = h->tk_h[small ? qs++ : qb++];
+      tk = QrcpTask{};
+      tk.m = t1[t];
       tk.q = t1[t];
       tk.tol = tol_trunc;
       tk.max_rank = maxrank + 1;
@@ -548,9 +597,41 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       tk.ldz = h->smax;
       tk.rank = h->qr_d + t;
       tk.flag = h->qr_d + h->nt + t;
+      if (small) {
+        tk.Y = h->Bt + (int64_t)t * nb * h->smax;
+        tk.ldy = nb;
+        tk.upper = 1;
+        tk.W = h->Ybuf + (int64_t)t * nb;
+        tk.ldw = h->n;
+      } else {
+        tk.Y = h->Ybuf + (int64_t)t * nb;
+        tk.ldy = h->n;
+        big.push_back(t);
+      }
+      cflops += 4.0 * t1[t] * t1[t] * t1[t] / 3.0;
+    }
+    if (!big.empty()) {
+      const int nbg = (int)big.size();
+      meta_reserve(h, nbg, 2 * (int64_t)nbg);
+      int* nn_d;
+      int* nn_h = im_take(h, nbg, &nn_d);
+      int64_t *so_d, *do_d;
+      int64_t* so_h = lm_take(h, nbg, &so_d);
+      int64_t* do_h = lm_take(h, nbg, &do_d);
+      int nmax = 0;
+      for (int q = 0; q < nbg; ++q) {
+        nn_h[q] = t1[big[q]];
+        so_h[q] = (int64_t)big[q] * nb * h->smax;
+        do_h[q] = (int64_t)big[q] * nb;
+        nmax = std::max(nmax, nn_h[q]);
+      }
+      im_push(h, nn_h, nn_d, nbg);
+      lm_push(h, so_h, so_d, 2 * (int64_t)nbg);
+      HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, h->n, do_d, nn_d, nmax, nbg, h->s));
     }
     HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_qrcp(h->tk_d, L, h->s));
+    HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
+    HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
     sync(h);
     meta_reset(h);
@@ -558,8 +639,7 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       const int t = lr[q];
       k2[t] = h->qr_h[t];
       const double m = tile_rows(h, i_first + t);
-      cflops += 2.0 * ncols * t1[t] * m + 4.0 * ncols * t1[t] * k2[t] + 2.0 * ncols * k2[t] * k2[t] +
-                2.0 * m * t1[t] * k2[t];
+      cflops += 4.0 * ncols * t1[t] * k2[t] + 2.0 * m * t1[t] * k2[t];
       if (k2[t] > maxrank) {
         if (h->strict) {
           h->bad_i = i_first + t;
@@ -588,9 +668,26 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       if (k2[t] > 0) ++nlr;
     }
   }
-  // 5. U_t = Q1_t Z_t  (m_t x k_t) for the low-rank tiles
+  // 6. V~ = Q_b [Q_r; 0] and U_t = Q1_t Z_t (m_t x k_t) for the low-rank tiles
   meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
   if (nlr > 0) {
+    int q = 0;
+    for (int t = 0; t < T; ++t) {
+      if (dense[t] || k2[t] == 0) continue;
+      HqrTask& tk = hq_ab[q++];
+      tk = HqrTask{};
+      tk.A = h->Bt + (int64_t)t * nb * h->smax;
+      tk.lda = nb;
+      tk.m = ncols;
+      tk.s = t1[t];
+      tk.T = h->Tw + (int64_t)t * h->tw_stride;
+      tk.X = vt + (int64_t)t * h->vslot;
+      tk.ldx = nb;
+      tk.kx = k2[t];
+      tk.xrows = t1[t];
+    }
+    HIPCHK(hipMemcpyAsync(h->hq_d + 3 * nt, hq_ab, nlr * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_apply(h->hq_d + 3 * nt, nlr, h->s));
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, nlr, &m_d);
     int* n_h = im_take(h, nlr, &n_d);
@@ -599,7 +696,8 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     int64_t* a_h = lm_take(h, nlr, &a_d);
     int64_t* b_h = lm_take(h, nlr, &b_d);
     int64_t* c_h = lm_take(h, nlr, &c_d);
-    int maxm = 1, q = 0;
+    int maxm = 1;
+    q = 0;
     for (int t = 0; t < T; ++t) {
       if (dense[t] || k2[t] == 0) continue;
       m_h[q] = tile_rows(h, i_first + t);
@@ -1333,6 +1431,10 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->tk_cap = (int)nt;
       h->tk_d = dalloc<QrcpTask>(h, nt);
       h->tk_h = halloc<QrcpTask>(h, nt);
+      h->hq_d = dalloc<HqrTask>(h, 4 * nt);
+      h->hq_h = halloc<HqrTask>(h, 4 * nt);
+      h->tw_stride = (int64_t)((h->smax + 15) / 16) * 256;
+      h->Tw = dalloc<double>(h, nt * h->tw_stride);
       h->qr_d = dalloc<int>(h, 2 * nt);
       h->qr_h = halloc<int>(h, 2 * nt);
       HIPCHK(launch_gaussian(h->omega, nb * h->smax, (uint32_t)o->seed, h->s));

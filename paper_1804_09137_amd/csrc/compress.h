@@ -23,9 +23,39 @@ struct QrcpTask {
   int64_t ldz;
   int* rank;
   int* flag;
+  int upper;       // qrcp_reg: read only the upper triangle of Y (zeros below)
+  double* W;       // qrcp_reg: m x rank workspace for the reflectors (ldw)
+  int64_t ldw;
+};
+
+// Register-resident pivoted QR (qrcp_reg_kernel) limit on rows and columns.
+constexpr int kRegQrMax = 192;
+
+// Blocked Householder QR (hqr_factor_kernel) of the m x s matrix A (lda), in
+// place, m <= kQrMaxRows, s <= kQrMaxCols; and the application of its Q
+// (hqr_apply_kernel) to X (m x kx, ldx).
+struct HqrTask {
+  double* A;
+  int64_t lda;
+  int m, s;
+  double* T;        // ceil(min(m, s) / 16) compact-WY factors, 256 doubles each
+  double tol;       // factor: > 0 selects the range rank (rank, flag)
+  int min_tail;
+  int* rank;
+  int* flag;
+  double* X;        // apply: X <- Q X
+  int64_t ldx;
+  int kx;
+  int xrows;        // apply (identity == 0): rows >= xrows of X are cleared first
+  int identity;     // apply: X starts as [I_kx; 0]
 };
 
 hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s);
+hipError_t launch_qrcp_reg(const QrcpTask* d_tasks, int count, hipStream_t s);
+hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
+hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s);
+hipError_t launch_copy_upper(const double* src, int64_t sld, const int64_t* soff, double* dst, int64_t dld,
+                             const int64_t* doff, const int* nn, int nmax, int count, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint32_t seed, hipStream_t s);
 hipError_t launch_batched_copy(const double* src, int64_t sld, const int64_t* soff, double* dst, int64_t dld,
                                const int64_t* doff, const int* mrows, const int* kcols, int64_t max_elems,

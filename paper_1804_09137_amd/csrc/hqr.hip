@@ -1,0 +1,710 @@
+// Blocked Householder QR of tall tiles and a register-resident column-pivoted
+// QR of the small triangular factors they produce.  Together they replace a
+// pivoted QR of the tall sketch (whose every pivot step streams the whole
+// matrix) in the randomized compression of Section V:
+//
+//   Y = C Omega = Q_y R_y              hqr_factor (unpivoted, blocked)
+//   rank t1 from R_y's column tails    hqr_factor (posterior range estimate)
+//   Q1 = Q_y [I_t1; 0]                 hqr_apply
+//   B^T = C^T Q1 = Q_b R_b             hqr_factor
+//   R_b Pi = Q_r R_r, truncated at k   qrcp_reg (pivoting on a t1 x t1 matrix)
+//   V~ = Q_b [Q_r; 0],  U = Q1 Pi R_r[:k,:]^T
+//
+// Column pivoting is invariant under the orthogonal factor, so pivoting R_b
+// selects what pivoting B^T would.
+//
+// hqr_factor: one 512-thread workgroup per matrix (m <= 1024 rows).  Panels of
+// 16 columns are factored in registers (two barriers per column); the
+// compact-WY factor T (Schreiber-Van Loan: Q_p = I - V T V^T) is built from
+// the Gram matrix V^T V; the trailing columns are updated 16 at a time as
+// A -= V (T^T (V^T A)), both products on v_mfma_f64_16x16x4f64, the K = rows
+// reduction of V^T A split over the 8 waves, the panel V resident in LDS.
+//
+// MFMA lane layout (measured on gfx950): D = X Y + C with X[i][k] in lane
+// i + 16k, Y[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i mod 4),
+// register i / 4.
+#include "kernels.h"
+#include "compress.h"
+
+namespace tlrk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int NT = 512;                 // threads per workgroup
+constexpr int NW = NT / 64;             // wave64s
+constexpr int PB = 16;                  // panel width
+constexpr int LDP = kQrMaxRows + 2;     // LDS panel stride (2 mod 32 doubles: conflict-free fragments)
+constexpr int MB = kQrMaxRows / (NW * 16);   // 16-row blocks per wave
+constexpr int RS = 16 * 17;             // per-wave slot of `red`: a 16 x 17 tile or a 16 x 16 partial
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reduces N (16 or 32) per-lane partial sums over the wave: halving steps
+// exchange half of the remaining entries with lane ^ OFF (OFF = 32, 16, ...),
+// then the last steps add across the remaining lanes.  Lane l ends with the
+// total of entry (l >> (6 - log2 N)) & (N - 1).  Fewer shuffles than N
+// separate reductions; every index is a compile-time constant, so the array
+// stays in registers.
+template <int HALF, int OFF>
+struct BflyStep {
+  template <int N>
+  __device__ static void run(double (&v)[N], int lane) {
+    const bool hi = (lane & OFF) != 0;
+#pragma unroll
+    for (int i = 0; i < HALF; ++i) {
+      const double keep = hi ? v[i + HALF] : v[i];
+      const double send = hi ? v[i] : v[i + HALF];
+      v[i] = keep + __shfl_xor(send, OFF, 64);
+    }
+    BflyStep<HALF / 2, OFF / 2>::run(v, lane);
+  }
+};
+template <int OFF>
+struct BflyStep<0, OFF> {
+  template <int N>
+  __device__ static void run(double (&)[N], int) {}
+};
+
+template <int N>
+__device__ inline double bfly(double (&v)[N], int lane) {
+  static_assert(N == 16 || N == 32, "bfly: N must be 16 or 32");
+  BflyStep<N / 2, 32>::run(v, lane);
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 / N; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+__device__ inline d4 mfma(double x, double y, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
+
+// Householder vector entry V[r][c] of panel c0 (unit lower trapezoidal).
+__device__ inline double vval_lds(const double* P, int r, int c, int mm, bool live) {
+  if (!live || r >= mm || r < c) return 0.0;
+  return r == c ? 1.0 : P[c * LDP + r];
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One trailing-update round on the 16 columns col0.. of M (rows c0.., mm of
+// them; ncol columns in all): M -= V op(T) (V^T M), op(T) = T^T (applying
+// Q^T) or T (applying Q).  vx: this wave's V fragments in the X-layout of
+// V^T M (registers); the Y-layout fragments of V W' are read from the panel P
+// in LDS.  Each wave reads its rows of the chunk once, coalesced, into
+// registers (the D-layout of the update product) and transposes them block by
+// block through a wave-private 16 x 17 LDS tile (its slot of `red`) for
+// V^T M.  Three barriers.
+template <bool TRANS>
+__device__ inline void wy_update(double* M, int64_t ldm, int c0, int mm, int col0, int ncol, int rb, int nblk,
+                                 const double (&vx)[MB][4], const double* P, int nlive, double* red, double* Wf,
+                                 double* Wp, const double* Ts, int tid, int lane, int w) {
+  double* tile = red + w * RS;   // 16 x 17 transpose tile; later this wave's partial W
+  d4 cd[MB];
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int row = rb + 16 * b + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = col0 + 4 * r + (lane >> 4);
+      cd[b][r] = (b < nblk && row < mm && col < ncol) ? M[(int64_t)col * ldm + c0 + row] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    if (b < nblk) {
+      // D-layout (row lane & 15, column 4r + (lane >> 4)) -> tile[col * 17 + row]
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tile[(4 * r + (lane >> 4)) * 17 + (lane & 15)] = cd[b][r];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = mfma(vx[b][q], tile[(lane & 15) * 17 + 4 * q + (lane >> 4)], acc);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) tile[(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  if (tid < 256) {
+    double sacc = 0.0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) sacc += red[v * RS + tid];
+    Wf[tid] = sacc;   // W[i][j], i = panel column, j = column col0 + j
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int k = tid >> 4, j = tid & 15;
+    double sacc = 0.0;
+    if (TRANS) {
+#pragma unroll
+      for (int l = 0; l < 16; ++l)
+        if (l <= k) sacc += Ts[l * 16 + k] * Wf[l * 16 + j];
+    } else {
+#pragma unroll
+      for (int l = 0; l < 16; ++l)
+        if (l >= k) sacc += Ts[k * 16 + l] * Wf[l * 16 + j];
+    }
+    Wp[tid] = sacc;
+  }
+  __syncthreads();
+  double xw[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) xw[q] = -Wp[(4 * q + (lane >> 4)) * 16 + (lane & 15)];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    if (b < nblk) {
+      const int row = rb + 16 * b + (lane & 15);
+      d4 c = cd[b];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cy = 4 * q + (lane >> 4);
+        c = mfma(xw[q], vval_lds(P, row, cy, mm, cy < nlive), c);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = col0 + 4 * r + (lane >> 4);
+        if (row < mm && col < ncol) M[(int64_t)col * ldm + c0 + row] = c[r];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// A = Q R in place: R in the upper triangle, the Householder vectors (unit
+// diagonal implied) below it, T factors per panel in tk.T.  With tk.tol > 0
+// also the range rank t1 = max_i t_i, t_i the first row from which column i's
+// tail norm ||R[t:, i]|| stays <= tol: for t >= t1 every sample y_i with
+// i >= t is reproduced by Q_y[:, :t] to within tol (a posteriori estimate of
+// ||(I - Q Q^T) C||, Halko-Martinsson-Tropp).  flag = 1 when fewer than
+// min_tail samples back that estimate (and t1 < m).
+//
+// The panel is factored in registers (thread: rows tid, tid + 512); per
+// column one norm reduction and one batched reduction of the 15 reflector
+// products, each finished across waves through 8 LDS partials.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restrict__ tasks) {
+  const HqrTask tk = tasks[blockIdx.x];
+  __shared__ double P[PB * LDP];   // the panel
+  __shared__ double red[NW * RS];
+  __shared__ double Wf[256], Wp[256], Ts[256];
+  __shared__ double taus[PB];
+  __shared__ double nred[NW];
+  __shared__ double dred[NW * PB];
+  __shared__ double sh_alpha;
+  __shared__ int sh_t1;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m = tk.m, s = tk.s;
+  if (m <= 0 || s <= 0) {
+    if (tid == 0) {
+      if (tk.rank) *tk.rank = 0;
+      if (tk.flag) *tk.flag = 0;
+    }
+    return;
+  }
+  double* A = tk.A;
+  const int64_t lda = tk.lda;
+  const int nref = m < s ? m : s;
+  const int np = (nref + PB - 1) / PB;
+  const int r0 = tid, r1 = tid + NT;
+
+  for (int p = 0; p < np; ++p) {
+    const int c0 = p * PB;
+    const int mm = m - c0;
+    const int pw = (s - c0) < PB ? (s - c0) : PB;
+    // 1. panel -> registers
+    double a0[PB], a1[PB];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      const double* ac = A + (int64_t)(c0 + c) * lda + c0;
+      a0[c] = (c < pw && r0 < mm) ? ac[r0] : 0.0;
+      a1[c] = (c < pw && r1 < mm) ? ac[r1] : 0.0;
+    }
+    // 2. factor the panel
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      if (c0 + c < nref) {
+        const double x0 = a0[c], x1 = a1[c];
+        double sq = (r0 > c ? x0 * x0 : 0.0) + x1 * x1;
+        sq = wave_sum(sq);
+        if (lane == 0) nred[w] = sq;
+        if (tid == c) sh_alpha = x0;
+        __syncthreads();
+        double sig = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) sig += nred[v];
+        const double alpha = sh_alpha;
+        double ta, beta, sc;
+        if (sig == 0.0) {
+          ta = 0.0; beta = alpha; sc = 0.0;
+        } else {
+          const double nx = sqrt(alpha * alpha + sig);
+          beta = alpha >= 0.0 ? -nx : nx;
+          ta = (beta - alpha) / beta;
+          sc = 1.0 / (alpha - beta);
+        }
+        const double v0 = (r0 > c) ? x0 * sc : (r0 == c ? 1.0 : 0.0);
+        const double v1 = x1 * sc;
+        a0[c] = (r0 == c) ? beta : (r0 > c ? v0 : x0);
+        a1[c] = v1;
+        if (tid == 0) taus[c] = ta;
+        if (c + 1 < PB) {
+          double part[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) part[k] = (k > c) ? v0 * a0[k] + v1 * a1[k] : 0.0;
+          const double tot = bfly<16>(part, lane);
+          if ((lane & 3) == 0) dred[w * PB + ((lane >> 2) & 15)] = tot;
+          __syncthreads();
+          double d = 0.0;
+#pragma unroll
+          for (int v = 0; v < NW; ++v) d += dred[v * PB + (lane & 15)];
+          d *= ta;
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (k > c) {
+              const double dk = readlane_d(d, k);
+              a0[k] -= dk * v0;
+              a1[k] -= dk * v1;
+            }
+        }
+      } else if (tid == 0) {
+        taus[c] = 0.0;
+      }
+    }
+    // 3. panel -> LDS and A (R above and on the diagonal, reflectors below)
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      if (r0 < mm) P[c * LDP + r0] = a0[c];
+      if (r1 < mm) P[c * LDP + r1] = a1[c];
+      double* ac = A + (int64_t)(c0 + c) * lda + c0;
+      if (c < pw && r0 < mm) ac[r0] = a0[c];
+      if (c < pw && r1 < mm) ac[r1] = a1[c];
+    }
+    __syncthreads();
+    // 4. V fragments and the Gram matrix G = V^T V
+    const int rw = ((mm + NW * 16 - 1) / (NW * 16)) * 16;
+    const int nblk = rw / 16;
+    const int rb = w * rw;
+    const int nlive = nref - c0;
+    double vx[MB][4];
+    d4 g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cx = lane & 15;
+        vx[b][q] = (b < nblk) ? vval_lds(P, rb + 16 * b + 4 * q + (lane >> 4), cx, mm, cx < nlive) : 0.0;
+        if (b < nblk) g = mfma(vx[b][q], vx[b][q], g);
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w * RS + (4 * r + (lane >> 4)) * 16 + (lane & 15)] = g[r];
+    __syncthreads();
+    if (tid < 256) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) sacc += red[v * RS + tid];
+      Wf[tid] = sacc;
+    }
+    __syncthreads();
+    // T (upper triangular): T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+    if (w == 0 && lane < 16) {
+      double tr[16] = {};
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < 16; ++l)
+          if (l < i && l >= lane) acc += tr[l] * Wf[l * 16 + i];
+        const double ti = taus[i];
+        tr[i] = (lane < i) ? -ti * acc : (lane == i ? ti : 0.0);
+      }
+#pragma unroll
+      for (int l = 0; l < 16; ++l) {
+        Ts[lane * 16 + l] = tr[l];
+        tk.T[(int64_t)p * 256 + lane * 16 + l] = tr[l];
+      }
+    }
+    __syncthreads();
+    // 5. trailing columns: A -= V T^T V^T A
+    for (int col0 = c0 + PB; col0 < s; col0 += PB)
+      wy_update<true>(A, lda, c0, mm, col0, s, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
+    __syncthreads();
+  }
+
+  if (tk.tol > 0.0) {
+    if (tid == 0) sh_t1 = 0;
+    __syncthreads();
+    const double tol2 = tk.tol * tk.tol;
+    for (int i = tid; i < s; i += NT) {
+      const int top = i < m - 1 ? i : m - 1;
+      const double* ci = A + (int64_t)i * lda;
+      double acc = 0.0;
+      int ti = top + 1;
+      for (int l = top; l >= 0; --l) {
+        acc += ci[l] * ci[l];
+        if (acc > tol2) break;
+        ti = l;
+      }
+      atomicMax(&sh_t1, ti);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int t1 = sh_t1;
+      if (tk.rank) *tk.rank = t1;
+      if (tk.flag) *tk.flag = (t1 < m && s - t1 < tk.min_tail) ? 1 : 0;
+    }
+  } else if (tid == 0) {
+    if (tk.rank) *tk.rank = nref;
+    if (tk.flag) *tk.flag = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X <- Q X with Q = H_1 ... H_np from hqr_factor (X: m x kx, ldx).  identity:
+// X starts as [I_kx; 0] (then only columns >= c0 change in panel c0);
+// otherwise rows >= xrows of X are cleared first.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict__ tasks) {
+  const HqrTask tk = tasks[blockIdx.x];
+  __shared__ double P[PB * LDP];
+  __shared__ double red[NW * RS];
+  __shared__ double Wf[256], Wp[256], Ts[256];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m = tk.m, s = tk.s, kx = tk.kx;
+  if (m <= 0 || kx <= 0) return;
+  double* X = tk.X;
+  const int64_t ldx = tk.ldx;
+  const double* A = tk.A;
+  const int64_t lda = tk.lda;
+  if (tk.identity) {
+    for (int c = 0; c < kx; ++c)
+      for (int r = tid; r < m; r += NT) X[(int64_t)c * ldx + r] = (r == c) ? 1.0 : 0.0;
+  } else {
+    const int rz = tk.xrows < 0 ? 0 : tk.xrows;
+    for (int c = 0; c < kx; ++c)
+      for (int r = rz + tid; r < m; r += NT) X[(int64_t)c * ldx + r] = 0.0;
+  }
+  const int nref = m < s ? m : s;
+  const int np = (nref + PB - 1) / PB;
+  for (int p = np - 1; p >= 0; --p) {
+    const int c0 = p * PB;
+    if (tk.identity && c0 >= kx) continue;
+    const int mm = m - c0;
+    const int nlive = nref - c0;
+    __syncthreads();   // previous panel done with P, Ts and X
+    if (tid < 256) Ts[tid] = tk.T[(int64_t)p * 256 + tid];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      const double* ac = A + (int64_t)(c0 + c) * lda + c0;
+      for (int r = tid; r < mm; r += NT) P[c * LDP + r] = (c < nlive) ? ac[r] : 0.0;
+    }
+    __syncthreads();
+    const int rw = ((mm + NW * 16 - 1) / (NW * 16)) * 16;
+    const int nblk = rw / 16;
+    const int rb = w * rw;
+    double vx[MB][4];
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cx = lane & 15;
+        vx[b][q] = (b < nblk) ? vval_lds(P, rb + 16 * b + 4 * q + (lane >> 4), cx, mm, cx < nlive) : 0.0;
+      }
+    for (int col0 = tk.identity ? c0 : 0; col0 < kx; col0 += PB)
+      wy_update<false>(X, ldx, c0, mm, col0, kx, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column-pivoted Householder QR of a small matrix (m, q <= kRegQrMax) held in
+// registers: wave w owns columns w + 8j, lane l rows l + 64i.  Same stopping
+// rule and outputs as qrcp_kernel (rank, Z, explicit Q), reading Y (only its
+// upper triangle when tk.upper) and writing reflectors to the workspace W.
+// Each step: the pivot column's wave forms the reflector (one barrier), every
+// wave reflects its live columns and recomputes their norms with two batched
+// wave reductions (one barrier).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int RI = kRegQrMax / 64;   // row slots per lane
+constexpr int RJ = kRegQrMax / NW;   // column slots per wave
+static_assert(RJ <= 32, "column slots must fit two 16-entry butterflies");
+}  // namespace
+
+__global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict__ tasks) {
+  const QrcpTask tk = tasks[blockIdx.x];
+  __shared__ double vs[kRegQrMax];
+  __shared__ double taus[kRegQrMax];
+  __shared__ int step_of[kRegQrMax];
+  __shared__ double wsum[NW], wmax[NW];
+  __shared__ int widx[NW];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m = tk.m, q = tk.q;
+  if (m <= 0 || q <= 0) {
+    if (tid == 0) {
+      if (tk.rank) *tk.rank = 0;
+      if (tk.flag) *tk.flag = 0;
+    }
+    return;
+  }
+  if (m > kRegQrMax || q > kRegQrMax) {   // the host routes these to qrcp_kernel
+    if (tid == 0) {
+      if (tk.rank) *tk.rank = 0;
+      if (tk.flag) *tk.flag = 1;
+    }
+    return;
+  }
+  const double* Y = tk.Y;
+  const int64_t ldy = tk.ldy;
+  double a[RJ][RI];
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) {
+    const int c = w + NW * j;
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int r = lane + 64 * i;
+      a[j][i] = (c < q && r < m && (!tk.upper || r <= c)) ? Y[(int64_t)c * ldy + r] : 0.0;
+    }
+  }
+  for (int c = tid; c < kRegQrMax; c += NT) step_of[c] = 0x7fffffff;
+  uint32_t done = 0;   // bit j: column w + 8j already pivoted
+
+  // Sums over the wave of per-column partials f(j), j < RJ, in two 16-entry
+  // butterflies: lanes with (lane & 3) == 0 end with the totals of columns
+  // slot e and 16 + e, e = (lane >> 2) & 15.
+  auto reduce_cols = [&](auto f, double& lo, double& hi) {
+    double part[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) part[j] = (j < RJ) ? f(j) : 0.0;
+    lo = bfly<16>(part, lane);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) part[j] = (16 + j < RJ) ? f(16 + j) : 0.0;
+    hi = bfly<16>(part, lane);
+  };
+  // per-wave norm statistics of the live columns over rows > t (t = -1: all)
+  auto norms = [&](int t) {
+    double lo, hi;
+    reduce_cols([&](int j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < RI; ++i)
+        if (lane + 64 * i > t) acc += a[j][i] * a[j][i];
+      return acc;
+    }, lo, hi);
+    const int e = (lane >> 2) & 15;
+    double mv = -1.0, sv = 0.0;
+    int mi = 0x7fffffff;
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int es = e + 16 * h2;
+      const int ce = w + NW * es;
+      const double v = h2 ? hi : lo;
+      if ((lane & 3) == 0 && es < RJ && ce < q && !((done >> es) & 1u)) {
+        sv += v;
+        if (v > mv || (v == mv && ce < mi)) { mv = v; mi = ce; }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double om = __shfl_xor(mv, o, 64);
+      const int oi = __shfl_xor(mi, o, 64);
+      if (om > mv || (om == mv && oi < mi)) { mv = om; mi = oi; }
+      sv += __shfl_xor(sv, o, 64);
+    }
+    if (lane == 0) { wsum[w] = sv; wmax[w] = mv; widx[w] = mi; }
+  };
+  norms(-1);
+  __syncthreads();
+
+  const int tmax = m < q ? m : q;
+  const double tol2 = tk.tol * tk.tol;
+  int t = 0;
+  for (; t < tmax; ++t) {
+    double total = 0.0, best = -1.0;
+    int p = 0x7fffffff;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      total += wsum[v];
+      if (wmax[v] > best || (wmax[v] == best && widx[v] < p)) { best = wmax[v]; p = widx[v]; }
+    }
+    if (total <= tol2 || t >= tk.max_rank || p >= q) break;
+    const int pw = p % NW, pj = p / NW;
+    if (w == pw) {
+      double x[RI];
+#pragma unroll
+      for (int i = 0; i < RI; ++i) {
+        x[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < RJ; ++j)
+          if (j == pj) x[i] = a[j][i];
+      }
+      double sq = 0.0;
+#pragma unroll
+      for (int i = 0; i < RI; ++i)
+        if (lane + 64 * i > t) sq += x[i] * x[i];
+      sq = wave_sum(sq);
+      double xs = x[0];
+#pragma unroll
+      for (int i = 1; i < RI; ++i)
+        if ((t >> 6) == i) xs = x[i];
+      const double alpha = __shfl(xs, t & 63, 64);
+      double ta, beta, sc;
+      if (sq == 0.0) {
+        ta = 0.0; beta = alpha; sc = 0.0;
+      } else {
+        const double nx = sqrt(alpha * alpha + sq);
+        beta = alpha >= 0.0 ? -nx : nx;
+        ta = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < RI; ++i) {
+        const int r = lane + 64 * i;
+        const double v = (r > t) ? x[i] * sc : (r == t ? 1.0 : 0.0);
+        vs[r] = v;
+        const double nv = (r == t) ? beta : (r > t ? v : x[i]);
+#pragma unroll
+        for (int j = 0; j < RJ; ++j)
+          if (j == pj) a[j][i] = nv;
+      }
+      if (lane == 0) { taus[t] = ta; step_of[p] = t; }
+    }
+    done |= (pw == w) ? (1u << pj) : 0u;
+    __syncthreads();
+    const double ta = taus[t];
+    double vv[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) vv[i] = vs[lane + 64 * i];
+    double lo, hi;
+    reduce_cols([&](int j) {
+      double acc = 0.0;
+      if (!((done >> j) & 1u)) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i) acc += vv[i] * a[j][i];
+      }
+      return acc;
+    }, lo, hi);
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const double d = ta * readlane_d(j < 16 ? lo : hi, 4 * (j & 15));
+#pragma unroll
+      for (int i = 0; i < RI; ++i) a[j][i] -= d * vv[i];
+    }
+    norms(t);
+    __syncthreads();
+  }
+  const int rank = t;
+  if (tid == 0) {
+    if (tk.rank) *tk.rank = rank;
+    if (tk.flag) *tk.flag = (q - rank < tk.min_tail) ? 1 : 0;
+  }
+  // Z[c, rr] = R[rr, step_of[c]]; reflector of step st -> W column st
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) {
+    const int c = w + NW * j;
+    if (c >= q) continue;
+    const int st = step_of[c];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int r = lane + 64 * i;
+      if (tk.Z && r < rank) tk.Z[(int64_t)r * tk.ldz + c] = (st >= r) ? a[j][i] : 0.0;
+      if (st < rank && r < m) tk.W[(int64_t)st * tk.ldw + r] = (r > st) ? a[j][i] : 0.0;
+    }
+  }
+  if (!tk.Q || rank == 0) return;
+  __syncthreads();
+  // explicit Q = H_0 ... H_{rank-1} [I; 0]: column c still equals e_c before
+  // step st <= c is applied, so step st only touches columns >= st
+  double qa[RJ][RI];
+#pragma unroll
+  for (int j = 0; j < RJ; ++j)
+#pragma unroll
+    for (int i = 0; i < RI; ++i) qa[j][i] = (lane + 64 * i == w + NW * j) ? 1.0 : 0.0;
+  for (int st = rank - 1; st >= 0; --st) {
+    const double ta = taus[st];
+    double vv[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int r = lane + 64 * i;
+      vv[i] = (r == st) ? 1.0 : ((r > st && r < m) ? tk.W[(int64_t)st * tk.ldw + r] : 0.0);
+    }
+    double lo, hi;
+    reduce_cols([&](int j) {
+      double acc = 0.0;
+      const int c = w + NW * j;
+      if (c >= st && c < rank) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i) acc += vv[i] * qa[j][i];
+      }
+      return acc;
+    }, lo, hi);
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const double d = ta * readlane_d(j < 16 ? lo : hi, 4 * (j & 15));
+#pragma unroll
+      for (int i = 0; i < RI; ++i) qa[j][i] -= d * vv[i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) {
+    const int c = w + NW * j;
+    if (c >= rank) continue;
+#pragma unroll
+    for (int i = 0; i < RI; ++i) {
+      const int r = lane + 64 * i;
+      if (r < m) tk.Q[(int64_t)c * tk.ldq + r] = qa[j][i];
+    }
+  }
+}
+
+// Upper-triangular copy (zeros below the diagonal) of rows/cols [0, n_b) of
+// batched square blocks; grid.y = batch.
+__global__ void copy_upper_kernel(const double* __restrict__ src, int64_t sld, const int64_t* __restrict__ soff,
+                                  double* __restrict__ dst, int64_t dld, const int64_t* __restrict__ doff,
+                                  const int* __restrict__ nn) {
+  const int b = blockIdx.y;
+  const int n = nn[b];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int64_t r = e % n, c = e / n;
+  dst[doff[b] + c * dld + r] = (r <= c) ? src[soff[b] + c * sld + r] : 0.0;
+}
+
+hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hqr_factor_kernel, dim3((unsigned)count), dim3(NT), 0, s, d_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)count), dim3(NT), 0, s, d_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_qrcp_reg(const QrcpTask* d_tasks, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(qrcp_reg_kernel, dim3((unsigned)count), dim3(NT), 0, s, d_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_upper(const double* src, int64_t sld, const int64_t* soff, double* dst, int64_t dld,
+                             const int64_t* doff, const int* nn, int nmax, int count, hipStream_t s) {
+  if (count <= 0 || nmax <= 0) return hipSuccess;
+  const int64_t tot = (int64_t)nmax * nmax;
+  hipLaunchKernelGGL(copy_upper_kernel, dim3((unsigned)((tot + 255) / 256), (unsigned)count), dim3(256), 0, s, src,
+                     sld, soff, dst, dld, doff, nn);
+  return hipGetLastError();
+}
+
+}  // namespace tlrk
