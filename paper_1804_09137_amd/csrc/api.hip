@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -43,6 +44,8 @@ struct tlr_handle_s {
   int device = 0;
   int64_t n = 0;
   int nb = 0, nt = 0, maxrank = 0, smax = 0;
+  int gcap = 0;         // tile slots of the compression scratch
+  bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
   bool dense = false, grad = false, strict = false;
   int64_t slot = 0;      // doubles per low-rank slot (nb * maxrank)
   int64_t vslot = 0;     // doubles per V~ staging block (nb * (maxrank + 1)): the
@@ -80,6 +83,10 @@ struct tlr_handle_s {
   struct Family {
     int64_t u_base = 0, v_base = 0;      // arena offsets of the slot regions
     std::vector<int> rk;                 // nt*nt (i * nt + j)
+    std::vector<int> r1;                 // range-finder ranks (sketch width prediction)
+    std::vector<int> r1_prev, rk_prev;   // the previous factorisation's ranks, if hist
+    bool hist = false;
+    int done_kind = 0;                   // what the last finished pass computed: 1 factor, 2 compression of Sigma
     std::vector<int64_t> uoff, voff;     // arena offsets of U_ij, V_ij
     std::vector<char> isdense;
     int* rk_d = nullptr;
@@ -91,10 +98,10 @@ struct tlr_handle_s {
   double* col = nullptr;   // n x nb, ld n
   double* cold = nullptr;  // tangent column
   double* omega = nullptr; // nb x smax
-  double* Ybuf = nullptr;  // n x smax, ld n
-  double* Q1 = nullptr;    // n x smax, ld n
+  double* Ybuf = nullptr;  // nt blocks of nb x smax (ld nb): sketches, then small-QR workspace
+  double* Q1 = nullptr;    // nt blocks of nb x smax (ld nb): range bases
   double* Bt = nullptr;    // nt x (nb x smax)
-  double* Vtmp = nullptr;  // nt x vslot
+  double* Vtmp = nullptr;  // gcap x vslot: V~ of the tiles being compressed
   double* Ptmp = nullptr;  // nt x nb x nb (gradient: dL_jj V_ij products)
   double* Zb = nullptr;    // nt x (smax x maxrank)
   double* Wb = nullptr;
@@ -122,11 +129,11 @@ struct tlr_handle_s {
   QrcpTask* tk_d = nullptr;
   QrcpTask* tk_h = nullptr;
   int tk_cap = 0;
-  HqrTask* hq_d = nullptr;  // 4 x nt: one region per launch between synchronisations
+  HqrTask* hq_d = nullptr;  // 4 x gcap: one region per launch between synchronisations
   HqrTask* hq_h = nullptr;
   double* Tw = nullptr;     // nt x tw_stride compact-WY factors
   int64_t tw_stride = 0;
-  int* qr_d = nullptr;  // 2 * nt: ranks, flags
+  int* qr_d = nullptr;  // 2 * gcap: ranks, flags
   int* qr_h = nullptr;
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -333,8 +340,36 @@ int choose_splitk(const tlr_handle_s* h, int64_t M, int64_t N, int64_t K) {
   return (int)sk;
 }
 
+// mh / nh: host copies of a hinted batch's per-item M and N.  With them the
+// launch gets a flat list of the real tiles (one workgroup each) instead of
+// the launch maximum's tile grid per item.
 void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
-          const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false, int tm = 0, int tn = 0) {
+          const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false, int tm = 0, int tn = 0,
+          const int* mh = nullptr, const int* nh = nullptr) {
+  GemmBatch fb;
+  if (b && mh && nh && tm && tn) {
+    int64_t tot = 0;
+    for (int q = 0; q < b->count; ++q) tot += ((int64_t)mh[q] + tm - 1) / tm * (((int64_t)nh[q] + tn - 1) / tn);
+    if (tot == 0) return;
+    if (h->im_use + b->count + tot <= h->im_cap - h->im_cap / 4) {   // headroom for the caller's later takes
+      int* first_d;
+      int* first = im_take(h, b->count + tot, &first_d);
+      int* item = first + b->count;
+      int64_t acc = 0;
+      for (int q = 0; q < b->count; ++q) {
+        first[q] = (int)acc;
+        const int64_t t = ((int64_t)mh[q] + tm - 1) / tm * (((int64_t)nh[q] + tn - 1) / tn);
+        for (int64_t e = 0; e < t; ++e) item[acc + e] = q;
+        acc += t;
+      }
+      im_push(h, first, first_d, b->count + tot);
+      fb = *b;
+      fb.tile_first = first_d;
+      fb.tile_item = first_d + b->count;
+      fb.ntiles = tot;
+      b = &fb;
+    }
+  }
   int sk = 1;
   if (allow_split && !b) {
     int64_t K = 0;
@@ -351,8 +386,21 @@ using Family = tlr_handle_s::Family;
 
 inline size_t tid_of(const tlr_handle_s* h, int i, int j) { return (size_t)i * h->nt + j; }
 
-void family_reset(tlr_handle_s* h, Family& F) {
+// kind: 1 for a factorisation, 2 for the compression of Sigma.  When the
+// family's last finished pass was of the same kind, its ranks become the
+// predictions for this one (theta moves little between evaluations of an
+// optimisation); an interrupted pass leaves no history.
+void family_reset(tlr_handle_s* h, Family& F, int kind) {
+  if (F.done_kind == kind) {
+    F.r1_prev.swap(F.r1);
+    F.rk_prev = F.rk;
+    F.hist = true;
+  } else {
+    F.hist = false;
+  }
+  F.done_kind = 0;
   std::fill(F.rk.begin(), F.rk.end(), 0);
+  std::fill(F.r1.begin(), F.r1.end(), 0);
   std::fill(F.isdense.begin(), F.isdense.end(), 0);
   for (int i = 0; i < h->nt; ++i)
     for (int j = 0; j < i; ++j) {
@@ -379,49 +427,96 @@ void throw_if_not_spd(tlr_handle_s* h) {
   if (*h->h_info != ~0ull) throw Fail{TLR_ENOTSPD};
 }
 
+// Rank predictions for a column: final ranks and range-finder ranks.
+struct RankPred {
+  std::vector<int> k, r1;
+};
+
 // ---------------------------------------------------------------------------
-// Compression of the T tiles below the diagonal of column `col`, held densely
-// in src (ld); tile t is global tile i = i_first + t (rows t*nb .. of src).
-// Low-rank tiles: U written to F's slot, V~ (before the TRSM) to vt + t*slot,
-// F.rk = rank.  Tiles whose rank would exceed maxrank are copied to a dense
-// block: F.uoff = block, F.voff = dense_voff, F.rk = ncols (unless strict).
-// pred: predicted ranks (sketch widths, and the early dense decision).
+// Compression of the tiles below the diagonal of one or more columns (the
+// primal column j+1 and the tangent column j share every launch).  Job k's
+// tiles are held densely in its src (ld = n, inside the column workspace),
+// tile t being global tile i = i_first + t of column col, and occupy the
+// global slots g0 .. g0 + T - 1 of the compression scratch.
+// Low-rank tiles: U written to the family's slot, V~ (before the TRSM) to
+// Vtmp + g*vslot, rank recorded.  Tiles whose rank would exceed maxrank are
+// copied to a dense block: uoff = block, voff = dense_voff, rank = ncols
+// (unless strict).  pred: predicted ranks (sketch widths, early dense
+// decision).
 //
 //   Y = C Omega; Y = Q_y R_y (blocked Householder); t1 from R_y's column
 //   tails; Q1 = Q_y[:, :t1]; B^T = C^T Q1 = Q_b R_b; R_b Pi = Q_r R_r cut at
 //   k; V~ = Q_b [Q_r; 0]; U = Q1 Pi R_r[:k, :]^T.
 // ---------------------------------------------------------------------------
-void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first, int T, int col, int ncols,
-                     Family& F, double* vt, const std::vector<int>& pred, int64_t dense_voff) {
-  if (T <= 0) return;
+struct ColumnJob {
+  const double* src;
+  int i_first, T, col;
+  Family* F;
+  RankPred pred;
+  int64_t dense_voff;
+  int g0;
+};
+
+void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
+  int G = 0;
+  for (ColumnJob& jb : jobs) {
+    jb.g0 = G;
+    G += std::max(jb.T, 0);
+  }
+  if (G <= 0) return;
+  if (G > h->gcap) throw Fail{TLR_EINVAL};
   const int nb = h->nb;
+  const int ncols = nb;   // a column with tiles below its diagonal is never the ragged last one
+  const int64_t ld = h->n;
   const int maxrank = h->maxrank;
+  const int gc = h->gcap;
   const size_t e_c = prof_mark(h);
   double cflops = 0.0;
   const double tol = h->o.tol;
-  const double tol_range = 0.05 * tol;  // per-sample residual of the range finder
-  const double tol_trunc = 0.9 * tol;   // Frobenius norm of the discarded block
-  const int nt = h->nt;
-  HqrTask* hq_fy = h->hq_h;           // factor Y (synchronised per round)
-  HqrTask* hq_ay = h->hq_h + nt;      // Q1 = Q_y [I; 0]
-  HqrTask* hq_fb = h->hq_h + 2 * nt;  // factor B^T
-  HqrTask* hq_ab = h->hq_h + 3 * nt;  // V~ = Q_b [Q_r; 0]
-  std::vector<char> dense(T, 0);
-  std::vector<int> sz(T), t1(T, 0), todo;
-  for (int t = 0; t < T; ++t) {
-    if (!h->strict && pred[t] > maxrank) {
-      dense[t] = 1;
+  // error budget: range finder (per-sample residual; the spectral error it
+  // leaves is about that size, rarely twice it) + truncation (Frobenius norm
+  // of the discarded block) <= tol in the spectral norm
+  const double tol_range = 0.1 * tol;
+  const double tol_trunc = 0.8 * tol;
+  HqrTask* hq_fy = h->hq_h;            // factor Y (synchronised per round)
+  HqrTask* hq_ay = h->hq_h + gc;       // Q1 = Q_y [I; 0]
+  HqrTask* hq_fb = h->hq_h + 2 * gc;   // factor B^T
+  HqrTask* hq_ab = h->hq_h + 3 * gc;   // V~ = Q_b [Q_r; 0]
+  // global slot -> job, local tile, source row offset (from the workspace base)
+  std::vector<int> jof(G), tloc(G), rows(G);
+  std::vector<int64_t> srow(G);
+  for (int k = 0; k < (int)jobs.size(); ++k)
+    for (int t = 0; t < jobs[k].T; ++t) {
+      const int g = jobs[k].g0 + t;
+      jof[g] = k;
+      tloc[g] = t;
+      rows[g] = tile_rows(h, jobs[k].i_first + t);
+      srow[g] = (jobs[k].src - h->col) + (int64_t)t * nb;
+    }
+  auto fail_rank = [&](int g) {
+    h->bad_i = jobs[jof[g]].i_first + tloc[g];
+    h->bad_j = jobs[jof[g]].col;
+    throw Fail{TLR_ERANK};
+  };
+  std::vector<char> dense(G, 0);
+  std::vector<int> sz(G), t1(G, 0), todo;
+  int rounds = 0;
+  for (int g = 0; g < G; ++g) {
+    const RankPred& pred = jobs[jof[g]].pred;
+    const int t = tloc[g];
+    if (!h->strict && pred.k[t] > maxrank) {
+      dense[g] = 1;
+      t1[g] = pred.r1[t];
       continue;
     }
-    sz[t] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred[t] + 16)));
-    todo.push_back(t);
+    sz[g] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred.r1[t] + pred.r1[t] * 3 / 20 + 16)));
+    todo.push_back(g);
   }
   // 1-2. sketch and range rank; a tile with fewer than 8 samples beyond its
-  // rank estimate is sketched again, alone, twice as wide
-  bool first = true;
+  // rank estimate is sketched again, alone, 1.3 times as wide
   while (!todo.empty()) {
     int swide = 0;
-    for (int t : todo) swide = std::max(swide, sz[t]);
+    for (int g : todo) swide = std::max(swide, sz[g]);
     const int cnt = (int)todo.size();
     meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
     {
@@ -433,101 +528,92 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       int64_t* c_h = lm_take(h, cnt, &c_d);
       int maxm = 1;
       for (int q = 0; q < cnt; ++q) {
-        const int t = todo[q];
-        m_h[q] = tile_rows(h, i_first + t);
-        n_h[q] = sz[t];
-        a_h[q] = (int64_t)t * nb;
-        c_h[q] = (int64_t)t * nb;
+        const int g = todo[q];
+        m_h[q] = rows[g];
+        n_h[q] = sz[g];
+        a_h[q] = srow[g];
+        c_h[q] = (int64_t)g * nb * h->smax;
         maxm = std::max(maxm, m_h[q]);
       }
       im_push(h, m_h, m_d, 2 * (int64_t)cnt);
       lm_push(h, a_h, a_d, 2 * (int64_t)cnt);
       GemmSeg sg{};
-      sg.A = op_contig(src, ld, 0, 0);
+      sg.A = op_contig(h->col, ld, 0, 0);
       sg.B = op_contigT(h->omega, nb, 0, 0);
       sg.K = ncols;
-      if (first && cnt == T) {  // every tile: one plain GEMM over the stacked rows
-        int64_t rows = 0;
-        for (int t = 0; t < T; ++t) rows += tile_rows(h, i_first + t);
-        gemm(h, rows, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0));
-      } else {
-        GemmBatch bt{};
-        bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
-        gemm(h, maxm, swide, 1, &sg, h->Ybuf, h->n, epi_linear(1.0, 0.0), &bt);
-      }
+      GemmBatch bt{};
+      bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
+      gemm(h, maxm, swide, 1, &sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, swide <= 64 ? 64 : 128, m_h,
+           n_h);
     }
     for (int q = 0; q < cnt; ++q) {
-      const int t = todo[q];
+      const int g = todo[q];
       HqrTask& tk = hq_fy[q];
       tk = HqrTask{};
-      tk.A = h->Ybuf + (int64_t)t * nb;
-      tk.lda = h->n;
-      tk.m = tile_rows(h, i_first + t);
-      tk.s = sz[t];
-      tk.T = h->Tw + (int64_t)t * h->tw_stride;
+      tk.A = h->Ybuf + (int64_t)g * nb * h->smax;
+      tk.lda = nb;
+      tk.m = rows[g];
+      tk.s = sz[g];
+      tk.T = h->Tw + (int64_t)g * h->tw_stride;
       tk.tol = tol_range;
       tk.min_tail = 8;
-      tk.rank = h->qr_d + t;
-      tk.flag = h->qr_d + h->nt + t;
+      tk.rank = h->qr_d + g;
+      tk.flag = h->qr_d + gc + g;
     }
     HIPCHK(hipMemcpyAsync(h->hq_d, hq_fy, cnt * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
-    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
     sync(h);
     meta_reset(h);
     throw_if_not_spd(h);
     std::vector<int> next;
     for (int q = 0; q < cnt; ++q) {
-      const int t = todo[q];
-      t1[t] = h->qr_h[t];
-      const double m = tile_rows(h, i_first + t);
-      cflops += 2.0 * m * sz[t] * ncols + 2.0 * m * sz[t] * sz[t];
-      if (h->qr_h[h->nt + t]) {
-        if (sz[t] >= h->smax) {
-          if (h->strict) {
-            h->bad_i = i_first + t;
-            h->bad_j = col;
-            throw Fail{TLR_ERANK};
-          }
-          dense[t] = 1;
+      const int g = todo[q];
+      t1[g] = h->qr_h[g];
+      const double m = rows[g];
+      cflops += 2.0 * m * sz[g] * ncols + 2.0 * m * sz[g] * sz[g];
+      if (h->qr_h[gc + g]) {
+        if (sz[g] >= h->smax) {
+          if (h->strict) fail_rank(g);
+          dense[g] = 1;
           continue;
         }
-        sz[t] = std::min(h->smax, 2 * sz[t]);
-        next.push_back(t);
-      } else if (!h->strict && t1[t] > maxrank + maxrank / 2 + 16) {
-        dense[t] = 1;  // the truncation cannot get below maxrank
+        sz[g] = (int)std::min<int64_t>(h->smax, pad16(sz[g] + sz[g] * 3 / 10));
+        next.push_back(g);
+      } else if (!h->strict && t1[g] > maxrank + maxrank / 2 + 16) {
+        dense[g] = 1;  // the truncation cannot get below maxrank
       }
     }
     todo.swap(next);
-    first = false;
+    ++rounds;
   }
   std::vector<int> lr;  // tiles still headed for a low-rank form, t1 > 0
-  for (int t = 0; t < T; ++t)
-    if (!dense[t] && t1[t] > 0) lr.push_back(t);
+  for (int g = 0; g < G; ++g)
+    if (!dense[g] && t1[g] > 0) lr.push_back(g);
   const int L = (int)lr.size();
-  std::vector<int> k2(T, 0);
+  std::vector<int> k2(G, 0);
   if (L > 0) {
     // Q1 = Q_y [I_t1; 0]
     for (int q = 0; q < L; ++q) {
-      const int t = lr[q];
+      const int g = lr[q];
       HqrTask& tk = hq_ay[q];
       tk = HqrTask{};
-      tk.A = h->Ybuf + (int64_t)t * nb;
-      tk.lda = h->n;
-      tk.m = tile_rows(h, i_first + t);
-      tk.s = sz[t];
-      tk.T = h->Tw + (int64_t)t * h->tw_stride;
-      tk.X = h->Q1 + (int64_t)t * nb;
-      tk.ldx = h->n;
-      tk.kx = t1[t];
+      tk.A = h->Ybuf + (int64_t)g * nb * h->smax;
+      tk.lda = nb;
+      tk.m = rows[g];
+      tk.s = sz[g];
+      tk.T = h->Tw + (int64_t)g * h->tw_stride;
+      tk.X = h->Q1 + (int64_t)g * nb * h->smax;
+      tk.ldx = nb;
+      tk.kx = t1[g];
       tk.identity = 1;
-      cflops += 2.0 * tk.m * t1[t] * t1[t];
+      cflops += 2.0 * tk.m * t1[g] * t1[g];
     }
-    HIPCHK(hipMemcpyAsync(h->hq_d + nt, hq_ay, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_apply(h->hq_d + nt, L, h->s));
+    HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s));
     meta_reserve(h, 3 * (int64_t)L, 3 * (int64_t)L);
-    // 3. project: Bt_t = C_t^T Q1_t (ncols x t1)
+    // 3. project: Bt_g = C_g^T Q1_g (ncols x t1)
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, L, &m_d);
     int* n_h = im_take(h, L, &n_d);
@@ -538,42 +624,42 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     int64_t* c_h = lm_take(h, L, &c_d);
     int maxn = 1;
     for (int q = 0; q < L; ++q) {
-      const int t = lr[q];
+      const int g = lr[q];
       m_h[q] = ncols;
-      n_h[q] = t1[t];
-      k_h[q] = tile_rows(h, i_first + t);
-      a_h[q] = (int64_t)t * nb;                       // row offset of tile t in src (contigT frame)
-      b_h[q] = (int64_t)t * nb;                       // Q1 rows
-      c_h[q] = (int64_t)t * nb * h->smax;             // Bt block
+      n_h[q] = t1[g];
+      k_h[q] = rows[g];
+      a_h[q] = srow[g];                               // row offset of the tile in the workspace (contigT frame)
+      b_h[q] = (int64_t)g * nb * h->smax;             // Q1 block
+      c_h[q] = (int64_t)g * nb * h->smax;             // Bt block
       maxn = std::max(maxn, n_h[q]);
-      cflops += 2.0 * ncols * t1[t] * k_h[q];
+      cflops += 2.0 * ncols * t1[g] * k_h[q];
     }
     im_push(h, m_h, m_d, 3 * (int64_t)L);
     lm_push(h, a_h, a_d, 3 * (int64_t)L);
     {
       GemmSeg sg{};
-      sg.A = op_contigT(src, ld, 0, 0);
-      sg.B = op_contigT(h->Q1, h->n, 0, 0);
+      sg.A = op_contigT(h->col, ld, 0, 0);
+      sg.B = op_contigT(h->Q1, nb, 0, 0);
       sg.K = nb;
       GemmBatch bt{};
       bt.count = L; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
-      gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
+      gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
     }
     // 4. B^T = Q_b R_b
     for (int q = 0; q < L; ++q) {
-      const int t = lr[q];
+      const int g = lr[q];
       HqrTask& tk = hq_fb[q];
       tk = HqrTask{};
-      tk.A = h->Bt + (int64_t)t * nb * h->smax;
+      tk.A = h->Bt + (int64_t)g * nb * h->smax;
       tk.lda = nb;
       tk.m = ncols;
-      tk.s = t1[t];
-      tk.T = h->Tw + (int64_t)t * h->tw_stride;
-      cflops += 2.0 * ncols * t1[t] * t1[t];
+      tk.s = t1[g];
+      tk.T = h->Tw + (int64_t)g * h->tw_stride;
+      cflops += 2.0 * ncols * t1[g] * t1[g];
     }
-    HIPCHK(hipMemcpyAsync(h->hq_d + 2 * nt, hq_fb, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_factor(h->hq_d + 2 * nt, L, h->s));
-    // 5. truncation by pivoted QR of R_b (t1 x t1): Q_r into vt, Z = Pi R_r[:k, :]^T.
+    HIPCHK(hipMemcpyAsync(h->hq_d + 2 * gc, hq_fb, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
+    // 5. truncation by pivoted QR of R_b (t1 x t1): Q_r into Vtmp, Z = Pi R_r[:k, :]^T.
     // Small factors stay in registers; larger ones are copied out and pivoted
     // in place (reflectors in the Y workspace, which Q1 no longer needs).
     std::vector<int> big;
@@ -582,34 +668,35 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       if (t1[lr[q]] <= kRegQrMax) ++nsmall;
     int qs = 0, qb = nsmall;
     for (int q = 0; q < L; ++q) {
-      const int t = lr[q];
-      const bool small = t1[t] <= kRegQrMax;
+      const int g = lr[q];
+      const bool small = t1[g] <= kRegQrMax;
       QrcpTask& tk = h->tk_h[small ? qs++ : qb++];
       tk = QrcpTask{};
-      tk.m = t1[t];
-      tk.q = t1[t];
+      tk.m = t1[g];
+      tk.q = t1[g];
       tk.tol = tol_trunc;
       tk.max_rank = maxrank + 1;
       tk.min_tail = 0;
-      tk.Q = vt + (int64_t)t * h->vslot;
+      tk.Q = h->Vtmp + (int64_t)g * h->vslot;
       tk.ldq = nb;
-      tk.Z = h->Zb + (int64_t)t * h->smax * (maxrank + 1);
+      tk.Z = h->Zb + (int64_t)g * h->smax * (maxrank + 1);
       tk.ldz = h->smax;
-      tk.rank = h->qr_d + t;
-      tk.flag = h->qr_d + h->nt + t;
+      tk.rank = h->qr_d + g;
+      tk.flag = h->qr_d + gc + g;
       if (small) {
-        tk.Y = h->Bt + (int64_t)t * nb * h->smax;
+        tk.Y = h->Bt + (int64_t)g * nb * h->smax;
         tk.ldy = nb;
         tk.upper = 1;
-        tk.W = h->Ybuf + (int64_t)t * nb;
-        tk.ldw = h->n;
+        tk.W = h->Ybuf + (int64_t)g * nb * h->smax;
+        tk.ldw = nb;
       } else {
-        tk.Y = h->Ybuf + (int64_t)t * nb;
-        tk.ldy = h->n;
-        big.push_back(t);
+        tk.Y = h->Ybuf + (int64_t)g * nb * h->smax;
+        tk.ldy = nb;
+        big.push_back(g);
       }
-      cflops += 4.0 * t1[t] * t1[t] * t1[t] / 3.0;
+      cflops += 4.0 * t1[g] * t1[g] * t1[g] / 3.0;
     }
+    int big_m = 0;
     if (!big.empty()) {
       const int nbg = (int)big.size();
       meta_reserve(h, nbg, 2 * (int64_t)nbg);
@@ -618,76 +705,89 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
       int64_t *so_d, *do_d;
       int64_t* so_h = lm_take(h, nbg, &so_d);
       int64_t* do_h = lm_take(h, nbg, &do_d);
-      int nmax = 0;
       for (int q = 0; q < nbg; ++q) {
         nn_h[q] = t1[big[q]];
         so_h[q] = (int64_t)big[q] * nb * h->smax;
-        do_h[q] = (int64_t)big[q] * nb;
-        nmax = std::max(nmax, nn_h[q]);
+        do_h[q] = (int64_t)big[q] * nb * h->smax;
+        big_m = std::max(big_m, nn_h[q]);
       }
       im_push(h, nn_h, nn_d, nbg);
       lm_push(h, so_h, so_d, 2 * (int64_t)nbg);
-      HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, h->n, do_d, nn_d, nmax, nbg, h->s));
+      HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
     }
     HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
     HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
-    HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s));
-    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, h->nt * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
+    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
     sync(h);
     meta_reset(h);
     for (int q = 0; q < L; ++q) {
-      const int t = lr[q];
-      k2[t] = h->qr_h[t];
-      const double m = tile_rows(h, i_first + t);
-      cflops += 4.0 * ncols * t1[t] * k2[t] + 2.0 * m * t1[t] * k2[t];
-      if (k2[t] > maxrank) {
-        if (h->strict) {
-          h->bad_i = i_first + t;
-          h->bad_j = col;
-          throw Fail{TLR_ERANK};
-        }
-        dense[t] = 1;
+      const int g = lr[q];
+      k2[g] = h->qr_h[g];
+      const double m = rows[g];
+      cflops += 4.0 * ncols * t1[g] * k2[g] + 2.0 * m * t1[g] * k2[g];
+      if (k2[g] > maxrank) {
+        if (h->strict) fail_rank(g);
+        dense[g] = 1;
       }
     }
   }
   // record the outcome
   int maxk = 0, nlr = 0, ndense = 0;
-  for (int t = 0; t < T; ++t) {
-    const size_t id = tid_of(h, i_first + t, col);
-    F.isdense[id] = dense[t];
-    if (dense[t]) {
+  for (int g = 0; g < G; ++g) {
+    const ColumnJob& jb = jobs[jof[g]];
+    Family& F = *jb.F;
+    const int i = jb.i_first + tloc[g];
+    const size_t id = tid_of(h, i, jb.col);
+    F.isdense[id] = dense[g];
+    F.r1[id] = t1[g];
+    if (dense[g]) {
       F.rk[id] = ncols;
       F.uoff[id] = take_dense_block(h);
-      F.voff[id] = dense_voff;
+      F.voff[id] = jb.dense_voff;
       ++ndense;
     } else {
-      F.rk[id] = k2[t];
-      F.uoff[id] = F.u_base + slot_of(h, i_first + t, col) * h->slot;
-      F.voff[id] = F.v_base + slot_of(h, i_first + t, col) * h->slot;
-      maxk = std::max(maxk, k2[t]);
-      if (k2[t] > 0) ++nlr;
+      F.rk[id] = k2[g];
+      F.uoff[id] = F.u_base + slot_of(h, i, jb.col) * h->slot;
+      F.voff[id] = F.v_base + slot_of(h, i, jb.col) * h->slot;
+      maxk = std::max(maxk, k2[g]);
+      if (k2[g] > 0) ++nlr;
     }
   }
-  // 6. V~ = Q_b [Q_r; 0] and U_t = Q1_t Z_t (m_t x k_t) for the low-rank tiles
+  if (h->debug) {
+    for (const ColumnJob& jb : jobs) {
+      int s_max = 0, t1_max = 0, k_max = 0, nbig = 0, nd = 0;
+      for (int g = jb.g0; g < jb.g0 + jb.T; ++g) {
+        s_max = std::max(s_max, sz[g]);
+        t1_max = std::max(t1_max, t1[g]);
+        if (!dense[g]) k_max = std::max(k_max, k2[g]);
+        nbig += (!dense[g] && t1[g] > kRegQrMax) ? 1 : 0;
+        nd += dense[g];
+      }
+      std::fprintf(stderr, "[tlr] col %d%s tiles %d rounds %d sketch<=%d t1<=%d k<=%d big %d dense %d\n", jb.col,
+                   jb.F == &h->fam[1] ? "'" : "", jb.T, rounds, s_max, t1_max, k_max, nbig, nd);
+    }
+  }
+  // 6. V~ = Q_b [Q_r; 0] and U_g = Q1_g Z_g (m_g x k_g) for the low-rank tiles
   meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
   if (nlr > 0) {
     int q = 0;
-    for (int t = 0; t < T; ++t) {
-      if (dense[t] || k2[t] == 0) continue;
+    for (int g = 0; g < G; ++g) {
+      if (dense[g] || k2[g] == 0) continue;
       HqrTask& tk = hq_ab[q++];
       tk = HqrTask{};
-      tk.A = h->Bt + (int64_t)t * nb * h->smax;
+      tk.A = h->Bt + (int64_t)g * nb * h->smax;
       tk.lda = nb;
       tk.m = ncols;
-      tk.s = t1[t];
-      tk.T = h->Tw + (int64_t)t * h->tw_stride;
-      tk.X = vt + (int64_t)t * h->vslot;
+      tk.s = t1[g];
+      tk.T = h->Tw + (int64_t)g * h->tw_stride;
+      tk.X = h->Vtmp + (int64_t)g * h->vslot;
       tk.ldx = nb;
-      tk.kx = k2[t];
-      tk.xrows = t1[t];
+      tk.kx = k2[g];
+      tk.xrows = t1[g];
     }
-    HIPCHK(hipMemcpyAsync(h->hq_d + 3 * nt, hq_ab, nlr * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_apply(h->hq_d + 3 * nt, nlr, h->s));
+    HIPCHK(hipMemcpyAsync(h->hq_d + 3 * gc, hq_ab, nlr * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s));
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, nlr, &m_d);
     int* n_h = im_take(h, nlr, &n_d);
@@ -698,26 +798,27 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     int64_t* c_h = lm_take(h, nlr, &c_d);
     int maxm = 1;
     q = 0;
-    for (int t = 0; t < T; ++t) {
-      if (dense[t] || k2[t] == 0) continue;
-      m_h[q] = tile_rows(h, i_first + t);
-      n_h[q] = k2[t];
-      k_h[q] = t1[t];
-      a_h[q] = (int64_t)t * nb;
-      b_h[q] = (int64_t)t * h->smax * (maxrank + 1);
-      c_h[q] = F.uoff[tid_of(h, i_first + t, col)];
+    for (int g = 0; g < G; ++g) {
+      if (dense[g] || k2[g] == 0) continue;
+      const ColumnJob& jb = jobs[jof[g]];
+      m_h[q] = rows[g];
+      n_h[q] = k2[g];
+      k_h[q] = t1[g];
+      a_h[q] = (int64_t)g * nb * h->smax;
+      b_h[q] = (int64_t)g * h->smax * (maxrank + 1);
+      c_h[q] = jb.F->uoff[tid_of(h, jb.i_first + tloc[g], jb.col)];
       maxm = std::max(maxm, m_h[q]);
       ++q;
     }
     im_push(h, m_h, m_d, 3 * (int64_t)nlr);
     lm_push(h, a_h, a_d, 3 * (int64_t)nlr);
     GemmSeg sg{};
-    sg.A = op_contig(h->Q1, h->n, 0, 0);
+    sg.A = op_contig(h->Q1, nb, 0, 0);
     sg.B = op_contigT(h->Zb, h->smax, 0, 0);
     sg.K = h->smax;
     GemmBatch bt{};
     bt.count = nlr; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
-    gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
+    gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
   }
   // dense tiles: copy the tile into its block
   if (ndense > 0) {
@@ -728,17 +829,18 @@ void compress_column(tlr_handle_s* h, const double* src, int64_t ld, int i_first
     int64_t* so_h = lm_take(h, ndense, &so_d);
     int64_t* do_h = lm_take(h, ndense, &do_d);
     int q = 0;
-    for (int t = 0; t < T; ++t) {
-      if (!dense[t]) continue;
-      m_h[q] = tile_rows(h, i_first + t);
+    for (int g = 0; g < G; ++g) {
+      if (!dense[g]) continue;
+      const ColumnJob& jb = jobs[jof[g]];
+      m_h[q] = rows[g];
       k_h[q] = ncols;
-      so_h[q] = (int64_t)t * nb;
-      do_h[q] = F.uoff[tid_of(h, i_first + t, col)];
+      so_h[q] = srow[g];
+      do_h[q] = jb.F->uoff[tid_of(h, jb.i_first + tloc[g], jb.col)];
       ++q;
     }
     im_push(h, m_h, m_d, 2 * (int64_t)ndense);
     lm_push(h, so_h, so_d, 2 * (int64_t)ndense);
-    HIPCHK(launch_batched_copy(src, ld, so_d, h->arena, nb, do_d, m_d, k_d, (int64_t)nb * ncols, ndense, h->s));
+    HIPCHK(launch_batched_copy(h->col, ld, so_d, h->arena, nb, do_d, m_d, k_d, (int64_t)nb * ncols, ndense, h->s));
   }
   prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
 }
@@ -786,7 +888,7 @@ void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt
   GemmBatch bt{};
   bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
   const size_t e_t = prof_mark(h);
-  gemm(h, nbj, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32);
+  gemm(h, nbj, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
   prof_add(h, TLR_K_LOWRANK, e_t, 2.0 * nbj * nbj * kt, 8.0 * (2.0 * nbj * kt + (double)nbj * nbj));
 }
 
@@ -938,7 +1040,8 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           xb.count = cnt;
           xb.m_of = xm_d; xb.n_of = xn_d; xb.k_of = xk_d;
           xb.a_off = xa_d; xb.b_off = xb_d; xb.c_off = xc_d;
-          gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb, false, grp ? 128 : 32, 32);
+          gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb, false, grp ? 128 : 32, 32, xm_h,
+               xn_h);
           GemmSeg ws{};
           ws.A = op_contig(h->arena, nb, 0, 0);
           ws.B = op_contigT(h->Xb, maxa, 0, 0);
@@ -947,7 +1050,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           wb.count = cnt;
           wb.m_of = wm_d; wb.n_of = wn_d; wb.k_of = wk_d;
           wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
-          gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32);
+          gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32, wm_h, wn_h);
         }
     }
     prof_add(h, TLR_K_LOWRANK, e_w, wflops, wbytes);
@@ -1066,29 +1169,48 @@ void factor_dense(tlr_handle_s* h, bool tangent) {
   }
 }
 
-std::vector<int> predict_ranks(const tlr_handle_s* h, const Family& F, int j, int T) {
-  // the tile up-left on the same diagonal and the tile to the left
-  std::vector<int> pred(T);
+// Rank predictions for the tiles below the diagonal of column j: the same
+// tile's ranks in the previous factorisation when there is one, else the
+// tile up-left on the same diagonal and the tile to the left.  The final rank
+// decides a tile dense early; the range-finder rank sets the sketch width.
+RankPred predict_ranks(const tlr_handle_s* h, const Family& F, int j, int T) {
+  RankPred p;
+  p.k.resize(T);
+  p.r1.resize(T);
   for (int t = 0; t < T; ++t) {
     const int i = j + 1 + t;
-    pred[t] = (j > 0) ? std::max(F.rk[tid_of(h, i - 1, j - 1)], F.rk[tid_of(h, i, j - 1)]) : 48;
+    if (F.hist) {
+      p.k[t] = F.rk_prev[tid_of(h, i, j)];
+      p.r1[t] = F.r1_prev[tid_of(h, i, j)];
+    } else if (j > 0) {
+      p.k[t] = std::max(F.rk[tid_of(h, i - 1, j - 1)], F.rk[tid_of(h, i, j - 1)]);
+      p.r1[t] = std::max(F.r1[tid_of(h, i - 1, j - 1)], F.r1[tid_of(h, i, j - 1)]);
+    } else {
+      p.k[t] = 0;
+      p.r1[t] = 40;
+    }
   }
-  return pred;
+  return p;
 }
 
+// Left-looking TLR Cholesky, column by column.  With the tangent, the primal
+// column j+1 and the tangent column j are processed in lockstep (both need
+// only the primal columns <= j and the tangent columns < j), and their tiles
+// share the compression launches: half as many serial launch groups, twice
+// as many tiles per launch.
 void factor_tlr(tlr_handle_s* h, bool tangent) {
   const int nt = h->nt, nb = h->nb;
   reset_info(h);
-  family_reset(h, h->fam[0]);
-  family_reset(h, h->fam[1]);
+  family_reset(h, h->fam[0], 1);
+  family_reset(h, h->fam[1], 1);
   h->dense_used = 0;
   meta_reset(h);
   sync(h);
   Family& P = h->fam[0];
   Family& G = h->fam[1];
-  for (int j = 0; j < nt; ++j) {
+  // generation + update + diagonal factorisation of primal column j
+  auto primal_column = [&](int j) {
     const int nbj = tile_rows(h, j);
-    const int64_t dinv_j = h->dinv_off + (int64_t)j * nb * nb;
     LRTerm tm{&P, &P};
     tlr_column_update(h, j, 1, &tm, h->col, kEpiGenMinus);
     const size_t e_d = prof_mark(h);
@@ -1096,96 +1218,127 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     HIPCHK(tile_potrf_inv(diag_tile(h, j), nb, nbj, dinv_tile(h, j), nb, h->info_d, (int64_t)j * nb, h->tw, h->s));
     HIPCHK(launch_logdiag(diag_tile(h, j), nb, nbj, h->scal + j, h->s));
     prof_add(h, TLR_K_DIAG, e_d, 2.0 / 3.0 * nbj * (double)nbj * nbj, 16.0 * nbj * (double)nbj);
+  };
+  auto primal_job = [&](int j) {
     const int T = nt - j - 1;
-    if (T > 0) {
-      compress_column(h, h->col + nbj, h->n, j + 1, T, j, nbj, P, h->Vtmp, predict_ranks(h, P, j, T), dinv_j);
-      lowrank_trsm(h, j, j + 1, T, h->Vtmp, P);
-    }
-    if (!tangent) continue;
-    // dC(:, j) = dSigma/dbeta - sum_k [dL_ik L_jk^T + L_ik dL_jk^T]
+    return ColumnJob{h->col + tile_rows(h, j), j + 1, T, j, &P, predict_ranks(h, P, j, T),
+                     h->dinv_off + (int64_t)j * nb * nb, 0};
+  };
+  // dC(:, j) = dSigma/dbeta - sum_k [dL_ik L_jk^T + L_ik dL_jk^T]; the
+  // tangent of the diagonal step; dC_ij <- dC_ij - L_ij dL_jj^T (then
+  // compressed: dL_ij = (that) L_jj^{-T}, low-rank V <- L_jj^{-1} V)
+  auto tangent_column = [&](int j) {
+    const int nbj = tile_rows(h, j);
     LRTerm tt[2] = {{&G, &P}, {&P, &G}};
     tlr_column_update(h, j, 2, tt, h->cold, kEpiDGenMinus);
     double* ddj = h->Dd + (int64_t)j * nb * nb;
     const size_t e_td = prof_mark(h);
     tangent_diag(h, j, h->cold, h->n, diag_tile(h, j), nb, ddj, nb);
     prof_add(h, TLR_K_DIAG, e_td, 6.0 * nbj * (double)nbj * nbj, 32.0 * nbj * (double)nbj);
-    if (T > 0) {
-      // dC_ij <- dC_ij - L_ij dL_jj^T = dC_ij - U_ij (dL_jj V_ij)^T, then compress;
-      // dL_ij = (that) L_jj^{-T}: low-rank V <- L_jj^{-1} V, dense V = L_jj^{-1}
-      int kmax = 0, cnt = 0;
-      for (int t = 0; t < T; ++t) {
-        const int r = P.rk[tid_of(h, j + 1 + t, j)];
-        kmax = std::max(kmax, r);
-        if (r > 0) ++cnt;
-      }
-      const size_t e_c = prof_mark(h);
-      double cf = 0.0;
-      if (cnt > 0) {
-        meta_reserve(h, 6 * (int64_t)cnt, 6 * (int64_t)cnt);
-        int *m_d, *n_d, *k_d;
-        int* m_h = im_take(h, cnt, &m_d);
-        int* n_h = im_take(h, cnt, &n_d);
-        int* k_h = im_take(h, cnt, &k_d);
-        int64_t *a_d, *b_d, *c_d;
-        int64_t* a_h = lm_take(h, cnt, &a_d);
-        int64_t* b_h = lm_take(h, cnt, &b_d);
-        int64_t* c_h = lm_take(h, cnt, &c_d);
-        int q = 0;
-        for (int t = 0; t < T; ++t) {
-          const size_t id = tid_of(h, j + 1 + t, j);
-          if (P.rk[id] <= 0) continue;
-          m_h[q] = nbj; n_h[q] = P.rk[id]; k_h[q] = nbj;
-          a_h[q] = 0;
-          b_h[q] = P.voff[id];
-          c_h[q] = (int64_t)t * nb * nb;
-          cf += 2.0 * nbj * nbj * P.rk[id];
-          ++q;
-        }
-        im_push(h, m_h, m_d, 3 * (int64_t)cnt);
-        lm_push(h, a_h, a_d, 3 * (int64_t)cnt);
-        GemmSeg ps{};
-        ps.A = op_contig(ddj, nb, 0, 0);
-        ps.B = op_contigT(h->arena, nb, 0, 0);
-        ps.K = nbj;
-        GemmBatch pb{};
-        pb.count = cnt; pb.m_of = m_d; pb.n_of = n_d; pb.k_of = k_d; pb.a_off = a_d; pb.b_off = b_d; pb.c_off = c_d;
-        gemm(h, nbj, kmax, 1, &ps, h->Ptmp, nb, epi_linear(1.0, 0.0), &pb, false, 128, kmax > 64 ? 128 : 32);
-        int* m2_h = im_take(h, cnt, &m_d);
-        int* n2_h = im_take(h, cnt, &n_d);
-        int* k2_h = im_take(h, cnt, &k_d);
-        int64_t* a2_h = lm_take(h, cnt, &a_d);
-        int64_t* b2_h = lm_take(h, cnt, &b_d);
-        int64_t* c2_h = lm_take(h, cnt, &c_d);
-        int mmax = 1;
-        q = 0;
-        for (int t = 0; t < T; ++t) {
-          const size_t id = tid_of(h, j + 1 + t, j);
-          if (P.rk[id] <= 0) continue;
-          m2_h[q] = tile_rows(h, j + 1 + t); n2_h[q] = nbj; k2_h[q] = P.rk[id];
-          a2_h[q] = P.uoff[id];
-          b2_h[q] = (int64_t)t * nb * nb;
-          c2_h[q] = (int64_t)nbj + (int64_t)t * nb;
-          mmax = std::max(mmax, m2_h[q]);
-          cf += 2.0 * m2_h[q] * nbj * P.rk[id];
-          ++q;
-        }
-        im_push(h, m2_h, m_d, 3 * (int64_t)cnt);
-        lm_push(h, a2_h, a_d, 3 * (int64_t)cnt);
-        GemmSeg cs{};
-        cs.A = op_contig(h->arena, nb, 0, 0);
-        cs.B = op_contig(h->Ptmp, nb, 0, 0);
-        cs.K = kmax;
-        GemmBatch cb{};
-        cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
-        gemm(h, mmax, nbj, 1, &cs, h->cold, h->n, epi_linear(-1.0, 1.0), &cb);
-      }
-      prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
-      compress_column(h, h->cold + nbj, h->n, j + 1, T, j, nbj, G, h->Vtmp, predict_ranks(h, G, j, T), dinv_j);
-      lowrank_trsm(h, j, j + 1, T, h->Vtmp, G);
+    const int T = nt - j - 1;
+    if (T <= 0) return;
+    int kmax = 0, cnt = 0;
+    for (int t = 0; t < T; ++t) {
+      const int r = P.rk[tid_of(h, j + 1 + t, j)];
+      kmax = std::max(kmax, r);
+      if (r > 0) ++cnt;
     }
+    const size_t e_c = prof_mark(h);
+    double cf = 0.0;
+    if (cnt > 0) {
+      meta_reserve(h, 6 * (int64_t)cnt, 6 * (int64_t)cnt);
+      int *m_d, *n_d, *k_d;
+      int* m_h = im_take(h, cnt, &m_d);
+      int* n_h = im_take(h, cnt, &n_d);
+      int* k_h = im_take(h, cnt, &k_d);
+      int64_t *a_d, *b_d, *c_d;
+      int64_t* a_h = lm_take(h, cnt, &a_d);
+      int64_t* b_h = lm_take(h, cnt, &b_d);
+      int64_t* c_h = lm_take(h, cnt, &c_d);
+      int q = 0;
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (P.rk[id] <= 0) continue;
+        m_h[q] = nbj; n_h[q] = P.rk[id]; k_h[q] = nbj;
+        a_h[q] = 0;
+        b_h[q] = P.voff[id];
+        c_h[q] = (int64_t)t * nb * nb;
+        cf += 2.0 * nbj * nbj * P.rk[id];
+        ++q;
+      }
+      im_push(h, m_h, m_d, 3 * (int64_t)cnt);
+      lm_push(h, a_h, a_d, 3 * (int64_t)cnt);
+      GemmSeg ps{};
+      ps.A = op_contig(ddj, nb, 0, 0);
+      ps.B = op_contigT(h->arena, nb, 0, 0);
+      ps.K = nbj;
+      GemmBatch pb{};
+      pb.count = cnt; pb.m_of = m_d; pb.n_of = n_d; pb.k_of = k_d; pb.a_off = a_d; pb.b_off = b_d; pb.c_off = c_d;
+      gemm(h, nbj, kmax, 1, &ps, h->Ptmp, nb, epi_linear(1.0, 0.0), &pb, false, 128, kmax > 64 ? 128 : 32, m_h,
+           n_h);
+      int* m2_h = im_take(h, cnt, &m_d);
+      int* n2_h = im_take(h, cnt, &n_d);
+      int* k2_h = im_take(h, cnt, &k_d);
+      int64_t* a2_h = lm_take(h, cnt, &a_d);
+      int64_t* b2_h = lm_take(h, cnt, &b_d);
+      int64_t* c2_h = lm_take(h, cnt, &c_d);
+      int mmax = 1;
+      q = 0;
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (P.rk[id] <= 0) continue;
+        m2_h[q] = tile_rows(h, j + 1 + t); n2_h[q] = nbj; k2_h[q] = P.rk[id];
+        a2_h[q] = P.uoff[id];
+        b2_h[q] = (int64_t)t * nb * nb;
+        c2_h[q] = (int64_t)nbj + (int64_t)t * nb;
+        mmax = std::max(mmax, m2_h[q]);
+        cf += 2.0 * m2_h[q] * nbj * P.rk[id];
+        ++q;
+      }
+      im_push(h, m2_h, m_d, 3 * (int64_t)cnt);
+      lm_push(h, a2_h, a_d, 3 * (int64_t)cnt);
+      GemmSeg cs{};
+      cs.A = op_contig(h->arena, nb, 0, 0);
+      cs.B = op_contig(h->Ptmp, nb, 0, 0);
+      cs.K = kmax;
+      GemmBatch cb{};
+      cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
+      gemm(h, mmax, nbj, 1, &cs, h->cold, h->n, epi_linear(-1.0, 1.0), &cb);
+    }
+    prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
+  };
+  auto tangent_job = [&](int j) {
+    const int T = nt - j - 1;
+    return ColumnJob{h->cold + tile_rows(h, j), j + 1, T, j, &G, predict_ranks(h, G, j, T),
+                     h->dinv_off + (int64_t)j * nb * nb, 0};
+  };
+  auto finish = [&](std::vector<ColumnJob>& jobs) {
+    compress_columns(h, jobs);
+    for (const ColumnJob& jb : jobs)
+      if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
+  };
+
+  primal_column(0);
+  {
+    std::vector<ColumnJob> jobs{primal_job(0)};
+    finish(jobs);
+  }
+  for (int j = 0; j < nt; ++j) {
+    std::vector<ColumnJob> jobs;
+    if (j + 1 < nt) {
+      primal_column(j + 1);
+      jobs.push_back(primal_job(j + 1));
+    }
+    if (tangent) {
+      tangent_column(j);
+      jobs.push_back(tangent_job(j));
+    }
+    finish(jobs);
   }
   family_upload(h, P);
   sync(h);
+  P.done_kind = 1;
+  if (tangent) G.done_kind = 1;
 }
 
 // log|Sigma~| and y = L^{-1} z (into vec[1]); returns (logdet, quad)
@@ -1351,6 +1504,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     // sketch width cap: a tile whose range finder needs more columns than
     // this is (unless strict) kept dense
     h->smax = (int)std::min<int64_t>(kQrMaxCols, pad16(mr + mr / 2 + 48));
+    h->debug = std::getenv("TLR_DEBUG") != nullptr;
     h->slot = (int64_t)o->nb * mslot;
     h->vslot = (int64_t)o->nb * (mslot + 1);
     h->ntiles = (int64_t)h->nt * (h->nt - 1) / 2;
@@ -1359,8 +1513,9 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->d_tab = dalloc<double>(h, kTabSize);
     h->h_tab.assign(kTabSize, 0.0);
     if (h->dense) h->Dinv = dalloc<double>(h, nt * nb * nb);
-    h->col = dalloc<double>(h, n * nb);
-    if (h->grad) h->cold = dalloc<double>(h, n * nb);
+    // one allocation: compressions of both columns address their tiles from h->col
+    h->col = dalloc<double>(h, n * nb * (h->grad ? 2 : 1));
+    if (h->grad) h->cold = h->col + n * nb;
     h->tw = dalloc<double>(h, 64 * nb + 3 * nb * nb);
     h->vec = dalloc<double>(h, 4 * n);
     h->scal = dalloc<double>(h, 4 * nt + 16);
@@ -1389,6 +1544,9 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
           F.v_base = cur; cur += nslots * h->slot;
         }
         F.rk.assign((size_t)nt * nt, 0);
+        F.r1.assign((size_t)nt * nt, 0);
+        F.r1_prev.assign((size_t)nt * nt, 0);
+        F.rk_prev.assign((size_t)nt * nt, 0);
         F.uoff.assign((size_t)nt * nt, 0);
         F.voff.assign((size_t)nt * nt, 0);
         F.isdense.assign((size_t)nt * nt, 0);
@@ -1405,11 +1563,13 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       HIPCHK(launch_identity(h->arena + h->ident_off, nb, nb, h->s));
       if (h->grad) h->Ptmp = dalloc<double>(h, nt * nb * nb);
       h->omega = dalloc<double>(h, nb * h->smax);
-      h->Ybuf = dalloc<double>(h, n * h->smax);
-      h->Q1 = dalloc<double>(h, n * h->smax);
-      h->Bt = dalloc<double>(h, nt * nb * h->smax);
-      h->Vtmp = dalloc<double>(h, nt * h->vslot);
-      h->Zb = dalloc<double>(h, nt * h->smax * (mslot + 1));
+      h->gcap = (int)(h->grad ? 2 * nt : nt);   // tiles compressed together: two columns with the tangent
+      const int64_t gc = h->gcap;
+      h->Ybuf = dalloc<double>(h, gc * nb * h->smax);
+      h->Q1 = dalloc<double>(h, gc * nb * h->smax);
+      h->Bt = dalloc<double>(h, gc * nb * h->smax);
+      h->Vtmp = dalloc<double>(h, gc * h->vslot);
+      h->Zb = dalloc<double>(h, gc * h->smax * (mslot + 1));
       // a row of tiles may hold dense tiles (width nb) in every slot
       const int64_t rmax = nterms * nt * nb;
       h->urow_cap = nb * rmax;
@@ -1423,20 +1583,21 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * nb * nb);
       h->Wb = dalloc<double>(h, h->w_cap);
       h->Xb = dalloc<double>(h, h->x_cap);
-      h->im_cap = h->lm_cap = std::max<int64_t>(1 << 16, 16 * nt * nt * nterms + 64 * nt);
+      h->lm_cap = std::max<int64_t>(1 << 16, 16 * nt * nt * nterms + 64 * nt);
+      h->im_cap = std::max<int64_t>(1 << 20, 64 * nt * nt * nterms + 64 * nt);   // + flat tile lists
       h->im_d = dalloc<int>(h, h->im_cap);
       h->im_h = halloc<int>(h, h->im_cap);
       h->lm_d = dalloc<int64_t>(h, h->lm_cap);
       h->lm_h = halloc<int64_t>(h, h->lm_cap);
-      h->tk_cap = (int)nt;
-      h->tk_d = dalloc<QrcpTask>(h, nt);
-      h->tk_h = halloc<QrcpTask>(h, nt);
-      h->hq_d = dalloc<HqrTask>(h, 4 * nt);
-      h->hq_h = halloc<HqrTask>(h, 4 * nt);
+      h->tk_cap = (int)gc;
+      h->tk_d = dalloc<QrcpTask>(h, gc);
+      h->tk_h = halloc<QrcpTask>(h, gc);
+      h->hq_d = dalloc<HqrTask>(h, 4 * gc);
+      h->hq_h = halloc<HqrTask>(h, 4 * gc);
       h->tw_stride = (int64_t)((h->smax + 15) / 16) * 256;
-      h->Tw = dalloc<double>(h, nt * h->tw_stride);
-      h->qr_d = dalloc<int>(h, 2 * nt);
-      h->qr_h = halloc<int>(h, 2 * nt);
+      h->Tw = dalloc<double>(h, gc * h->tw_stride);
+      h->qr_d = dalloc<int>(h, 2 * gc);
+      h->qr_h = halloc<int>(h, 2 * gc);
       HIPCHK(launch_gaussian(h->omega, nb * h->smax, (uint32_t)o->seed, h->s));
     }
     for (hipEvent_t& e : h->ev) HIPCHK(hipEventCreate(&e));
@@ -1493,7 +1654,7 @@ tlr_status tlr_compress(tlr_handle_t h) {
     prof_reset_pool(h);
     const int nt = h->nt, nb = h->nb;
     Family& F = h->fam[0];
-    family_reset(h, F);
+    family_reset(h, F, 2);
     h->dense_used = 0;
     reset_info(h);
     sync(h);
@@ -1508,7 +1669,8 @@ tlr_status tlr_compress(tlr_handle_t h) {
       const int64_t rows = h->n - (int64_t)(j + 1) * nb;
       HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)(j + 1) * nb, rows, (int64_t)j * nb, nbj, h->col,
                                  h->n, false, h->s));
-      compress_column(h, h->col, h->n, j + 1, T, j, nbj, F, h->Vtmp, predict_ranks(h, F, j, T), h->ident_off);
+      std::vector<ColumnJob> jobs{ColumnJob{h->col, j + 1, T, j, &F, predict_ranks(h, F, j, T), h->ident_off, 0}};
+      compress_columns(h, jobs);
       // low-rank V slots <- V~ (no TRSM: this is Sigma itself)
       int cnt = 0;
       for (int t = 0; t < T; ++t) {
@@ -1541,6 +1703,7 @@ tlr_status tlr_compress(tlr_handle_t h) {
     }
     family_upload(h, F);
     sync(h);
+    F.done_kind = 2;
     rank_stats(h);
     h->state = 1;
     return TLR_OK;

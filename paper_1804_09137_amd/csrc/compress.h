@@ -50,7 +50,7 @@ struct HqrTask {
   int identity;     // apply: X starts as [I_kx; 0]
 };
 
-hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s);
+hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s, int max_m = kQrMaxRows);
 hipError_t launch_qrcp_reg(const QrcpTask* d_tasks, int count, hipStream_t s);
 hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
 hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s);

@@ -1,20 +1,15 @@
-// Tile compression kernels (Section V: each off-diagonal tile is replaced by
-// U V^T, keeping what exceeds an absolute accuracy threshold).
-//
-// Method used on the GPU (the paper allows SVD, randomized SVD or ACA):
-//   1. sketch       Y = C Omega            (MFMA GEMM, Omega Gaussian)
-//   2. range        Y Pi = Q1 R1 by column-pivoted Householder QR, stopped
-//                   when the Frobenius norm of the unreduced block of Y is
-//                   below a small fraction of the threshold
-//   3. project      B^T = C^T Q1           (MFMA GEMM)
-//   4. truncate     B^T Pi2 = Q2 R2 by column-pivoted Householder QR, stopped
-//                   when ||R2[k:, k:]||_F <= threshold
-//   5. assemble     U = Q1 Pi2 R2[:k, :]^T, V = Q2[:, :k]
-// so ||C - U V^T||_2 <= ||(I - Q1 Q1^T) C||_2 + ||R2[k:, k:]||_F.
-//
-// qrcp_kernel is one 512-thread workgroup per matrix; the matrix stays in
-// global memory (L2-resident), each of the 8 waves owns a set of columns and
-// keeps two column slices in registers during a Householder application.
+// Compression helpers (Section V: each off-diagonal tile is replaced by
+// U V^T, keeping what exceeds an absolute accuracy threshold).  The pipeline
+// itself (sketch, blocked Householder QR, range rank, projection, truncation)
+// is described in hqr.hip; this file holds:
+//   * qrcp_kernel: column-pivoted Householder QR of a matrix in global memory
+//     (L2-resident), one 512-thread workgroup per matrix, stopped when the
+//     Frobenius norm of the unreduced block is <= tol or at max_rank; used for
+//     the small truncation factors too large for the register-resident
+//     qrcp_reg_kernel.  Each of the 8 waves owns a set of columns and keeps
+//     two column slices in registers during a Householder application.
+//   * the Gaussian sketch matrix (Philox4x32-10 + Box-Muller);
+//   * a batched block copy.
 #include "kernels.h"
 #include "compress.h"
 
@@ -34,6 +29,9 @@ __device__ inline double wave_sum(double v) {
 // (2) every live column is reflected and its norm over rows > t recomputed
 // exactly; the per-wave partial sums and maxima of those norms feed the next
 // step's stopping test and pivot choice.  Three barriers per step.
+// RPL: rows per lane (m <= 64 RPL); CB: columns a wave reflects at once (their
+// loads are in flight together: the step's latency is q / (8 CB) round trips).
+template <int RPL, int CB>
 __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __restrict__ tasks) {
   const QrcpTask tk = tasks[blockIdx.x];
   __shared__ double nrm[kQrMaxCols];
@@ -50,14 +48,13 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
   const int m = tk.m, q = tk.q;
   double* Y = tk.Y;
   const int64_t ld = tk.ldy;
-  if (m <= 0 || q <= 0) {
+  if (m <= 0 || q <= 0 || m > 64 * RPL || q > kQrMaxCols) {
     if (tid == 0) {
       if (tk.rank) *tk.rank = 0;
-      if (tk.flag) *tk.flag = 0;
+      if (tk.flag) *tk.flag = (m > 0 && q > 0) ? 1 : 0;
     }
     return;
   }
-  constexpr int RPL = kQrMaxRows / 64;   // rows per lane
 
   // initial norms and per-wave partials
   {
@@ -83,7 +80,7 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
   const double tol2 = tk.tol * tk.tol;
   int t = 0;
   for (; t < tmax; ++t) {
-    // every thread reduces the 16 wave partials identically
+    // every thread reduces the wave partials identically
     double total = 0.0, best = -1.0;
     int p = 0x7fffffff;
 #pragma unroll
@@ -126,54 +123,54 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
     if (r2 < m) { const double v = x2 * sc; vs[r2] = v; colp[r2] = v; }
     if (tid == 0) tau[t] = ta;
     __syncthreads();
-    // reflect the live columns, two per wave at a time
+    // reflect the live columns, CB per wave at a time
+    double vv[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int rr = t + lane + 64 * i;
+      vv[i] = rr < m ? vs[rr] : 0.0;
+    }
     double ls = 0.0, lm = -1.0;
     int li = 0x7fffffff;
-    for (int c0 = wv; c0 < q; c0 += 2 * kQrWaves) {
-      const int c1 = c0 + kQrWaves;
-      const bool a0 = (step_of[c0] > t) && (c0 != p);
-      const bool a1 = (c1 < q) && (step_of[c1] > t) && (c1 != p);
-      if (!a0 && !a1) continue;
-      double* y0 = Y + (int64_t)c0 * ld;
-      double* y1 = Y + (int64_t)(a1 ? c1 : c0) * ld;
-      double v0[RPL], v1[RPL];
-      double w0 = 0.0, w1 = 0.0;
+    for (int c0 = wv; c0 < q; c0 += CB * kQrWaves) {
+      double v[CB][RPL];
+      bool act[CB];
+      double w[CB];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int rr = t + lane + 64 * i;
-        const bool in = rr < m;
-        v0[i] = (in && a0) ? y0[rr] : 0.0;
-        v1[i] = (in && a1) ? y1[rr] : 0.0;
-        const double vv = in ? vs[rr] : 0.0;
-        w0 += vv * v0[i];
-        w1 += vv * v1[i];
-      }
-      w0 = wave_sum(w0) * ta;
-      w1 = wave_sum(w1) * ta;
-      double s0 = 0.0, s1 = 0.0;
+      for (int b = 0; b < CB; ++b) {
+        const int c = c0 + b * kQrWaves;
+        act[b] = (c < q) && (step_of[c] > t) && (c != p);
+        const double* yc = Y + (int64_t)(act[b] ? c : c0) * ld;
+        w[b] = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int rr = t + lane + 64 * i;
-        if (rr < m) {
-          const double vv = vs[rr];
-          const double n0 = v0[i] - w0 * vv;
-          const double n1 = v1[i] - w1 * vv;
-          if (a0) y0[rr] = n0;
-          if (a1) y1[rr] = n1;
-          if (rr > t) { s0 += n0 * n0; s1 += n1 * n1; }
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = t + lane + 64 * i;
+          v[b][i] = (act[b] && rr < m) ? yc[rr] : 0.0;
+          w[b] += vv[i] * v[b][i];
         }
       }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
-      if (a0) {
-        if (lane == 0) nrm[c0] = s0;
-        ls += s0;
-        if (s0 > lm || (s0 == lm && c0 < li)) { lm = s0; li = c0; }
-      }
-      if (a1) {
-        if (lane == 0) nrm[c1] = s1;
-        ls += s1;
-        if (s1 > lm || (s1 == lm && c1 < li)) { lm = s1; li = c1; }
+#pragma unroll
+      for (int b = 0; b < CB; ++b) w[b] = wave_sum(w[b]) * ta;
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int c = c0 + b * kQrWaves;
+        double* yc = Y + (int64_t)(act[b] ? c : c0) * ld;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = t + lane + 64 * i;
+          if (rr < m) {
+            const double nv = v[b][i] - w[b] * vv[i];
+            if (act[b]) yc[rr] = nv;
+            if (rr > t) s += nv * nv;
+          }
+        }
+        s = wave_sum(s);
+        if (act[b]) {
+          if (lane == 0) nrm[c] = s;
+          ls += s;
+          if (s > lm || (s == lm && c < li)) { lm = s; li = c; }
+        }
       }
     }
     if (lane == 0) { wsum[wv] = ls; wmax[wv] = lm; widx[wv] = li; }
@@ -208,32 +205,39 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
     for (int rr = st + tid; rr < m; rr += kQrThreads) vs[rr] = (rr == st) ? 1.0 : vcol[rr];
     __syncthreads();
     const double ta = tau[st];
-    for (int c0 = st + wv; c0 < rank; c0 += 2 * kQrWaves) {
-      const int c1 = c0 + kQrWaves;
-      const bool a1 = c1 < rank;
-      double* y0 = Q + (int64_t)c0 * ldq;
-      double* y1 = Q + (int64_t)(a1 ? c1 : c0) * ldq;
-      double v0[RPL], v1[RPL];
-      double w0 = 0.0, w1 = 0.0;
+    double vv[RPL];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int rr = st + lane + 64 * i;
-        const bool in = rr < m;
-        v0[i] = in ? y0[rr] : 0.0;
-        v1[i] = (in && a1) ? y1[rr] : 0.0;
-        const double vv = in ? vs[rr] : 0.0;
-        w0 += vv * v0[i];
-        w1 += vv * v1[i];
+    for (int i = 0; i < RPL; ++i) {
+      const int rr = st + lane + 64 * i;
+      vv[i] = rr < m ? vs[rr] : 0.0;
+    }
+    for (int c0 = st + wv; c0 < rank; c0 += CB * kQrWaves) {
+      double v[CB][RPL];
+      double w[CB];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int c = c0 + b * kQrWaves;
+        const bool a = c < rank;
+        const double* yc = Q + (int64_t)(a ? c : c0) * ldq;
+        w[b] = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = st + lane + 64 * i;
+          v[b][i] = (a && rr < m) ? yc[rr] : 0.0;
+          w[b] += vv[i] * v[b][i];
+        }
       }
-      w0 = wave_sum(w0) * ta;
-      w1 = wave_sum(w1) * ta;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int rr = st + lane + 64 * i;
-        if (rr < m) {
-          const double vv = vs[rr];
-          y0[rr] = v0[i] - w0 * vv;
-          if (a1) y1[rr] = v1[i] - w1 * vv;
+      for (int b = 0; b < CB; ++b) w[b] = wave_sum(w[b]) * ta;
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int c = c0 + b * kQrWaves;
+        if (c >= rank) continue;
+        double* yc = Q + (int64_t)c * ldq;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int rr = st + lane + 64 * i;
+          if (rr < m) yc[rr] = v[b][i] - w[b] * vv[i];
         }
       }
     }
@@ -241,9 +245,15 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
   }
 }
 
-hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s) {
+// Tasks are launched with the smallest row capacity that fits the largest m.
+hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s, int max_m) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(qrcp_kernel, dim3((unsigned)count), dim3(kQrThreads), 0, s, d_tasks);
+  if (max_m <= 256)
+    hipLaunchKernelGGL((qrcp_kernel<4, 8>), dim3((unsigned)count), dim3(kQrThreads), 0, s, d_tasks);
+  else if (max_m <= 512)
+    hipLaunchKernelGGL((qrcp_kernel<8, 6>), dim3((unsigned)count), dim3(kQrThreads), 0, s, d_tasks);
+  else
+    hipLaunchKernelGGL((qrcp_kernel<16, 3>), dim3((unsigned)count), dim3(kQrThreads), 0, s, d_tasks);
   return hipGetLastError();
 }
 

@@ -152,14 +152,26 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
   const int wn = w / WM;
 
   // XCD-aware remap of the 1-D grid (padded to a multiple of kXcds).
-  const int64_t total = g.gx * g.gy;
+  const bool flat = g.batch.tile_item != nullptr;
+  const int64_t total = flat ? g.batch.ntiles : g.gx * g.gy;
   const int64_t per = (total + kXcds - 1) / kXcds;
   const int64_t wid = blockIdx.x;
   const int64_t logical = (wid % kXcds) * per + wid / kXcds;
   if (logical >= total) return;
-  const int64_t tm = logical / g.gy;
-  const int64_t tn = logical - tm * g.gy;
-  const int z = blockIdx.y;
+  int z;
+  int64_t tm, tn;
+  if (flat) {
+    z = g.batch.tile_item[logical];
+    const int64_t local = logical - g.batch.tile_first[z];
+    const int64_t nz = g.batch.n_of ? g.batch.n_of[z] : g.N;
+    const int64_t gyz = (nz + BN - 1) / BN;
+    tm = local / gyz;
+    tn = local - tm * gyz;
+  } else {
+    z = blockIdx.y;
+    tm = logical / g.gy;
+    tn = logical - tm * g.gy;
+  }
 
   int64_t M = g.M, N = g.N;
   int64_t Kb[2] = {g.seg[0].K, g.nseg > 1 ? g.seg[1].K : 0};
@@ -170,7 +182,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
     const int64_t chunk = (g.kt_total + g.splitk - 1) / g.splitk;
     ks = z * chunk;
     ke = ks + chunk < g.kt_total ? ks + chunk : g.kt_total;
-  } else if (g.batch.count > 1 || g.batch.a_off || g.batch.m_of) {
+  } else if (g.batch.count > 1 || g.batch.a_off || g.batch.m_of || flat) {
     c_off = g.batch.c_off ? g.batch.c_off[z] : z * g.batch.c_bstride;
     grow0 += z * g.ep.grow_bstride;
     for (int s = 0; s < g.nseg; ++s) {
@@ -300,7 +312,8 @@ static hipError_t run(GemmArgs& g, int zdim, hipStream_t s) {
       if (o->layout == kPanels && (o->nb % BK != 0 || o->c0 % BK != 0)) return hipErrorInvalidValue;
   g.gx = (g.M + BM - 1) / BM;
   g.gy = (g.N + BN - 1) / BN;
-  const int64_t total = g.gx * g.gy;
+  if (g.batch.tile_item) zdim = 1;
+  const int64_t total = g.batch.tile_item ? g.batch.ntiles : g.gx * g.gy;
   const int64_t grid = ((total + kXcds - 1) / kXcds) * kXcds;
   if (grid > 0x7fffffff || zdim > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, BK, PAD, EPI, DB>), dim3((unsigned)grid, (unsigned)zdim),
@@ -355,6 +368,12 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
   g.work = work;
   const int zdim = splitk > 1 ? splitk : g.batch.count;
   hipError_t e;
+  if (g.batch.tile_item) {   // the tile list was built for exactly these tile sizes
+    const int key = tile_m * 1000 + tile_n;
+    if (key != 32032 && key != 32064 && key != 32128 && key != 64032 && key != 64064 && key != 64128 &&
+        key != 128032 && key != 128064 && key != 128128)
+      return hipErrorInvalidValue;
+  }
   if (tile_m || tile_n) {
     // hinted small tiles (batched low-rank products): four waves, one LDS stage
     const int bm = tile_m ? tile_m : 128, bn = tile_n ? tile_n : 128;

@@ -25,6 +25,7 @@
 // register i / 4.
 #include "kernels.h"
 #include "compress.h"
+#include "wave.h"
 
 namespace tlrk {
 
@@ -39,47 +40,6 @@ constexpr int LDP = kQrMaxRows + 2;     // LDS panel stride (2 mod 32 doubles: c
 constexpr int MB = kQrMaxRows / (NW * 16);   // 16-row blocks per wave
 constexpr int RS = 16 * 17;             // per-wave slot of `red`: a 16 x 17 tile or a 16 x 16 partial
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Reduces N (16 or 32) per-lane partial sums over the wave: halving steps
-// exchange half of the remaining entries with lane ^ OFF (OFF = 32, 16, ...),
-// then the last steps add across the remaining lanes.  Lane l ends with the
-// total of entry (l >> (6 - log2 N)) & (N - 1).  Fewer shuffles than N
-// separate reductions; every index is a compile-time constant, so the array
-// stays in registers.
-template <int HALF, int OFF>
-struct BflyStep {
-  template <int N>
-  __device__ static void run(double (&v)[N], int lane) {
-    const bool hi = (lane & OFF) != 0;
-#pragma unroll
-    for (int i = 0; i < HALF; ++i) {
-      const double keep = hi ? v[i + HALF] : v[i];
-      const double send = hi ? v[i] : v[i + HALF];
-      v[i] = keep + __shfl_xor(send, OFF, 64);
-    }
-    BflyStep<HALF / 2, OFF / 2>::run(v, lane);
-  }
-};
-template <int OFF>
-struct BflyStep<0, OFF> {
-  template <int N>
-  __device__ static void run(double (&)[N], int) {}
-};
-
-template <int N>
-__device__ inline double bfly(double (&v)[N], int lane) {
-  static_assert(N == 16 || N == 32, "bfly: N must be 16 or 32");
-  BflyStep<N / 2, 32>::run(v, lane);
-  double r = v[0];
-#pragma unroll
-  for (int o = 32 / N; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-  return r;
-}
-
 __device__ inline d4 mfma(double x, double y, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
 
 // Householder vector entry V[r][c] of panel c0 (unit lower trapezoidal).
@@ -88,12 +48,6 @@ __device__ inline double vval_lds(const double* P, int r, int c, int mm, bool li
   return r == c ? 1.0 : P[c * LDP + r];
 }
 
-__device__ inline double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
 // One trailing-update round on the 16 columns col0.. of M (rows c0.., mm of
 // them; ncol columns in all): M -= V op(T) (V^T M), op(T) = T^T (applying
@@ -237,7 +191,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
       if (c0 + c < nref) {
         const double x0 = a0[c], x1 = a1[c];
         double sq = (r0 > c ? x0 * x0 : 0.0) + x1 * x1;
-        sq = wave_sum(sq);
+        sq = wave::sum(sq);
         if (lane == 0) nred[w] = sq;
         if (tid == c) sh_alpha = x0;
         __syncthreads();
@@ -263,7 +217,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
           double part[16];
 #pragma unroll
           for (int k = 0; k < 16; ++k) part[k] = (k > c) ? v0 * a0[k] + v1 * a1[k] : 0.0;
-          const double tot = bfly<16>(part, lane);
+          const double tot = wave::bfly<16>(part, lane);
           if ((lane & 3) == 0) dred[w * PB + ((lane >> 2) & 15)] = tot;
           __syncthreads();
           double d = 0.0;
@@ -273,7 +227,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
 #pragma unroll
           for (int k = 0; k < 16; ++k)
             if (k > c) {
-              const double dk = readlane_d(d, k);
+              const double dk = wave::read(d, k);
               a0[k] -= dk * v0;
               a1[k] -= dk * v1;
             }
@@ -486,10 +440,10 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
     double part[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) part[j] = (j < RJ) ? f(j) : 0.0;
-    lo = bfly<16>(part, lane);
+    lo = wave::bfly<16>(part, lane);
 #pragma unroll
     for (int j = 0; j < 16; ++j) part[j] = (16 + j < RJ) ? f(16 + j) : 0.0;
-    hi = bfly<16>(part, lane);
+    hi = wave::bfly<16>(part, lane);
   };
   // per-wave norm statistics of the live columns over rows > t (t = -1: all)
   auto norms = [&](int t) {
@@ -514,13 +468,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
         if (v > mv || (v == mv && ce < mi)) { mv = v; mi = ce; }
       }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double om = __shfl_xor(mv, o, 64);
-      const int oi = __shfl_xor(mi, o, 64);
-      if (om > mv || (om == mv && oi < mi)) { mv = om; mi = oi; }
-      sv += __shfl_xor(sv, o, 64);
-    }
+    wave::max_sum(mv, mi, sv, lane);
     if (lane == 0) { wsum[w] = sv; wmax[w] = mv; widx[w] = mi; }
   };
   norms(-1);
@@ -552,12 +500,12 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
 #pragma unroll
       for (int i = 0; i < RI; ++i)
         if (lane + 64 * i > t) sq += x[i] * x[i];
-      sq = wave_sum(sq);
+      sq = wave::sum(sq);
       double xs = x[0];
 #pragma unroll
       for (int i = 1; i < RI; ++i)
         if ((t >> 6) == i) xs = x[i];
-      const double alpha = __shfl(xs, t & 63, 64);
+      const double alpha = wave::read(xs, t & 63);
       double ta, beta, sc;
       if (sq == 0.0) {
         ta = 0.0; beta = alpha; sc = 0.0;
@@ -596,7 +544,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
     }, lo, hi);
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
-      const double d = ta * readlane_d(j < 16 ? lo : hi, 4 * (j & 15));
+      const double d = ta * wave::read(j < 16 ? lo : hi, 4 * (j & 15));
 #pragma unroll
       for (int i = 0; i < RI; ++i) a[j][i] -= d * vv[i];
     }
@@ -650,7 +598,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
     }, lo, hi);
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
-      const double d = ta * readlane_d(j < 16 ? lo : hi, 4 * (j & 15));
+      const double d = ta * wave::read(j < 16 ? lo : hi, 4 * (j & 15));
 #pragma unroll
       for (int i = 0; i < RI; ++i) qa[j][i] -= d * vv[i];
     }

@@ -45,6 +45,13 @@ struct GemmBatch {
   const int64_t* a_off;      // optional device arrays: per-batch element offsets of
   const int64_t* b_off;      //   segment 0's A and B and of C (replace the strides)
   const int64_t* c_off;
+  // optional flat tile list (hinted tile sizes only): workgroup w computes
+  // tile w - tile_first[z] of batch z = tile_item[w]; ntiles in all.  Without
+  // it every batch gets the launch maximum's tile grid, most of it empty when
+  // the per-batch sizes vary.
+  const int* tile_item;
+  const int* tile_first;
+  int64_t ntiles;
 };
 
 // Returns hipErrorInvalidValue on bad shapes.  work (may be null) must hold

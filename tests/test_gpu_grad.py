@@ -84,7 +84,9 @@ def test_tlr_loglik_grad_value_equals_potrf_path():
     h.generate(xd, yd, th)
     h.potrf()
     ll, _, _ = h.loglik(zd)
-    assert ll == ll_g
+    # the second factorisation may sketch some tiles wider (its widths come
+    # from the first one's ranks), so the two agree to the compression accuracy
+    assert abs(ll - ll_g) <= 10 * eps * abs(ll)
 
 
 def test_tlr_gradient_with_dense_tiles():
