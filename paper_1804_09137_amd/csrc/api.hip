@@ -906,21 +906,21 @@ struct LRTerm {
 void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind) {
   const int nt = h->nt, nb = h->nb;
   const int nbj = tile_rows(h, j);
-  // padded K layout: for each term, for each k < j, a segment of pad16(rank_j(k))
+  // K layout: for each term, for each k < j, a segment of rank_j(k) columns
+  // (the GEMM takes any K, so segments are not padded)
   std::vector<int64_t> off((size_t)nterms * std::max(j, 1));
   int64_t R = 0, Ktrue = 0;
   for (int tm = 0; tm < nterms; ++tm)
     for (int k = 0; k < j; ++k) {
       off[(size_t)tm * j + k] = R;
       const int r = terms[tm].Fj->rk[tid_of(h, j, k)];
-      R += pad16(r);
+      R += r;
       Ktrue += r;
     }
   const size_t e_urow = prof_mark(h);
-  // U_row (nb_j x R): zero, then copy the right factors of row j
+  // U_row (nb_j x R): the right factors of row j, side by side
   if (R > 0) {
     if ((int64_t)nb * R > h->urow_cap) NOMEM("row factor buffer");
-    HIPCHK(launch_fill(h->Urow, nb, nb, R, 0.0, h->s));
     int cnt = 0;
     for (int tm = 0; tm < nterms; ++tm)
       for (int k = 0; k < j; ++k)
@@ -962,7 +962,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       for (int tm = 0; tm < nterms; ++tm)
         for (int k = 0; k < j; ++k) {
           const int a = terms[tm].Fi->rk[tid_of(h, i1, k)];
-          xadd += (int64_t)(a > h->maxrank ? nb : h->maxrank) * pad16(terms[tm].Fj->rk[tid_of(h, j, k)]);
+          xadd += (int64_t)(a > h->maxrank ? nb : h->maxrank) * terms[tm].Fj->rk[tid_of(h, j, k)];
         }
       if (wrows * std::max<int64_t>(R, 1) > h->w_cap || xneed + xadd > h->x_cap) break;
       xneed += xadd;

@@ -17,48 +17,53 @@ __global__ void __launch_bounds__(256) potrf_small_kernel(double* __restrict__ A
   __shared__ double L[64][65];
   __shared__ double X[64][65];
   const int tid = threadIdx.x;
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e % w, k = e / w;
-    L[i][k] = (i >= k) ? A[(int64_t)k * lda + i] : 0.0;
-    X[i][k] = 0.0;
+  const int li = tid & 63;    // row handled by this lane
+  const int kq = tid >> 6;    // this wave's columns: k = kq + 4 s
+  for (int k = kq; k < w; k += 4) {
+    L[li][k] = (li < w && li >= k) ? A[(int64_t)k * lda + li] : 0.0;
+    X[li][k] = 0.0;
   }
   __syncthreads();
+  // right-looking: scale column c, then rank-1 update of the lower part
   for (int c = 0; c < w; ++c) {
     double d = L[c][c];
     const bool bad = !(d > 0.0);
     if (bad) d = 1.0;
-    const double s = sqrt(d);
-    __syncthreads();
+    const double sc = sqrt(d);
+    const double is = 1.0 / sc;
+    __syncthreads();   // every thread has read L[c][c]
     if (tid == 0) {
       if (bad) atomicMin(info, (unsigned long long)(row0 + c + 1));
-      L[c][c] = s;
+      L[c][c] = sc;
     }
-    const double is = 1.0 / s;
-    for (int i = c + 1 + tid; i < w; i += 256) L[i][c] *= is;
+    if (tid < 64 && li > c && li < w) L[li][c] *= is;
     __syncthreads();
-    // trailing update of columns c+1..w-1, lower part
-    const int rem = w - c - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = c + 1 + e % rem, k = c + 1 + e / rem;
-      if (i >= k) L[i][k] -= L[i][c] * L[k][c];
+    const double lic = (li > c && li < w) ? L[li][c] : 0.0;
+    for (int k = c + 1 + ((kq - c - 1) & 3); k < w; k += 4)
+      if (li >= k) L[li][k] -= lic * L[k][c];
+    __syncthreads();
+  }
+  // X = L^{-1} by rows: X[i][k] = (delta_ik - sum_{k <= t < i} L[i][t] X[t][k]) / L[i][i];
+  // the four waves split the sum over t, lane k owns column k
+  __shared__ double part[4][64];
+  for (int i = 0; i < w; ++i) {
+    const int k = li;
+    double acc = 0.0;
+    if (k < i)
+      for (int t = k + kq; t < i; t += 4) acc += L[i][t] * X[t][k];
+    part[kq][k] = acc;
+    __syncthreads();
+    if (tid < 64 && k <= i) {
+      const double s = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+      X[i][k] = ((k == i ? 1.0 : 0.0) - s) / L[i][i];
     }
     __syncthreads();
   }
-  // inverse: column k of X solves L x = e_k; one thread per column
-  if (tid < w) {
-    const int k = tid;
-    X[k][k] = 1.0 / L[k][k];
-    for (int i = k + 1; i < w; ++i) {
-      double acc = 0.0;
-      for (int t = k; t < i; ++t) acc += L[i][t] * X[t][k];
-      X[i][k] = -acc / L[i][i];
+  for (int k = kq; k < w; k += 4) {
+    if (li < w) {
+      if (li >= k) A[(int64_t)k * lda + li] = L[li][k];
+      Inv[(int64_t)k * ldi + li] = (li >= k) ? X[li][k] : 0.0;
     }
-  }
-  __syncthreads();
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e % w, k = e / w;
-    if (i >= k) A[(int64_t)k * lda + i] = L[i][k];
-    Inv[(int64_t)k * ldi + i] = (i >= k) ? X[i][k] : 0.0;
   }
 }
 

@@ -400,6 +400,22 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
     e = run<32, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s);
   } else if (M <= 64) {
     e = run<64, 128, 2, 2, 32, 4, 0, 1>(g, zdim, s);
+  } else if (splitk == 1 && g.batch.count == 1 && !g.batch.m_of && N % 128 != 0 && N % 128 <= 64) {
+    // N = 128 q + r (r <= 64): 128 x 128 tiles over the first 128 q columns,
+    // 128 x r-wide tiles over the rest, instead of a mostly idle last tile column
+    const int64_t n1 = N - N % 128;
+    g.N = n1;
+    e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s);
+    if (e != hipSuccess) return e;
+    GemmArgs g2 = g;
+    g2.N = N - n1;
+    for (int i = 0; i < g2.nseg; ++i) g2.seg[i].B.r0 += n1;
+    g2.C = C + n1 * ldc;
+    g2.ep.gcol0 += n1;
+    if (N - n1 <= 32)
+      e = run<128, 32, 2, 2, 32, 4, 0, 0>(g2, zdim, s);
+    else
+      e = run<128, 64, 2, 2, 32, 4, 0, 1>(g2, zdim, s);
   } else {
     e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s);
   }
