@@ -91,13 +91,14 @@ typedef struct {
 
 /* Kernel classes timed by tlr_profile (each a group of launches). */
 typedef enum {
-  TLR_K_UPDATE = 0,    /* left-looking column update GEMM with the Matern generation epilogue */
+  TLR_K_UPDATE = 0,    /* left-looking column update GEMM C -= W U_row^T (its own kernel instances) */
   TLR_K_LOWRANK = 1,   /* low-rank products: W = U (V^T V) builds, low-rank TRSM, tangent corrections */
-  TLR_K_COMPRESS = 2,  /* sketch GEMM, pivoted Householder QRs, projection, U assembly */
+  TLR_K_COMPRESS = 2,  /* sketch GEMM, blocked Householder QRs, pivoted QR of the small factor, projection, U */
   TLR_K_DIAG = 3,      /* diagonal tile POTRF + inverse (+ tangent of the diagonal step) */
   TLR_K_SOLVE = 4,     /* forward and backward solves */
   TLR_K_GRADQ = 5,     /* a^T dSigma a over all pairs */
-  TLR_K_COUNT = 6
+  TLR_K_GEN = 6,       /* Matern (and dMatern/dbeta) generation of the column blocks */
+  TLR_K_COUNT = 7
 } tlr_kclass;
 
 typedef struct {

@@ -52,7 +52,7 @@ class KStat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
-KCLASSES = ["update", "lowrank", "compress", "diag", "solve", "gradq"]
+KCLASSES = ["update", "lowrank", "compress", "diag", "solve", "gradq", "gen"]
 
 EXPORTS = ["tlr_create", "tlr_destroy", "tlr_generate", "tlr_compress", "tlr_potrf", "tlr_loglik",
            "tlr_loglik_grad", "tlr_get_ranks", "tlr_get_info", "tlr_get_tile", "tlr_covariance_block",

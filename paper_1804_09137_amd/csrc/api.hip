@@ -345,7 +345,7 @@ int choose_splitk(const tlr_handle_s* h, int64_t M, int64_t N, int64_t K) {
 // the launch maximum's tile grid per item.
 void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
           const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false, int tm = 0, int tn = 0,
-          const int* mh = nullptr, const int* nh = nullptr) {
+          const int* mh = nullptr, const int* nh = nullptr, int tag = 0) {
   GemmBatch fb;
   if (b && mh && nh && tm && tn) {
     int64_t tot = 0;
@@ -376,7 +376,7 @@ void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, 
     for (int i = 0; i < nseg; ++i) K += segs[i].K;
     sk = choose_splitk(h, M, N, K);
   }
-  HIPCHK(launch_gemm(M, N, nseg, segs, C, ldc, ep, b, sk, sk > 1 ? h->skw : nullptr, h->s, tm, tn));
+  HIPCHK(launch_gemm(M, N, nseg, segs, C, ldc, ep, b, sk, sk > 1 ? h->skw : nullptr, h->s, tm, tn, tag));
 }
 
 // ---------------------------------------------------------------------------
@@ -1059,9 +1059,14 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     cs.A = op_contig(h->Wb, ldw, 0, 0);
     cs.B = op_contig(h->Urow, nb, 0, 0);
     cs.K = R;
+    // Matern generation of the block, then C -= W U_row^T
+    double* cblk = out + (int64_t)(i0 - j) * nb;
+    const size_t eg = prof_mark(h);
+    HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)i0 * nb, mrows, (int64_t)j * nb, nbj, cblk, h->n,
+                               epi_kind == kEpiDGenMinus, h->s));
+    prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
     const size_t e0 = prof_mark(h);
-    gemm(h, mrows, nbj, 1, &cs, out + (int64_t)(i0 - j) * nb, h->n,
-         epi_gen(h, epi_kind, (int64_t)i0 * nb, (int64_t)j * nb), nullptr, true);
+    gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr, 1);
     prof_add(h, TLR_K_UPDATE, e0, 2.0 * mrows * nbj * (double)Ktrue,
              8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + (double)mrows * nbj));
     i0 = i1;

@@ -12,16 +12,13 @@
 //   * a batched block copy.
 #include "kernels.h"
 #include "compress.h"
+#include "wave.h"
 
 namespace tlrk {
 
 constexpr int kQrThreads = 512;
 constexpr int kQrWaves = kQrThreads / 64;
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Column-pivoted Householder QR, one workgroup per matrix.  Columns are never
 // moved: piv[t] records the physical column chosen at step t and step_of[]
@@ -66,7 +63,7 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
         const double v = Y[(int64_t)c * ld + r];
         sacc += v * v;
       }
-      sacc = wave_sum(sacc);
+      sacc = wave::sum(sacc);
       if (lane == 0) nrm[c] = sacc;
       ls += sacc;
       if (sacc > lm || (sacc == lm && c < li)) { lm = sacc; li = c; }
@@ -99,7 +96,7 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
     if (r == t) sh_alpha = x;
     double sp = (r > t && r < m) ? x * x : 0.0;
     sp += (r2 < m) ? x2 * x2 : 0.0;
-    sp = wave_sum(sp);
+    sp = wave::sum(sp);
     if (lane == 0) red[wv] = sp;
     if (tid == 0) { piv[t] = p; step_of[p] = t; }
     __syncthreads();
@@ -150,7 +147,7 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
         }
       }
 #pragma unroll
-      for (int b = 0; b < CB; ++b) w[b] = wave_sum(w[b]) * ta;
+      for (int b = 0; b < CB; ++b) w[b] = wave::sum(w[b]) * ta;
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         const int c = c0 + b * kQrWaves;
@@ -165,7 +162,7 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
             if (rr > t) s += nv * nv;
           }
         }
-        s = wave_sum(s);
+        s = wave::sum(s);
         if (act[b]) {
           if (lane == 0) nrm[c] = s;
           ls += s;
@@ -228,7 +225,7 @@ __global__ void __launch_bounds__(kQrThreads) qrcp_kernel(const QrcpTask* __rest
         }
       }
 #pragma unroll
-      for (int b = 0; b < CB; ++b) w[b] = wave_sum(w[b]) * ta;
+      for (int b = 0; b < CB; ++b) w[b] = wave::sum(w[b]) * ta;
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         const int c = c0 + b * kQrWaves;

@@ -136,7 +136,7 @@ __device__ inline void epi_store(const GemmEpi& ep, double* C, int64_t ldc, int6
 
 // EPI = 0: linear epilogue only (fewer registers); 1: any epilogue kind.
 // DB = 1: two LDS stages, one barrier per K slice.
-template <int BM, int BN, int WM, int WN, int BK, int PAD, int EPI, int DB>
+template <int BM, int BN, int WM, int WN, int BK, int PAD, int EPI, int DB, int TAG>
 __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM / 16;
@@ -290,6 +290,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
   }
 }
 
+template <int TAG>
 __global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= g.M * g.N) return;
@@ -300,7 +301,8 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(GemmArgs g) {
   epi_store(g.ep, g.C, g.ldc, m, n, v, g.ep.grow0);
 }
 
-template <int BM, int BN, int WM, int WN, int BK = 32, int PAD = TLRK_GEMM_PAD, int EPI = 1, int DB = 0>
+template <int BM, int BN, int WM, int WN, int BK = 32, int PAD = TLRK_GEMM_PAD, int EPI = 1, int DB = 0,
+          int TAG = 0>
 static hipError_t run(GemmArgs& g, int zdim, hipStream_t s) {
   g.kt_total = 0;
   for (int i = 0; i < g.nseg; ++i) {
@@ -316,14 +318,15 @@ static hipError_t run(GemmArgs& g, int zdim, hipStream_t s) {
   const int64_t total = g.batch.tile_item ? g.batch.ntiles : g.gx * g.gy;
   const int64_t grid = ((total + kXcds - 1) / kXcds) * kXcds;
   if (grid > 0x7fffffff || zdim > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, BK, PAD, EPI, DB>), dim3((unsigned)grid, (unsigned)zdim),
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, BK, PAD, EPI, DB, TAG>), dim3((unsigned)grid, (unsigned)zdim),
                      dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
-                       const GemmEpi& ep_in, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
-                       int tile_m, int tile_n) {
+template <int TAG>
+static hipError_t launch_gemm_t(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
+                                const GemmEpi& ep_in, const GemmBatch* batch, int splitk, double* work,
+                                hipStream_t s, int tile_m, int tile_n) {
   if (M < 0 || N < 0 || nseg < 1 || nseg > 2 || splitk < 1) return hipErrorInvalidValue;
   if (M == 0 || N == 0) return hipSuccess;
   GemmEpi ep = ep_in;
@@ -378,34 +381,34 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
     // hinted small tiles (batched low-rank products): four waves, one LDS stage
     const int bm = tile_m ? tile_m : 128, bn = tile_n ? tile_n : 128;
     switch (bm * 1000 + bn) {
-      case 32032: e = run<32, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 32064: e = run<32, 64, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 32128: e = run<32, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 64032: e = run<64, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 64064: e = run<64, 64, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 64128: e = run<64, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 128032: e = run<128, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      case 128064: e = run<128, 64, 2, 2, 32, 4, 0, 0>(g, zdim, s); break;
-      default: e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s); break;
+      case 32032: e = run<32, 32, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 32064: e = run<32, 64, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 32128: e = run<32, 128, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 64032: e = run<64, 32, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 64064: e = run<64, 64, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 64128: e = run<64, 128, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 128032: e = run<128, 32, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      case 128064: e = run<128, 64, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s); break;
+      default: e = run<128, 128, 2, 4, 32, 4, 0, 1, TAG>(g, zdim, s); break;
     }
   } else if (panels && !bk32) {
-    e = run<128, 128, 2, 4, 16, 4, 0, 1>(g, zdim, s);
+    e = run<128, 128, 2, 4, 16, 4, 0, 1, TAG>(g, zdim, s);
   } else if (M >= 2048 && N >= 1024) {
-    e = run<256, 128, 4, 2, 16, 4, 0, 1>(g, zdim, s);
+    e = run<256, 128, 4, 2, 16, 4, 0, 1, TAG>(g, zdim, s);
   } else if (N <= 32) {
-    e = run<128, 32, 2, 2, 32, 4, 0, 0>(g, zdim, s);
+    e = run<128, 32, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s);
   } else if (N <= 64) {
-    e = run<128, 64, 2, 2, 32, 4, 0, 1>(g, zdim, s);
+    e = run<128, 64, 2, 2, 32, 4, 0, 1, TAG>(g, zdim, s);
   } else if (M <= 32) {
-    e = run<32, 128, 2, 2, 32, 4, 0, 0>(g, zdim, s);
+    e = run<32, 128, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s);
   } else if (M <= 64) {
-    e = run<64, 128, 2, 2, 32, 4, 0, 1>(g, zdim, s);
+    e = run<64, 128, 2, 2, 32, 4, 0, 1, TAG>(g, zdim, s);
   } else if (splitk == 1 && g.batch.count == 1 && !g.batch.m_of && N % 128 != 0 && N % 128 <= 64) {
     // N = 128 q + r (r <= 64): 128 x 128 tiles over the first 128 q columns,
     // 128 x r-wide tiles over the rest, instead of a mostly idle last tile column
     const int64_t n1 = N - N % 128;
     g.N = n1;
-    e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s);
+    e = run<128, 128, 2, 4, 32, 4, 0, 1, TAG>(g, zdim, s);
     if (e != hipSuccess) return e;
     GemmArgs g2 = g;
     g2.N = N - n1;
@@ -413,16 +416,23 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
     g2.C = C + n1 * ldc;
     g2.ep.gcol0 += n1;
     if (N - n1 <= 32)
-      e = run<128, 32, 2, 2, 32, 4, 0, 0>(g2, zdim, s);
+      e = run<128, 32, 2, 2, 32, 4, 0, 0, TAG>(g2, zdim, s);
     else
-      e = run<128, 64, 2, 2, 32, 4, 0, 1>(g2, zdim, s);
+      e = run<128, 64, 2, 2, 32, 4, 0, 1, TAG>(g2, zdim, s);
   } else {
-    e = run<128, 128, 2, 4, 32, 4, 0, 1>(g, zdim, s);
+    e = run<128, 128, 2, 4, 32, 4, 0, 1, TAG>(g, zdim, s);
   }
   if (e != hipSuccess || splitk == 1) return e;
   const int64_t tot = M * N;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(splitk_reduce_kernel<TAG>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g);
   return hipGetLastError();
+}
+
+hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
+                       const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
+                       int tile_m, int tile_n, int tag) {
+  if (tag == 1) return launch_gemm_t<1>(M, N, nseg, segs, C, ldc, ep, batch, splitk, work, s, tile_m, tile_n);
+  return launch_gemm_t<0>(M, N, nseg, segs, C, ldc, ep, batch, splitk, work, s, tile_m, tile_n);
 }
 
 }  // namespace tlrk

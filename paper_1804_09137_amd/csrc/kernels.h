@@ -59,8 +59,10 @@ struct GemmBatch {
 // tile_m / tile_n (32, 64 or 128; 0 = by M and N) choose the workgroup tile:
 // batched calls whose per-batch sizes are far below the launch maxima use
 // small tiles so that the workgroups of small problems stay short.
+// tag 1 launches separately named kernel instances (same code), so that a
+// kernel trace tells the left-looking column-update GEMMs apart.
 hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
                        const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
-                       int tile_m = 0, int tile_n = 0);
+                       int tile_m = 0, int tile_n = 0, int tag = 0);
 
 }  // namespace tlrk
