@@ -40,7 +40,12 @@ inline int64_t pad16(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct tlr_handle_s {
   tlr_opts o{};
-  hipStream_t s = nullptr;
+  hipStream_t s = nullptr;        // the stream work is issued on (s_main, or s_side inside SideStream)
+  hipStream_t s_main = nullptr;   // the caller's stream
+  hipStream_t s_side = nullptr;   // tangent chain of the lockstep factorisation (gradient handles)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // second set of update scratch for the side stream (same capacities)
+  double *Wb2 = nullptr, *Xb2 = nullptr, *Urow2 = nullptr, *skw2 = nullptr, *tw2 = nullptr;
   int device = 0;
   int64_t n = 0;
   int nb = 0, nt = 0, maxrank = 0, smax = 0;
@@ -236,9 +241,30 @@ void meta_reset(tlr_handle_s* h) {
 }
 void prof_harvest(tlr_handle_s* h);
 void sync(tlr_handle_s* h) {
-  HIPCHK(hipStreamSynchronize(h->s));
+  HIPCHK(hipStreamSynchronize(h->s_main));
+  if (h->s_side) HIPCHK(hipStreamSynchronize(h->s_side));
   prof_harvest(h);
 }
+
+// Issue on the side stream with the second scratch set until destroyed.
+struct SideStream {
+  tlr_handle_s* h;
+  explicit SideStream(tlr_handle_s* hh) : h(hh) {
+    swap_sets();
+    h->s = h->s_side;
+  }
+  ~SideStream() {
+    h->s = h->s_main;
+    swap_sets();
+  }
+  void swap_sets() {
+    std::swap(h->Wb, h->Wb2);
+    std::swap(h->Xb, h->Xb2);
+    std::swap(h->Urow, h->Urow2);
+    std::swap(h->skw, h->skw2);
+    std::swap(h->tw, h->tw2);
+  }
+};
 
 // Make room for a group of metadata takes: when the staging buffers would
 // overflow, wait for the stream (every queued copy has then been consumed)
@@ -1330,14 +1356,24 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   }
   for (int j = 0; j < nt; ++j) {
     std::vector<ColumnJob> jobs;
-    if (j + 1 < nt) {
-      primal_column(j + 1);
-      jobs.push_back(primal_job(j + 1));
+    const bool side = tangent && h->s_side;
+    if (side) {  // the two chains up to the shared compression run concurrently
+      HIPCHK(hipEventRecord(h->ev_fork, h->s_main));
+      HIPCHK(hipStreamWaitEvent(h->s_side, h->ev_fork, 0));
     }
+    if (j + 1 < nt) primal_column(j + 1);
     if (tangent) {
-      tangent_column(j);
-      jobs.push_back(tangent_job(j));
+      if (side) {
+        SideStream ss(h);
+        tangent_column(j);
+        HIPCHK(hipEventRecord(h->ev_join, h->s_side));
+      } else {
+        tangent_column(j);
+      }
     }
+    if (side) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_join, 0));
+    if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
+    if (tangent) jobs.push_back(tangent_job(j));
     finish(jobs);
   }
   family_upload(h, P);
@@ -1444,7 +1480,10 @@ tlr_status guarded(tlr_handle_s* h, F&& f) {
       h->info.bad_tile_i = h->bad_i;
       h->info.bad_tile_j = h->bad_j;
     }
-    if (h && e.st != TLR_ENOMEM) (void)hipStreamSynchronize(h->s);
+    if (h && e.st != TLR_ENOMEM) {
+      (void)hipStreamSynchronize(h->s_main);
+      if (h->s_side) (void)hipStreamSynchronize(h->s_side);
+    }
     return e.st;
   } catch (const std::bad_alloc&) {
     return TLR_ENOMEM;
@@ -1452,7 +1491,15 @@ tlr_status guarded(tlr_handle_s* h, F&& f) {
 }
 
 void free_all(tlr_handle_s* h) {
-  if (h->s) (void)hipStreamSynchronize(h->s);
+  if (h->s_main) (void)hipStreamSynchronize(h->s_main);
+  if (h->s_side) {
+    (void)hipStreamSynchronize(h->s_side);
+    (void)hipStreamDestroy(h->s_side);
+    h->s_side = nullptr;
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  h->ev_fork = h->ev_join = nullptr;
   for (void* p : h->dev_allocs) (void)hipFree(p);
   for (void* p : h->host_allocs) (void)hipHostFree(p);
   for (hipEvent_t& e : h->ev)
@@ -1493,7 +1540,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
   if (!h) return TLR_ENOMEM;
   tlr_status st = guarded(h, [&]() -> tlr_status {
     h->o = *o;
-    h->s = (hipStream_t)stream;
+    h->s = h->s_main = (hipStream_t)stream;
     HIPCHK(hipGetDevice(&h->device));
     h->n = o->n;
     h->nb = o->nb;
@@ -1588,6 +1635,17 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * nb * nb);
       h->Wb = dalloc<double>(h, h->w_cap);
       h->Xb = dalloc<double>(h, h->x_cap);
+      if (h->grad) {
+        // the tangent column of the lockstep runs on its own stream with its own scratch
+        HIPCHK(hipStreamCreateWithFlags(&h->s_side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        h->Wb2 = dalloc<double>(h, h->w_cap);
+        h->Xb2 = dalloc<double>(h, h->x_cap);
+        h->Urow2 = dalloc<double>(h, h->urow_cap);
+        h->skw2 = dalloc<double>(h, h->sk_cap);
+        h->tw2 = dalloc<double>(h, 64 * nb + 3 * nb * nb);
+      }
       h->lm_cap = std::max<int64_t>(1 << 16, 16 * nt * nt * nterms + 64 * nt);
       h->im_cap = std::max<int64_t>(1 << 20, 64 * nt * nt * nterms + 64 * nt);   // + flat tile lists
       h->im_d = dalloc<int>(h, h->im_cap);
