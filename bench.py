@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--dense-nb", type=int, default=512)
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--maxrank", type=int, default=256)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_updates"],
+                    help="fp32_updates: the column-update products on FP32 MFMA (meant for eps >= 1e-6)")
     ap.add_argument("--beta", type=float, default=0.1)
     ap.add_argument("--nu", type=float, default=0.5)
     ap.add_argument("--no-dense", action="store_true")
@@ -133,7 +135,8 @@ def main():
     xd, yd, ed = (torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (x, y, eps_v))
 
     out = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.prec == "fp64" else "f64 (f32 update products)",
            "data": "synthetic"}
     dense = None
     if args.z_white:
@@ -170,7 +173,7 @@ def main():
         torch.cuda.empty_cache()
 
     log(f"[bench] TLR handle n={n} nb={args.nb} eps={args.eps} maxrank={args.maxrank}")
-    ht = P.Handle(n, args.nb, tol=args.eps, maxrank=args.maxrank, want_grad=True)
+    ht = P.Handle(n, args.nb, tol=args.eps, maxrank=args.maxrank, want_grad=True, prec=args.prec)
     for w in range(args.warmup):
         ll, g = ht.loglik_grad(xd, yd, zd, th)
         log(f"[bench] warmup {w}: ll={ll:.10g} grad={g} factor {ht.info().t_factor_ms:.1f} ms")

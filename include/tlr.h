@@ -54,7 +54,13 @@ typedef enum {
 
 typedef enum {
   TLR_PREC_FP64 = 0,          /* all arithmetic in FP64 */
-  TLR_PREC_FP32_UPDATES = 1   /* TLR only: low-rank update products in FP32, everything else FP64 */
+  TLR_PREC_FP32_UPDATES = 1   /* TLR only: the column-update products C -= W U_row^T (most of the
+                                 update flops) on FP32 MFMA with FP32 operands; generation,
+                                 compression, POTRF, TRSM, solves and log-det stay FP64.  The
+                                 rounding of a densely accumulated update is a full-rank
+                                 perturbation of about 1e-7 of the update's magnitude, which the
+                                 compression keeps: ranks (and dense tiles) grow unless tol is
+                                 well above that level.  Accuracy is unaffected */
 } tlr_prec;
 
 /* tlr_opts.flags */

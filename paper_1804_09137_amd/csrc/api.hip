@@ -1092,7 +1092,8 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
                                epi_kind == kEpiDGenMinus, h->s));
     prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
     const size_t e0 = prof_mark(h);
-    gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr, 1);
+    gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
+         h->o.prec == TLR_PREC_FP32_UPDATES ? 2 : 1);
     prof_add(h, TLR_K_UPDATE, e0, 2.0 * mrows * nbj * (double)Ktrue,
              8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + (double)mrows * nbj));
     i0 = i1;

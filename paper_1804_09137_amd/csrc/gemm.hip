@@ -20,12 +20,15 @@
 // Workgroups are remapped so that the tiles sharing a row panel of A run
 // consecutively on one XCD (the 8 XCDs each have their own L2; hardware hands
 // workgroup w to XCD w mod 8).
+#include <type_traits>
+
 #include "kernels.h"
 #include "matern.h"
 
 namespace tlrk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcds = 8;
 #ifndef TLRK_GEMM_PAD
@@ -99,18 +102,17 @@ __device__ inline void load_slice(const Operand& o, const SliceAddr& sa, int64_t
   }
 }
 
-template <int ROWS, int BK, int PAD, int NT>
-__device__ inline void store_slice(int layout, double (*s)[ROWS + PAD], const double (&v)[ROWS * BK / NT],
-                                   int tid) {
+template <int ROWS, int BK, int PAD, int NT, class ST>
+__device__ inline void store_slice(int layout, ST (*s)[ROWS + PAD], const double (&v)[ROWS * BK / NT], int tid) {
   constexpr int NE = ROWS * BK / NT;
   if (layout == kContigT) {
     const int kk = tid % BK;
 #pragma unroll
-    for (int p = 0; p < NE; ++p) s[kk][tid / BK + (NT / BK) * p] = v[p];
+    for (int p = 0; p < NE; ++p) s[kk][tid / BK + (NT / BK) * p] = (ST)v[p];
   } else {
     const int r = tid % ROWS;
 #pragma unroll
-    for (int p = 0; p < NE; ++p) s[tid / ROWS + (NT / ROWS) * p][r] = v[p];
+    for (int p = 0; p < NE; ++p) s[tid / ROWS + (NT / ROWS) * p][r] = (ST)v[p];
   }
 }
 
@@ -136,14 +138,21 @@ __device__ inline void epi_store(const GemmEpi& ep, double* C, int64_t ldc, int6
 
 // EPI = 0: linear epilogue only (fewer registers); 1: any epilogue kind.
 // DB = 1: two LDS stages, one barrier per K slice.
+// TAG 2: the products in FP32 (v_mfma_f32_16x16x4f32, operands rounded to
+// FP32 when staged in LDS, FP32 accumulation within the launch), added to the
+// FP64 C.  Its output layout differs: D[i][j] in lane j + 16 (i / 4),
+// register i mod 4.
 template <int BM, int BN, int WM, int WN, int BK, int PAD, int EPI, int DB, int TAG>
 __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
+  constexpr bool F32 = TAG == 2;
+  using ST = typename std::conditional<F32, float, double>::type;
+  using AV = typename std::conditional<F32, f4, d4>::type;
   constexpr int NT = WM * WN * 64;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   constexpr int NS = DB ? 2 : 1;
-  __shared__ double sA[NS][BK][BM + PAD];
-  __shared__ double sB[NS][BK][BN + PAD];
+  __shared__ ST sA[NS][BK][BM + PAD];
+  __shared__ ST sB[NS][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -198,11 +207,11 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
   const int64_t m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
 
-  d4 acc[TM][TN];
+  AV acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = AV{0, 0, 0, 0};
 
   double va[BM * BK / NT], vb[BN * BK / NT];
   auto fetch = [&](int64_t t) {
@@ -221,7 +230,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
-      double a[TM], b[TN];
+      ST a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) a[i] = sA[buf][kr][wm * (BM / WM) + i * 16 + (lane & 15)];
 #pragma unroll
@@ -229,15 +238,20 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TN; ++j) {
+          if constexpr (F32)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+        }
     }
   };
 
   if (ks < ke) {
     int sc = fetch(ks);
     if (DB) {
-      store_slice<BM, BK, PAD, NT>(g.seg[sc].A.layout, sA[0], va, tid);
-      store_slice<BN, BK, PAD, NT>(g.seg[sc].B.layout, sB[0], vb, tid);
+      store_slice<BM, BK, PAD, NT, ST>(g.seg[sc].A.layout, sA[0], va, tid);
+      store_slice<BN, BK, PAD, NT, ST>(g.seg[sc].B.layout, sB[0], vb, tid);
       __syncthreads();
       for (int64_t t = ks; t < ke; ++t) {
         const int cur = (int)((t - ks) & 1);
@@ -245,15 +259,15 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
         if (more) sc = fetch(t + 1);
         compute(cur);
         if (more) {
-          store_slice<BM, BK, PAD, NT>(g.seg[sc].A.layout, sA[cur ^ 1], va, tid);
-          store_slice<BN, BK, PAD, NT>(g.seg[sc].B.layout, sB[cur ^ 1], vb, tid);
+          store_slice<BM, BK, PAD, NT, ST>(g.seg[sc].A.layout, sA[cur ^ 1], va, tid);
+          store_slice<BN, BK, PAD, NT, ST>(g.seg[sc].B.layout, sB[cur ^ 1], vb, tid);
         }
         __syncthreads();
       }
     } else {
       for (int64_t t = ks; t < ke; ++t) {
-        store_slice<BM, BK, PAD, NT>(g.seg[sc].A.layout, sA[0], va, tid);
-        store_slice<BN, BK, PAD, NT>(g.seg[sc].B.layout, sB[0], vb, tid);
+        store_slice<BM, BK, PAD, NT, ST>(g.seg[sc].A.layout, sA[0], va, tid);
+        store_slice<BN, BK, PAD, NT, ST>(g.seg[sc].B.layout, sB[0], vb, tid);
         __syncthreads();
         if (t + 1 < ke) sc = fetch(t + 1);
         compute(0);
@@ -263,6 +277,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
   }
 
   // epilogue: lane holds rows m = .. + (lane & 15), columns n = .. + (lane >> 4) + 4 r
+  // (FP32 products: n = .. + 4 (lane >> 4) + r)
   GemmEpi ep = g.ep;
   if (!EPI) ep.kind = kEpiLinear;
 #pragma unroll
@@ -272,9 +287,9 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
     for (int j = 0; j < TN; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t n = n0 + wn * (BN / WN) + j * 16 + (lane >> 4) + 4 * r;
+        const int64_t n = n0 + wn * (BN / WN) + j * 16 + (F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
         if (m < M && n < N) {
-          const double v = acc[i][j][r];
+          const double v = (double)acc[i][j][r];
           if (g.splitk > 1)
             g.work[(int64_t)z * g.M * g.N + n * g.M + m] = v;
           else if (!EPI) {
@@ -432,6 +447,7 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
                        const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
                        int tile_m, int tile_n, int tag) {
   if (tag == 1) return launch_gemm_t<1>(M, N, nseg, segs, C, ldc, ep, batch, splitk, work, s, tile_m, tile_n);
+  if (tag == 2) return launch_gemm_t<2>(M, N, nseg, segs, C, ldc, ep, batch, splitk, work, s, tile_m, tile_n);
   return launch_gemm_t<0>(M, N, nseg, segs, C, ldc, ep, batch, splitk, work, s, tile_m, tile_n);
 }
 

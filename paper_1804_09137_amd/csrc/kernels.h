@@ -60,7 +60,9 @@ struct GemmBatch {
 // batched calls whose per-batch sizes are far below the launch maxima use
 // small tiles so that the workgroups of small problems stay short.
 // tag 1 launches separately named kernel instances (same code), so that a
-// kernel trace tells the left-looking column-update GEMMs apart.
+// kernel trace tells the left-looking column-update GEMMs apart; tag 2 is the
+// same with the products in FP32 (operands rounded to FP32, FP32 MFMA and
+// accumulation within the launch, result added to the FP64 C).
 hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
                        const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
                        int tile_m = 0, int tile_n = 0, int tag = 0);

@@ -234,3 +234,31 @@ def test_tlr_mixed_dense_and_lowrank_tiles():
             worst = max(worst, np.abs(T - L[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]).max())
     log(f"  worst factor tile error {worst:.2e}")
     assert worst <= 1e3 * eps
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_fp32_update_products(grad):
+    # TLR_PREC_FP32_UPDATES at eps = 1e-6: the log-likelihood (and the score)
+    # within the same 10 eps of the oracle as the FP64 path, and close to it
+    n, nb, eps = 3000, 256, 1e-6
+    th = (1.0, 0.1, 0.5)
+    x, y, z = field(n, 3, th)
+    ref = D.gradient(x, y, z, th) if grad else D.loglik(x, y, z, th)
+    xd, yd, zd = to_dev(x, y, z)
+    out = {}
+    for prec in ("fp64", "fp32_updates"):
+        h = _handle(n, nb, tol=eps, maxrank=200, prec=prec, want_grad=grad)
+        if grad:
+            ll, g = h.loglik_grad(xd, yd, zd, th)
+        else:
+            h.generate(xd, yd, th)
+            h.potrf()
+            ll, _, _ = h.loglik(zd)
+            g = None
+        out[prec] = (ll, g)
+        log(f"{prec}: ll rel {abs(ll - ref['ll']) / abs(ref['ll']):.2e}" + (f" dbeta {g[1]} vs {ref['dbeta']}" if g else ""))
+        assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
+    assert abs(out["fp32_updates"][0] - out["fp64"][0]) <= 10 * eps * abs(ref["ll"])
+    if grad:
+        scale = 0.5 * (abs(ref["tr_beta"]) + abs(ref["qf_beta"]))
+        assert abs(out["fp32_updates"][1][1] - ref["dbeta"]) <= 100 * eps * scale
