@@ -65,6 +65,112 @@ def cpu_baseline(n_target: int, theta, n_sample: int) -> dict:
                       f"rate scaled by (n_sample/n)^3 to n={n_target}"}
 
 
+def batched(args) -> dict:
+    """Serving-style run: independent fields of uneven size (n uniform in
+    [2,000, 20,000], sigma^2 ~ U(0.5, 2), beta ~ U(0.03, 0.3), nu in {0.5,
+    1.5}; seeded), tile 400, one gradient handle per field on a stream of its
+    own, evaluated concurrently by tlr_loglik_grad_batched.  Handles are
+    created ahead of the timed region (the fields' worst-case storage does not
+    all fit at once, so the fields go in groups that fit); a step is one l +
+    gradient of every field.  The same handles evaluated one field at a time
+    give the sequential rate; every field is checked against its dense FP64
+    GPU l + gradient."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1804_09137_amd as P
+
+    torch.cuda.set_device(0)
+    specs = synth.batched_field_specs(args.fields, seed=0)
+    data, ref = [], []
+    for f, sp in enumerate(specs):
+        x, y = synth.jittered_subset(sp.n, sp.loc_seed)
+        p = P.morton_order(x, y)
+        x, y = x[p].copy(), y[p].copy()
+        xd, yd, ed = (torch.as_tensor(a, dtype=torch.float64, device="cuda")
+                      for a in (x, y, synth.standard_normal(sp.n, sp.z_seed)))
+        th = (sp.sigma2, sp.beta, sp.nu)
+        hd = P.Handle(sp.n, args.dense_nb, mode="dense", want_grad=True)
+        hd.generate(xd, yd, th)
+        hd.potrf()
+        zd = hd.sample(ed)
+        ref.append(hd.loglik_grad(xd, yd, zd, th))
+        hd.close()
+        data.append((xd, yd, zd, th))
+        if f % 8 == 7:
+            log(f"[batched] dense FP64 reference: {f + 1}/{len(specs)} fields")
+    torch.cuda.empty_cache()
+    budget = args.batched_budget_gb * 1e9
+    order, cur, used, last = list(range(len(specs))), [], 0.0, None
+    t_bat, t_seq, ll_all, g_all, retries, bytes_max = 0.0, 0.0, {}, {}, {}, 0.0
+
+    def run_group(idx):
+        nonlocal t_bat, t_seq, bytes_max
+        hs = [h for _, h in idx]
+        ids = [f for f, _ in idx]
+        xs, ys, zs, ths = ([data[f][k] for f in ids] for k in range(4))
+        bytes_max = max(bytes_max, sum(h.info().device_bytes for h in hs))
+        for w in range(args.warmup):
+            P.loglik_grad_batched(hs, xs, ys, zs, ths, nthreads=args.threads)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ll, g = P.loglik_grad_batched(hs, xs, ys, zs, ths, nthreads=args.threads)
+        torch.cuda.synchronize()
+        t_bat += (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for h, x, y, z, th in zip(hs, xs, ys, zs, ths):
+                h.loglik_grad(x, y, z, th)
+        torch.cuda.synchronize()
+        t_seq += (time.perf_counter() - t0) / args.steps
+        for k, f in enumerate(ids):
+            ll_all[f], g_all[f] = float(ll[k]), (float(g[k, 0]), float(g[k, 1]))
+            retries[f] = hs[k].info().fp64_retries
+        log(f"[batched] group of {len(ids)} fields (n {min(specs[f].n for f in ids)}.."
+            f"{max(specs[f].n for f in ids)}): {bytes_max / 1e9:.1f} GB; batched {t_bat:.3f} s, "
+            f"sequential {t_seq:.3f} s so far")
+        for h in hs:
+            h.close()
+        torch.cuda.empty_cache()
+
+    for f in order:
+        sp = specs[f]
+        est = 0.0 if last is None else last[1] * (sp.n / last[0]) ** 2
+        if cur and used + est > budget:
+            run_group(cur)
+            cur, used = [], 0.0
+        h = P.Handle(sp.n, args.batched_nb, tol=args.eps, maxrank=args.batched_nb // 2, want_grad=True,
+                     prec=args.prec, stream=torch.cuda.Stream())
+        b = h.info().device_bytes
+        used += b
+        last = (sp.n, b)
+        cur.append((f, h))
+    if cur:
+        run_group(cur)
+    rel_ll = [abs(ll_all[f] - ref[f][0]) / abs(ref[f][0]) for f in order]
+    rel_g = [max(abs(g_all[f][i] - ref[f][1][i]) / max(1e-300, abs(ref[f][1][i])) for i in range(2))
+             for f in order]
+    for f in sorted(order, key=lambda f: -rel_ll[f])[:6]:
+        sp = specs[f]
+        log(f"[batched] field {f}: n={sp.n} theta=({sp.sigma2:.3f}, {sp.beta:.3f}, {sp.nu}) ll rel err "
+            f"{rel_ll[f]:.2e} grad rel err {rel_g[f]:.2e}")
+    nf = len(specs)
+    return {"metric": f"batched l+grad fields/s ({nf} fields, n in [2000, 20000], tile {args.batched_nb})",
+            "value": nf / t_bat, "unit": "fields/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * t_bat, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.prec == "fp64" else "f64 (f32 update products)", "data": "synthetic",
+            "config": {"workload": f"{nf} independent Matérn fields, n uniform in [2000, 20000], tile "
+                                   f"{args.batched_nb}, eps={args.eps:g}, {args.prec}, {args.threads} host threads",
+                       "fields": nf, "nb": args.batched_nb, "eps": args.eps, "prec": args.prec,
+                       "threads": args.threads, "total_n": int(sum(sp.n for sp in specs)),
+                       "group_budget_GB": args.batched_budget_gb},
+            "sequential_fields_per_s": nf / t_seq, "concurrency_gain": t_seq / t_bat,
+            "max_rel_err_ll_vs_dense": max(rel_ll), "max_rel_err_grad_vs_dense": max(rel_g),
+            "median_rel_err_ll_vs_dense": float(np.median(rel_ll)), "peak_group_device_GB": bytes_max / 1e9,
+            "fields_refactored_fp64": int(sum(1 for f in order if retries[f] > 0))}
+
+
 def update_traffic(k):
     """HBM bytes per column-update launch from the committed counter summary
     (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
@@ -103,6 +209,13 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write), 5 times: the reference for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--batched", action="store_true",
+                    help="serving-style run over independent fields of uneven size instead of n=102400")
+    ap.add_argument("--fields", type=int, default=64)
+    ap.add_argument("--batched-nb", type=int, default=400)
+    ap.add_argument("--threads", type=int, default=8, help="host threads of the batched call")
+    ap.add_argument("--batched-budget-gb", type=float, default=200.0,
+                    help="device memory the handles of one group of fields may hold")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -119,6 +232,10 @@ def main():
         print("bench.py measures one GPU only: the TLR likelihood here runs on a single MI355X "
               "(multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.batched:
+        print(json.dumps(batched(args)), flush=True)
+        return
 
     import numpy as np
     import torch

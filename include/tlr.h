@@ -60,7 +60,11 @@ typedef enum {
                                  rounding of a densely accumulated update is a full-rank
                                  perturbation of about 1e-7 of the update's magnitude, which the
                                  compression keeps: ranks (and dense tiles) grow unless tol is
-                                 well above that level.  Accuracy is unaffected */
+                                 well above that level.  On an ill-conditioned Sigma it can also
+                                 make a pivot negative: the factorisation is then repeated with
+                                 FP64 products, and the handle keeps FP64 products for its later
+                                 calls (tlr_info.prec_used, fp64_retries), so a TLR_ENOTSPD
+                                 result is never caused by the FP32 products */
 } tlr_prec;
 
 /* tlr_opts.flags */
@@ -90,6 +94,9 @@ typedef struct {
   int32_t rank_max;           /* largest rank of a low-rank tile */
   int32_t dense_tiles;        /* strictly-lower tiles kept dense */
   int32_t bad_tile_i, bad_tile_j; /* TLR_ERANK: offending tile */
+  int32_t prec_used;          /* tlr_prec of the last factor: TLR_PREC_FP64 when an FP32-update
+                                 factor lost definiteness and was computed again in FP64 */
+  int32_t fp64_retries;       /* such repeated factorisations over the handle's life (0 or 1) */
   double t_factor_ms;         /* device time of the last factorisation (hipEvents) */
   double t_solve_ms;          /* device time of the last log-det + solves */
   double t_grad_ms;           /* device time of the gradient terms of the last tlr_loglik_grad */
@@ -160,6 +167,20 @@ tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y,
  * vector), e.g. a synthetic measurement vector z ~ N(0, Sigma) from
  * d_eps ~ N(0, I) (the data generator of Section VIII-D).  d_z must not alias
  * d_eps. */
+/* Log-likelihood and score of several independent fields at once (one handle
+ * per field, each built with want_grad; the handles must be distinct and
+ * should run on distinct streams, or their work serialises).  Field f is
+ * evaluated as tlr_loglik_grad(hs[f], d_x[f], d_y[f], d_z[f], theta + 3 f,
+ * ll + f, grad + 2 f, info + f); nthreads host threads (<= 0: 4) drive the
+ * fields concurrently so that their kernels overlap on the GPU.  ll, info and
+ * status (per-field tlr_status) may be null.  Returns the first failing
+ * field's status (in field order), else TLR_OK.  Batched evaluation is not in
+ * the paper: it serves many small fields, whose individual evaluations cannot
+ * fill the GPU. */
+tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, const double* const* d_x,
+                                   const double* const* d_y, const double* const* d_z, const double* theta,
+                                   double* ll, double* grad, int64_t* info, int32_t* status, int32_t nthreads);
+
 tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z);
 
 /* enable != 0: bracket every launch group with hipEvents on the handle's

@@ -12,7 +12,7 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["TLRError", "NotSPDError", "RankError", "Handle", "morton_order", "TLRLogLik"]
+__all__ = ["TLRError", "NotSPDError", "RankError", "Handle", "morton_order", "loglik_grad_batched", "TLRLogLik"]
 
 
 class TLRError(RuntimeError):
@@ -171,6 +171,38 @@ class Handle:
                                             _ptr(out), int(m))
         self._check(st, "tlr_covariance_block")
         return out.t()
+
+
+def loglik_grad_batched(handles, xs, ys, zs, thetas, nthreads: int = 4):
+    """l and dl/d(sigma^2, beta) of several independent fields, one Handle
+    each (built with want_grad=True, on distinct streams), evaluated
+    concurrently by tlr_loglik_grad_batched.  Returns (ll[nf], grad[nf, 2]);
+    raises the first failing field's error."""
+    nf = len(handles)
+    if not (len(xs) == len(ys) == len(zs) == len(thetas) == nf):
+        raise ValueError("one x, y, z and theta per handle")
+    lib = _lib.load()
+    P = ctypes.c_void_p
+    hs = (P * nf)(*[h._h.value for h in handles])
+    px = (P * nf)(*[_ptr(t).value for t in xs])
+    py = (P * nf)(*[_ptr(t).value for t in ys])
+    pz = (P * nf)(*[_ptr(t).value for t in zs])
+    th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).reshape(nf, 3))
+    ll = np.zeros(nf)
+    gr = np.zeros((nf, 2))
+    info = np.zeros(nf, dtype=np.int64)
+    st = np.zeros(nf, dtype=np.int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.tlr_loglik_grad_batched(nf, hs, px, py, pz, th.ctypes.data_as(dp), ll.ctypes.data_as(dp),
+                                     gr.ctypes.data_as(dp), info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(nthreads))
+    if rc != _lib.TLR_OK:
+        f = int(np.flatnonzero(st != _lib.TLR_OK)[0]) if np.any(st != _lib.TLR_OK) else 0
+        handles[f]._check(int(st[f]) if np.any(st != _lib.TLR_OK) else rc, f"tlr_loglik_grad_batched field {f}",
+                          int(info[f]))
+    for h, x, y in zip(handles, xs, ys):
+        h._keep = (x, y)
+    return ll, gr
 
 
 def morton_order(x, y) -> np.ndarray:

@@ -42,8 +42,8 @@ class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nb", ctypes.c_int32), ("nt", ctypes.c_int32),
                 ("maxrank", ctypes.c_int32), ("mode", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("rank_sum", ctypes.c_int64), ("rank_max", ctypes.c_int32), ("dense_tiles", ctypes.c_int32),
-                ("bad_tile_i", ctypes.c_int32),
-                ("bad_tile_j", ctypes.c_int32), ("t_factor_ms", ctypes.c_double),
+                ("bad_tile_i", ctypes.c_int32), ("bad_tile_j", ctypes.c_int32),
+                ("prec_used", ctypes.c_int32), ("fp64_retries", ctypes.c_int32), ("t_factor_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_grad_ms", ctypes.c_double)]
 
 
@@ -56,7 +56,7 @@ KCLASSES = ["update", "lowrank", "compress", "diag", "solve", "gradq", "gen"]
 
 EXPORTS = ["tlr_create", "tlr_destroy", "tlr_generate", "tlr_compress", "tlr_potrf", "tlr_loglik",
            "tlr_loglik_grad", "tlr_get_ranks", "tlr_get_info", "tlr_get_tile", "tlr_covariance_block",
-           "tlr_morton_order", "tlr_last_error", "tlr_sample", "tlr_profile", "tlr_get_kstats"]
+           "tlr_morton_order", "tlr_last_error", "tlr_sample", "tlr_profile", "tlr_get_kstats", "tlr_loglik_grad_batched"]
 
 _lib = None
 
@@ -91,6 +91,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlr_sample": [P, P, P],
         "tlr_profile": [P, ctypes.c_int32],
         "tlr_get_kstats": [P, ctypes.POINTER(KStat)],
+        "tlr_loglik_grad_batched": [ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(P), D3, D3, D3, ctypes.POINTER(I64),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -22,6 +22,10 @@
 #include "grad.h"
 
 #include <algorithm>
+#include <string>
+#include <thread>
+#include <atomic>
+#include <system_error>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -50,6 +54,7 @@ struct tlr_handle_s {
   int64_t n = 0;
   int nb = 0, nt = 0, maxrank = 0, smax = 0;
   int gcap = 0;         // tile slots of the compression scratch
+  int upd_tag = 1;      // column-update kernels of the running factorisation: 1 FP64, 2 FP32 products
   bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
   bool dense = false, grad = false, strict = false;
   int64_t slot = 0;      // doubles per low-rank slot (nb * maxrank)
@@ -1093,7 +1098,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
     const size_t e0 = prof_mark(h);
     gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
-         h->o.prec == TLR_PREC_FP32_UPDATES ? 2 : 1);
+         h->upd_tag);
     prof_add(h, TLR_K_UPDATE, e0, 2.0 * mrows * nbj * (double)Ktrue,
              8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + (double)mrows * nbj));
     i0 = i1;
@@ -1453,6 +1458,33 @@ tlr_status check_info(tlr_handle_s* h, int64_t* info) {
   return TLR_OK;
 }
 
+// Factorisation with its definiteness check.  With FP32 update products the
+// rounding of the densely accumulated updates (about 1e-7 of their size, full
+// rank) can push a pivot of an ill-conditioned Sigma below zero although
+// Sigma is positive definite: such a factor is computed again with FP64
+// products, and the info counters record it.  The handle keeps FP64 products
+// from then on: its later calls (nearby theta of the same field) would most
+// likely fail the same way and pay for two factorisations.
+tlr_status factor_checked(tlr_handle_s* h, bool tangent, int64_t* info) {
+  const bool f32 = h->o.prec == TLR_PREC_FP32_UPDATES && h->info.fp64_retries == 0;
+  h->upd_tag = f32 ? 2 : 1;
+  h->info.prec_used = f32 ? TLR_PREC_FP32_UPDATES : TLR_PREC_FP64;
+  for (;;) {
+    tlr_status st;
+    try {
+      if (h->dense) factor_dense(h, tangent); else factor_tlr(h, tangent);
+      st = check_info(h, info);
+    } catch (const Fail& f) {
+      if (f.st != TLR_ENOTSPD) throw;
+      st = check_info(h, info);
+    }
+    if (st != TLR_ENOTSPD || h->upd_tag != 2) return st;
+    h->upd_tag = 1;
+    h->info.prec_used = TLR_PREC_FP64;
+    ++h->info.fp64_retries;
+  }
+}
+
 void rank_stats(tlr_handle_s* h) {
   int64_t sum = 0;
   int mx = 0, nd = 0;
@@ -1782,17 +1814,12 @@ tlr_status tlr_potrf(tlr_handle_t h, int64_t* info) {
     prof_reset_pool(h);
     h->state = 0;
     HIPCHK(hipEventRecord(h->ev[0], h->s));
-    try {
-      if (h->dense) factor_dense(h, false); else factor_tlr(h, false);
-    } catch (const Fail& f) {
-      if (f.st == TLR_ENOTSPD) return check_info(h, info);
-      throw;
-    }
+    const tlr_status st = factor_checked(h, false, info);
+    if (st != TLR_OK) return st;
     HIPCHK(hipEventRecord(h->ev[1], h->s));
-    const tlr_status st = check_info(h, info);
+    sync(h);
     h->info.t_factor_ms = elapsed(h->ev[0], h->ev[1]);
     if (!h->dense) rank_stats(h);
-    if (st != TLR_OK) return st;
     h->state = 2;
     return TLR_OK;
   });
@@ -1926,17 +1953,12 @@ extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const d
     prof_reset_pool(h);
     h->state = 0;
     HIPCHK(hipEventRecord(h->ev[0], h->s));
-    try {
-      if (h->dense) factor_dense(h, true); else factor_tlr(h, true);
-    } catch (const Fail& f) {
-      if (f.st == TLR_ENOTSPD) return check_info(h, info);
-      throw;
-    }
+    const tlr_status fst = factor_checked(h, true, info);
+    if (fst != TLR_OK) return fst;
     HIPCHK(hipEventRecord(h->ev[1], h->s));
-    const tlr_status fst = check_info(h, info);
+    sync(h);
     h->info.t_factor_ms = elapsed(h->ev[0], h->ev[1]);
     if (!h->dense) rank_stats(h);
-    if (fst != TLR_OK) return fst;
     h->state = 3;
     double ld = 0.0, q = 0.0;
     HIPCHK(hipEventRecord(h->ev[2], h->s));
@@ -1965,4 +1987,60 @@ extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const d
     grad[1] = -0.5 * trace + 0.5 * qf;
     return TLR_OK;
   });
+}
+
+extern "C" tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, const double* const* d_x,
+                                              const double* const* d_y, const double* const* d_z,
+                                              const double* theta, double* ll, double* grad, int64_t* info,
+                                              int32_t* status, int32_t nthreads) {
+  if (nfields < 0) return TLR_EINVAL;
+  if (nfields == 0) return TLR_OK;
+  if (!hs || !d_x || !d_y || !d_z || !theta || !grad) return TLR_EINVAL;
+  {
+    std::vector<tlr_handle_t> seen(hs, hs + nfields);
+    for (tlr_handle_t x : seen)
+      if (!x) return TLR_EINVAL;
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return TLR_EINVAL;   // one handle, one field
+  }
+  const int T = std::max(1, std::min<int>(nthreads <= 0 ? 4 : nthreads, std::min<int>(nfields, 64)));
+  std::atomic<int> next{0};
+  std::vector<tlr_status> st((size_t)nfields, TLR_OK);
+  std::vector<std::string> msg((size_t)nfields);   // the error text is per thread: keep each field's
+  auto worker = [&]() {
+    int dev = -1;
+    for (;;) {
+      const int f = next.fetch_add(1);
+      if (f >= nfields) break;
+      if (hs[f]->device != dev) {
+        dev = hs[f]->device;
+        if (hipSetDevice(dev) != hipSuccess) {
+          st[f] = TLR_EHIP;
+          continue;
+        }
+      }
+      int64_t inf = 0;
+      st[f] = tlr_loglik_grad(hs[f], d_x[f], d_y[f], d_z[f], theta + 3 * (size_t)f, ll ? ll + f : nullptr,
+                              grad + 2 * (size_t)f, &inf);
+      if (info) info[f] = inf;
+      if (st[f] != TLR_OK) msg[f] = g_last_error;
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < T; ++t) pool.emplace_back(worker);
+  } catch (const std::system_error&) {
+    // fewer threads than asked: the rest of the work falls to those started
+  }
+  worker();
+  for (std::thread& t : pool) t.join();
+  tlr_status first = TLR_OK;
+  for (int f = 0; f < nfields; ++f) {
+    if (status) status[f] = st[f];
+    if (first == TLR_OK && st[f] != TLR_OK) {
+      first = st[f];
+      snprintf(g_last_error, sizeof(g_last_error), "%s", msg[f].c_str());
+    }
+  }
+  return first;
 }

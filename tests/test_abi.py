@@ -64,3 +64,31 @@ def test_morton_edge_cases():
     np.testing.assert_array_equal(morton_order(x, y), O.morton_order(x, y))
     x, y = synth.jittered_subset(2345, seed=4)
     np.testing.assert_array_equal(morton_order(x, y), O.morton_order(x, y))
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of tlr_opts, tlr_info and tlr_kstat have the sizes
+    and field offsets a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    from paper_1804_09137_amd import _lib as m
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tlr_opts": m.Opts, "tlr_info": m.Info, "tlr_kstat": m.KStat}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tlr.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict((" ".join(l.split()[:2]), int(l.split()[2]))
+               for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert got[f"{cname} size"] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[f"{cname} {fname}"] == getattr(cls, fname).offset, (cname, fname)
