@@ -163,7 +163,8 @@ def batched(args) -> dict:
             "config": {"workload": f"{nf} independent Matérn fields, n uniform in [2000, 20000], tile "
                                    f"{args.batched_nb}, eps={args.eps:g}, {args.prec}, {args.threads} host threads",
                        "fields": nf, "nb": args.batched_nb, "eps": args.eps, "prec": args.prec,
-                       "threads": args.threads, "total_n": int(sum(sp.n for sp in specs)),
+                       "threads": args.threads, "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                       "total_n": int(sum(sp.n for sp in specs)),
                        "group_budget_GB": args.batched_budget_gb},
             "sequential_fields_per_s": nf / t_seq, "concurrency_gain": t_seq / t_bat,
             "max_rel_err_ll_vs_dense": max(rel_ll), "max_rel_err_grad_vs_dense": max(rel_g),
@@ -213,7 +214,9 @@ def main():
                     help="serving-style run over independent fields of uneven size instead of n=102400")
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--batched-nb", type=int, default=400)
-    ap.add_argument("--threads", type=int, default=8, help="host threads of the batched call")
+    ap.add_argument("--threads", type=int, default=16, help="host threads of the batched call")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for --batched when the environment does not set it")
     ap.add_argument("--batched-budget-gb", type=float, default=200.0,
                     help="device memory the handles of one group of fields may hold")
     args = ap.parse_args()
@@ -234,6 +237,11 @@ def main():
         sys.exit(2)
 
     if args.batched:
+        # Every field runs on two streams of its own; the HIP runtime maps all
+        # streams of the process onto GPU_MAX_HW_QUEUES hardware queues (4 by
+        # default), which serialises the fields.  Read when the runtime
+        # starts, so it is set before torch touches the GPU.
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(args.hw_queues))
         print(json.dumps(batched(args)), flush=True)
         return
 

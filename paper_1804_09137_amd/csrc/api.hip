@@ -696,11 +696,11 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
     std::vector<int> big;
     int nsmall = 0;
     for (int q = 0; q < L; ++q)
-      if (t1[lr[q]] <= kRegQrMax) ++nsmall;
+      if (t1[lr[q]] <= kRegQrBig) ++nsmall;
     int qs = 0, qb = nsmall;
     for (int q = 0; q < L; ++q) {
       const int g = lr[q];
-      const bool small = t1[g] <= kRegQrMax;
+      const bool small = t1[g] <= kRegQrBig;
       QrcpTask& tk = h->tk_h[small ? qs++ : qb++];
       tk = QrcpTask{};
       tk.m = t1[g];
@@ -792,7 +792,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
         s_max = std::max(s_max, sz[g]);
         t1_max = std::max(t1_max, t1[g]);
         if (!dense[g]) k_max = std::max(k_max, k2[g]);
-        nbig += (!dense[g] && t1[g] > kRegQrMax) ? 1 : 0;
+        nbig += (!dense[g] && t1[g] > kRegQrBig) ? 1 : 0;
         nd += dense[g];
       }
       std::fprintf(stderr, "[tlr] col %d%s tiles %d rounds %d sketch<=%d t1<=%d k<=%d big %d dense %d\n", jb.col,

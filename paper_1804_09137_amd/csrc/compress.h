@@ -28,8 +28,10 @@ struct QrcpTask {
   int64_t ldw;
 };
 
-// Register-resident pivoted QR (qrcp_reg_kernel) limit on rows and columns.
+// On-chip pivoted QR (qrcp_reg_kernel): all in registers up to kRegQrMax
+// rows and columns, registers plus LDS up to kRegQrBig.
 constexpr int kRegQrMax = 192;
+constexpr int kRegQrBig = 224;
 
 // Blocked Householder QR (hqr_factor_kernel) of the m x s matrix A (lda), in
 // place, m <= kQrMaxRows, s <= kQrMaxCols; and the application of its Q

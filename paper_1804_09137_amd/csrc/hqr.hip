@@ -381,56 +381,92 @@ __global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Column-pivoted Householder QR of a small matrix (m, q <= kRegQrMax) held in
-// registers: wave w owns columns w + 8j, lane l rows l + 64i.  Same stopping
+// Column-pivoted Householder QR of a small matrix (m, q <= kRegQrBig) held
+// on chip: wave w owns columns w + 8j, lane l rows l + 64i.  Same stopping
 // rule and outputs as qrcp_kernel (rank, Z, explicit Q), reading Y (only its
 // upper triangle when tk.upper) and writing reflectors to the workspace W.
 // Each step: the pivot column's wave forms the reflector (one barrier), every
 // wave reflects its live columns and recomputes their norms with two batched
 // wave reductions (one barrier).
+//
+// Up to kRegQrMax rows and columns the matrix is all in registers.  Beyond
+// that (the range ranks of the tangent tiles next to the diagonal reach
+// ~220) the extra rows (one per lane l < kXr) and the extra column slots of
+// each wave live in LDS; every such element is read and written only by the
+// thread that owns it, so the LDS share acts as more registers and needs no
+// barriers of its own.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int RI = kRegQrMax / 64;   // row slots per lane
-constexpr int RJ = kRegQrMax / NW;   // column slots per wave
-static_assert(RJ <= 32, "column slots must fit two 16-entry butterflies");
-}  // namespace
+constexpr int RIR = kRegQrMax / 64;                  // row slots per lane in registers
+constexpr int RJR = kRegQrMax / NW;                  // column slots per wave in registers
+constexpr int kXr = kRegQrBig - kRegQrMax;           // extra rows, one per lane l < kXr
+constexpr int kXc = (kRegQrBig - kRegQrMax) / NW;    // extra column slots per wave
+static_assert(kRegQrMax % 64 == 0 && kRegQrMax % NW == 0, "register block must tile the wave layout");
+static_assert(kXr > 0 && kXr <= 64 && kXc * NW == kXr, "extra rows and columns must fit one slot each");
+static_assert(RJR + kXc <= 32, "column slots must fit two 16-entry butterflies");
 
-__global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict__ tasks) {
-  const QrcpTask tk = tasks[blockIdx.x];
-  __shared__ double vs[kRegQrMax];
-  __shared__ double taus[kRegQrMax];
-  __shared__ int step_of[kRegQrMax];
-  __shared__ double wsum[NW], wmax[NW];
-  __shared__ int widx[NW];
+// One lane's share of the matrix: element (row lane + 64 i, column w + NW j).
+template <bool BIG>
+struct QrShare {
+  static constexpr int RJ = BIG ? RJR + kXc : RJR;
+  static constexpr int RI = BIG ? RIR + 1 : RIR;
+  double r[RJR][RIR];
+  double* xr;   // LDS [kRegQrBig][kXr]: row kRegQrMax + l of column c at c * kXr + l
+  double* xc;   // LDS [kXc][NW][kRegQrMax]: extra column slot s of wave w, row r
+  int w, lane;
+  __device__ __forceinline__ double get(int j, int i) const {
+    if (j < RJR && i < RIR) return r[j][i];
+    if (i >= RIR) return lane < kXr ? xr[(w + NW * j) * kXr + lane] : 0.0;
+    return xc[((j - RJR) * NW + w) * kRegQrMax + lane + 64 * i];
+  }
+  __device__ __forceinline__ void set(int j, int i, double v) {
+    if (j < RJR && i < RIR) {
+      r[j][i] = v;
+    } else if (i >= RIR) {
+      if (lane < kXr) xr[(w + NW * j) * kXr + lane] = v;
+    } else {
+      xc[((j - RJR) * NW + w) * kRegQrMax + lane + 64 * i] = v;
+    }
+  }
+};
+
+struct QrShared {
+  double* vs;       // reflector of the current step, 64 * (RIR + 1) rows
+  double* taus;     // [kRegQrBig]
+  int* step_of;     // [kRegQrBig]
+  double* wsum;     // [NW] per-wave sum / max / argmax of the live column norms
+  double* wmax;
+  int* widx;
+  double* xr;
+  double* xc;
+};
+
+template <bool BIG>
+__device__ __forceinline__ void qrcp_reg_body(const QrcpTask& tk, const QrShared& sh) {
+  using Share = QrShare<BIG>;
+  constexpr int RJ = Share::RJ, RI = Share::RI;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int m = tk.m, q = tk.q;
-  if (m <= 0 || q <= 0) {
-    if (tid == 0) {
-      if (tk.rank) *tk.rank = 0;
-      if (tk.flag) *tk.flag = 0;
-    }
-    return;
-  }
-  if (m > kRegQrMax || q > kRegQrMax) {   // the host routes these to qrcp_kernel
-    if (tid == 0) {
-      if (tk.rank) *tk.rank = 0;
-      if (tk.flag) *tk.flag = 1;
-    }
-    return;
-  }
+  double* vs = sh.vs;
+  double* taus = sh.taus;
+  int* step_of = sh.step_of;
   const double* Y = tk.Y;
   const int64_t ldy = tk.ldy;
-  double a[RJ][RI];
+  Share a;
+  a.xr = sh.xr;
+  a.xc = sh.xc;
+  a.w = w;
+  a.lane = lane;
 #pragma unroll
   for (int j = 0; j < RJ; ++j) {
     const int c = w + NW * j;
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int r = lane + 64 * i;
-      a[j][i] = (c < q && r < m && (!tk.upper || r <= c)) ? Y[(int64_t)c * ldy + r] : 0.0;
+      a.set(j, i, (c < q && r < m && (!tk.upper || r <= c)) ? Y[(int64_t)c * ldy + r] : 0.0);
     }
   }
-  for (int c = tid; c < kRegQrMax; c += NT) step_of[c] = 0x7fffffff;
+  for (int c = tid; c < kRegQrBig; c += NT) step_of[c] = 0x7fffffff;
   uint32_t done = 0;   // bit j: column w + 8j already pivoted
 
   // Sums over the wave of per-column partials f(j), j < RJ, in two 16-entry
@@ -452,7 +488,10 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
       double acc = 0.0;
 #pragma unroll
       for (int i = 0; i < RI; ++i)
-        if (lane + 64 * i > t) acc += a[j][i] * a[j][i];
+        if (lane + 64 * i > t) {
+          const double v = a.get(j, i);
+          acc += v * v;
+        }
       return acc;
     }, lo, hi);
     const int e = (lane >> 2) & 15;
@@ -469,7 +508,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
       }
     }
     wave::max_sum(mv, mi, sv, lane);
-    if (lane == 0) { wsum[w] = sv; wmax[w] = mv; widx[w] = mi; }
+    if (lane == 0) { sh.wsum[w] = sv; sh.wmax[w] = mv; sh.widx[w] = mi; }
   };
   norms(-1);
   __syncthreads();
@@ -482,8 +521,8 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
     int p = 0x7fffffff;
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
-      total += wsum[v];
-      if (wmax[v] > best || (wmax[v] == best && widx[v] < p)) { best = wmax[v]; p = widx[v]; }
+      total += sh.wsum[v];
+      if (sh.wmax[v] > best || (sh.wmax[v] == best && sh.widx[v] < p)) { best = sh.wmax[v]; p = sh.widx[v]; }
     }
     if (total <= tol2 || t >= tk.max_rank || p >= q) break;
     const int pw = p % NW, pj = p / NW;
@@ -494,7 +533,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
         x[i] = 0.0;
 #pragma unroll
         for (int j = 0; j < RJ; ++j)
-          if (j == pj) x[i] = a[j][i];
+          if (j == pj) x[i] = a.get(j, i);
       }
       double sq = 0.0;
 #pragma unroll
@@ -523,7 +562,7 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
         const double nv = (r == t) ? beta : (r > t ? v : x[i]);
 #pragma unroll
         for (int j = 0; j < RJ; ++j)
-          if (j == pj) a[j][i] = nv;
+          if (j == pj) a.set(j, i, nv);
       }
       if (lane == 0) { taus[t] = ta; step_of[p] = t; }
     }
@@ -538,15 +577,17 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
       double acc = 0.0;
       if (!((done >> j) & 1u)) {
 #pragma unroll
-        for (int i = 0; i < RI; ++i) acc += vv[i] * a[j][i];
+        for (int i = 0; i < RI; ++i) acc += vv[i] * a.get(j, i);
       }
       return acc;
     }, lo, hi);
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
       const double d = ta * wave::read(j < 16 ? lo : hi, 4 * (j & 15));
+      if (!((done >> j) & 1u)) {
 #pragma unroll
-      for (int i = 0; i < RI; ++i) a[j][i] -= d * vv[i];
+        for (int i = 0; i < RI; ++i) a.set(j, i, a.get(j, i) - d * vv[i]);
+      }
     }
     norms(t);
     __syncthreads();
@@ -565,19 +606,26 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int r = lane + 64 * i;
-      if (tk.Z && r < rank) tk.Z[(int64_t)r * tk.ldz + c] = (st >= r) ? a[j][i] : 0.0;
-      if (st < rank && r < m) tk.W[(int64_t)st * tk.ldw + r] = (r > st) ? a[j][i] : 0.0;
+      if (r >= m) continue;
+      const double v = a.get(j, i);
+      if (tk.Z && r < rank) tk.Z[(int64_t)r * tk.ldz + c] = (st >= r) ? v : 0.0;
+      if (st < rank) tk.W[(int64_t)st * tk.ldw + r] = (r > st) ? v : 0.0;
     }
   }
   if (!tk.Q || rank == 0) return;
   __syncthreads();
   // explicit Q = H_0 ... H_{rank-1} [I; 0]: column c still equals e_c before
-  // step st <= c is applied, so step st only touches columns >= st
-  double qa[RJ][RI];
+  // step st <= c is applied, so step st only touches columns >= st.  The
+  // share is reused (each thread rewrites only its own elements).
+  Share qa;
+  qa.xr = sh.xr;
+  qa.xc = sh.xc;
+  qa.w = w;
+  qa.lane = lane;
 #pragma unroll
   for (int j = 0; j < RJ; ++j)
 #pragma unroll
-    for (int i = 0; i < RI; ++i) qa[j][i] = (lane + 64 * i == w + NW * j) ? 1.0 : 0.0;
+    for (int i = 0; i < RI; ++i) qa.set(j, i, (lane + 64 * i == w + NW * j) ? 1.0 : 0.0);
   for (int st = rank - 1; st >= 0; --st) {
     const double ta = taus[st];
     double vv[RI];
@@ -592,15 +640,18 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
       const int c = w + NW * j;
       if (c >= st && c < rank) {
 #pragma unroll
-        for (int i = 0; i < RI; ++i) acc += vv[i] * qa[j][i];
+        for (int i = 0; i < RI; ++i) acc += vv[i] * qa.get(j, i);
       }
       return acc;
     }, lo, hi);
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
+      const int c = w + NW * j;
       const double d = ta * wave::read(j < 16 ? lo : hi, 4 * (j & 15));
+      if (c >= st && c < rank) {
 #pragma unroll
-      for (int i = 0; i < RI; ++i) qa[j][i] -= d * vv[i];
+        for (int i = 0; i < RI; ++i) qa.set(j, i, qa.get(j, i) - d * vv[i]);
+      }
     }
   }
 #pragma unroll
@@ -610,9 +661,32 @@ __global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int r = lane + 64 * i;
-      if (r < m) tk.Q[(int64_t)c * tk.ldq + r] = qa[j][i];
+      if (r < m) tk.Q[(int64_t)c * tk.ldq + r] = qa.get(j, i);
     }
   }
+}
+}  // namespace
+
+__global__ void __launch_bounds__(NT) qrcp_reg_kernel(const QrcpTask* __restrict__ tasks) {
+  const QrcpTask tk = tasks[blockIdx.x];
+  __shared__ double vs[64 * (RIR + 1)];
+  __shared__ double taus[kRegQrBig];
+  __shared__ int step_of[kRegQrBig];
+  __shared__ double wsum[NW], wmax[NW];
+  __shared__ int widx[NW];
+  __shared__ double xr[kRegQrBig * kXr];
+  __shared__ double xc[kXc * NW * kRegQrMax];
+  const int m = tk.m, q = tk.q;
+  if (m <= 0 || q <= 0 || m > kRegQrBig || q > kRegQrBig) {   // the host routes larger ones to qrcp_kernel
+    if (threadIdx.x == 0) {
+      if (tk.rank) *tk.rank = 0;
+      if (tk.flag) *tk.flag = (m > 0 && q > 0) ? 1 : 0;
+    }
+    return;
+  }
+  const QrShared sh{vs, taus, step_of, wsum, wmax, widx, xr, xc};
+  if (m <= kRegQrMax && q <= kRegQrMax) qrcp_reg_body<false>(tk, sh);
+  else qrcp_reg_body<true>(tk, sh);
 }
 
 // Upper-triangular copy (zeros below the diagonal) of rows/cols [0, n_b) of

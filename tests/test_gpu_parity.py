@@ -316,3 +316,31 @@ def test_ill_conditioned_field_no_worse_than_oracle_tlr():
     log(f"rel error vs dense: HIP TLR {e_gpu:.2e}, oracle TLR {e_or:.2e}")
     assert e_or > 10 * eps          # the regime this test is about
     assert e_gpu <= max(10 * eps, 2.0 * e_or)
+
+
+def test_pivoted_qr_size_classes(monkeypatch, capfd):
+    # n = 6400 in tiles of 800 at eps = 1e-7: the primal tiles next to the
+    # diagonal have range ranks t1 just above 192 (pivoted QR in registers
+    # plus LDS), the tangent ones above 224 (pivoted QR in global memory), the
+    # rest below 192 (all in registers).  The library's per-column debug lines
+    # show which classes ran; the results match the oracle and the dense path.
+    import re
+    import paper_1804_09137_amd as P
+    n, nb, eps = 6400, 800, 1e-7
+    th = (1.0, 0.1, 0.5)
+    x, y, z = field(n, 0, th)
+    ref = D.loglik(x, y, z, th)
+    xd, yd, zd = to_dev(x, y, z)
+    monkeypatch.setenv("TLR_DEBUG", "1")
+    h = _handle(n, nb, tol=eps, maxrank=nb // 2, want_grad=True)
+    monkeypatch.delenv("TLR_DEBUG")
+    ll, g = h.loglik_grad(xd, yd, zd, th)
+    err = capfd.readouterr().err
+    t1 = [int(v) for v in re.findall(r"t1<=(\d+)", err)]
+    log(f"columns {len(t1)}, largest t1 per column {sorted(t1)}")
+    assert any(v <= 192 for v in t1) and any(192 < v <= 224 for v in t1) and any(v > 224 for v in t1)
+    hd = _handle(n, 320, mode="dense", want_grad=True)
+    lld, gd = hd.loglik_grad(xd, yd, zd, th)
+    log(f"ll rel {abs(ll - ref['ll']) / abs(ref['ll']):.2e}, grad {g} vs dense {gd}")
+    assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
+    assert abs(g[0] - gd[0]) <= 1e-5 * abs(gd[0]) and abs(g[1] - gd[1]) <= 1e-5 * abs(gd[1])
