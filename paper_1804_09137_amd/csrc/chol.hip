@@ -3,74 +3,106 @@
 // log-determinant reduction, matrix-vector products for the triangular solves.
 #include "kernels.h"
 #include "chol.h"
+#include "wave.h"
 
 namespace tlrk {
 
-// Factor the w x w (w <= 64) diagonal block at A (column-major, lda) in place
-// (lower Cholesky), and write its inverse (lower, zero above) to Inv (ldi).
-// A pivot that is not > 0 (or NaN) records row0 + c + 1 in *info (atomicMin
-// over 1-based rows; *info must start at INT64_MAX) and the factorisation
-// continues with the pivot replaced by 1 so that no NaN/inf is produced.
-__global__ void __launch_bounds__(256) potrf_small_kernel(double* __restrict__ A, int64_t lda, int w,
-                                                          double* __restrict__ Inv, int64_t ldi,
-                                                          unsigned long long* info, int64_t row0) {
-  __shared__ double L[64][65];
-  __shared__ double X[64][65];
-  const int tid = threadIdx.x;
-  const int li = tid & 63;    // row handled by this lane
-  const int kq = tid >> 6;    // this wave's columns: k = kq + 4 s
-  for (int k = kq; k < w; k += 4) {
-    L[li][k] = (li < w && li >= k) ? A[(int64_t)k * lda + li] : 0.0;
-    X[li][k] = 0.0;
+// Cholesky factor L and inverse L^{-1} of a w x w block (w <= 64) by one
+// wave.  Both halves are 64 steps of register rank-1 updates whose other
+// operand is broadcast from LDS:
+//   factor: lane i keeps row i of the matrix; at step c the scaled column c
+//     is published and every lane updates its entries right of c (entries
+//     right of the diagonal are never read as results);
+//   inverse: lane k keeps column k of X = L^{-1}, solved forward: at step t
+//     its X[t][k] is final, and every entry below it takes -L[r][t] X[t][k].
+// Rows and columns beyond w are padded with the identity.  A pivot that is
+// not > 0 (or NaN) is replaced by 1 and reported as info = row0 + c + 1
+// (atomicMin over calls; *info starts at the maximum).
+namespace {
+// v[k] -= s * b[k] for k in (c, 64), b in LDS
+template <int C>
+__device__ __forceinline__ void rank1_lds(double (&v)[64], double sv, const double* b) {
+#pragma unroll
+  for (int k = C + 1; k < 64; ++k) v[k] -= sv * b[k];
+}
+template <int C>
+struct Potrf64 {
+  __device__ __forceinline__ static void factor(double (&a)[64], double* col, int i, int w, int& bad) {
+    double d = wave::read(a[C], C);
+    if (!(d > 0.0)) {
+      if (C < w && bad == 0) bad = C + 1;
+      d = 1.0;
+    }
+    // 1 / sqrt(d) from the hardware estimate and two Newton-Raphson steps
+    // (error ~1 ulp): a division here is expanded inside a per-lane branch,
+    // and 64 such branches around the live row defeat register allocation
+    double is = __builtin_amdgcn_rsq(d);
+    is = is * (1.5 - 0.5 * d * is * is);
+    is = is * (1.5 - 0.5 * d * is * is);
+    const double sc = d * is;
+    a[C] = (i > C) ? a[C] * is : (i == C ? sc : a[C]);
+    col[i] = a[C];
+    __syncthreads();
+    rank1_lds<C>(a, a[C], col);
+    __syncthreads();
+    Potrf64<C + 1>::factor(a, col, i, w, bad);
   }
+  // Ls: rows of L (ld 65), row t at Ls + t * 65
+  __device__ __forceinline__ static void inverse(double (&x)[64], const double* Ls, int i) {
+    x[C] = ((C == i ? 1.0 : 0.0) - x[C]) * (1.0 / Ls[C * 65 + C]);
+    // entries r > C of column i: x[r] += L[r][C] x[C] (negated at finalisation)
+#pragma unroll
+    for (int r = C + 1; r < 64; ++r) x[r] += Ls[r * 65 + C] * x[C];
+    Potrf64<C + 1>::inverse(x, Ls, i);
+  }
+};
+template <>
+struct Potrf64<64> {
+  __device__ __forceinline__ static void factor(double (&)[64], double*, int, int, int&) {}
+  __device__ __forceinline__ static void inverse(double (&)[64], const double*, int) {}
+};
+}  // namespace
+
+__global__ void __launch_bounds__(64) potrf_small_kernel(double* __restrict__ A, int64_t lda, int w,
+                                                         double* __restrict__ Inv, int64_t ldi,
+                                                         unsigned long long* info, int64_t row0) {
+  __shared__ double col[64];
+  __shared__ double Ls[64 * 65];
+  const int i = threadIdx.x;
+  // the block goes through LDS (coalesced column reads); each lane then
+  // takes its row, padded with the identity
+  for (int k = 0; k < 64; ++k)
+    Ls[i * 65 + k] = (i < w && k < w) ? (k <= i ? A[(int64_t)k * lda + i] : 0.0) : (i == k ? 1.0 : 0.0);
   __syncthreads();
-  // right-looking: scale column c, then rank-1 update of the lower part
-  for (int c = 0; c < w; ++c) {
-    double d = L[c][c];
-    const bool bad = !(d > 0.0);
-    if (bad) d = 1.0;
-    const double sc = sqrt(d);
-    const double is = 1.0 / sc;
-    __syncthreads();   // every thread has read L[c][c]
-    if (tid == 0) {
-      if (bad) atomicMin(info, (unsigned long long)(row0 + c + 1));
-      L[c][c] = sc;
-    }
-    if (tid < 64 && li > c && li < w) L[li][c] *= is;
-    __syncthreads();
-    const double lic = (li > c && li < w) ? L[li][c] : 0.0;
-    for (int k = c + 1 + ((kq - c - 1) & 3); k < w; k += 4)
-      if (li >= k) L[li][k] -= lic * L[k][c];
-    __syncthreads();
-  }
-  // X = L^{-1} by rows: X[i][k] = (delta_ik - sum_{k <= t < i} L[i][t] X[t][k]) / L[i][i];
-  // the four waves split the sum over t, lane k owns column k
-  __shared__ double part[4][64];
-  for (int i = 0; i < w; ++i) {
-    const int k = li;
-    double acc = 0.0;
-    if (k < i)
-      for (int t = k + kq; t < i; t += 4) acc += L[i][t] * X[t][k];
-    part[kq][k] = acc;
-    __syncthreads();
-    if (tid < 64 && k <= i) {
-      const double s = part[0][k] + part[1][k] + part[2][k] + part[3][k];
-      X[i][k] = ((k == i ? 1.0 : 0.0) - s) / L[i][i];
-    }
-    __syncthreads();
-  }
-  for (int k = kq; k < w; k += 4) {
-    if (li < w) {
-      if (li >= k) A[(int64_t)k * lda + li] = L[li][k];
-      Inv[(int64_t)k * ldi + li] = (li >= k) ? X[li][k] : 0.0;
-    }
-  }
+  double a[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) a[k] = Ls[i * 65 + k];
+  int bad = 0;
+  Potrf64<0>::factor(a, col, i, w, bad);
+  if (bad && i == 0) atomicMin(info, (unsigned long long)(row0 + bad));
+#pragma unroll
+  for (int k = 0; k < 64; ++k) Ls[i * 65 + k] = (k <= i) ? a[k] : 0.0;
+  __syncthreads();
+  for (int k = 0; k < w; ++k)
+    if (i < w && k <= i) A[(int64_t)k * lda + i] = Ls[i * 65 + k];
+  // x[r] accumulates sum_{t<r} L[r][t] X[t][i] until step r finalises it
+  double x[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) x[r] = 0.0;
+  Potrf64<0>::inverse(x, Ls, i);
+  __syncthreads();
+  // transpose through LDS so that the stores below are coalesced
+#pragma unroll
+  for (int r = 0; r < 64; ++r) Ls[r * 65 + i] = x[r];
+  __syncthreads();
+  for (int k = 0; k < w; ++k)
+    if (i < w) Inv[(int64_t)k * ldi + i] = (i >= k) ? Ls[i * 65 + k] : 0.0;
 }
 
 hipError_t launch_potrf_small(double* A, int64_t lda, int w, double* Inv, int64_t ldi,
                               unsigned long long* info, int64_t row0, hipStream_t s) {
   if (w < 1 || w > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(potrf_small_kernel, dim3(1), dim3(256), 0, s, A, lda, w, Inv, ldi, info, row0);
+  hipLaunchKernelGGL(potrf_small_kernel, dim3(1), dim3(64), 0, s, A, lda, w, Inv, ldi, info, row0);
   return hipGetLastError();
 }
 
