@@ -1073,15 +1073,20 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           xb.a_off = xa_d; xb.b_off = xb_d; xb.c_off = xc_d;
           gemm(h, maxa, maxb, 1, &xs, h->Xb, maxa, epi_linear(1.0, 0.0), &xb, false, grp ? 128 : 32, 32, xm_h,
                xn_h);
-          GemmSeg ws{};
-          ws.A = op_contig(h->arena, nb, 0, 0);
-          ws.B = op_contigT(h->Xb, maxa, 0, 0);
-          ws.K = maxa;
           GemmBatch wb{};
           wb.count = cnt;
           wb.m_of = wm_d; wb.n_of = wn_d; wb.k_of = wk_d;
           wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
-          gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32, wm_h, wn_h);
+          if (grp == 0 && maxa <= kThinMaxK) {
+            // W_ik = U_ik X_ik, inner dimension a rank: a streaming kernel
+            HIPCHK(launch_thin_gemm(h->arena, nb, h->Xb, maxa, h->Wb, ldw, wb, maxrows, maxa, h->s));
+          } else {
+            GemmSeg ws{};
+            ws.A = op_contig(h->arena, nb, 0, 0);
+            ws.B = op_contigT(h->Xb, maxa, 0, 0);
+            ws.K = maxa;
+            gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32, wm_h, wn_h);
+          }
         }
     }
     prof_add(h, TLR_K_LOWRANK, e_w, wflops, wbytes);

@@ -451,4 +451,76 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
   return launch_gemm_t<0>(M, N, nseg, segs, C, ldc, ep, batch, splitk, work, s, tile_m, tile_n);
 }
 
+// ---------------------------------------------------------------------------
+// Batched products with a small inner dimension, C_p = A_p B_p (A_p: m_p x
+// k_p, B_p: k_p x n_p, column-major at element offsets a_off[p], b_off[p],
+// c_off[p]).  In the column update these are W_ik = U_ik X_ik: 800 rows, k and
+// n ranks of a few tens, thousands of pairs.  Memory-bound: A is streamed
+// (once per 16 columns of C, re-reads hit L2), B is staged in LDS 16
+// columns at a time and read as broadcasts, each thread owns one row of C.
+// Workgroup (p, y) covers rows [256 y, 256 y + 256) of pair p.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kThinRows = 256;
+constexpr int kThinCols = 16;
+}  // namespace
+
+__global__ void __launch_bounds__(kThinRows) thin_gemm_kernel(const double* __restrict__ A, int64_t lda,
+                                                              const double* __restrict__ B, int64_t ldb,
+                                                              double* __restrict__ C, int64_t ldc,
+                                                              const int* __restrict__ m_of,
+                                                              const int* __restrict__ n_of,
+                                                              const int* __restrict__ k_of,
+                                                              const int64_t* __restrict__ a_off,
+                                                              const int64_t* __restrict__ b_off,
+                                                              const int64_t* __restrict__ c_off) {
+  extern __shared__ double xs[];   // [k][kThinCols]
+  const int p = blockIdx.x;
+  const int m = m_of[p], n = n_of[p], k = k_of[p];
+  const int r0 = blockIdx.y * kThinRows;
+  if (r0 >= m || n <= 0) return;   // uniform over the workgroup
+  const int r = r0 + threadIdx.x;
+  const double* a = A + a_off[p];
+  const double* b = B + b_off[p];
+  double* c = C + c_off[p];
+  for (int n0 = 0; n0 < n; n0 += kThinCols) {
+    const int nc = (n - n0 < kThinCols) ? n - n0 : kThinCols;
+    __syncthreads();   // the previous slice has been read
+    for (int e = threadIdx.x; e < k * kThinCols; e += kThinRows) {
+      const int q = e / k, t = e - q * k;   // consecutive threads: consecutive rows of B
+      xs[t * kThinCols + q] = (q < nc) ? b[t + (int64_t)(n0 + q) * ldb] : 0.0;
+    }
+    __syncthreads();
+    if (r < m) {
+      double acc[kThinCols];
+#pragma unroll
+      for (int q = 0; q < kThinCols; ++q) acc[q] = 0.0;
+      const double* ar = a + r;
+#pragma unroll 4
+      for (int t = 0; t < k; ++t) {
+        const double u = ar[(int64_t)t * lda];
+        const double* xt = xs + t * kThinCols;
+#pragma unroll
+        for (int q = 0; q < kThinCols; ++q) acc[q] += u * xt[q];
+      }
+#pragma unroll
+      for (int q = 0; q < kThinCols; ++q)
+        if (q < nc) c[r + (int64_t)(n0 + q) * ldc] = acc[q];
+    }
+  }
+}
+
+hipError_t launch_thin_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                            const GemmBatch& batch, int maxm, int maxk, hipStream_t s) {
+  if (batch.count <= 0 || maxm <= 0) return hipSuccess;
+  if (maxk < 0 || maxk > kThinMaxK || !batch.m_of || !batch.n_of || !batch.k_of || !batch.a_off ||
+      !batch.b_off || !batch.c_off)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)(maxk > 0 ? maxk : 1) * kThinCols * sizeof(double);
+  hipLaunchKernelGGL(thin_gemm_kernel, dim3((unsigned)batch.count, (unsigned)((maxm + kThinRows - 1) / kThinRows)),
+                     dim3(kThinRows), lds, s, A, lda, B, ldb, C, ldc, batch.m_of, batch.n_of, batch.k_of,
+                     batch.a_off, batch.b_off, batch.c_off);
+  return hipGetLastError();
+}
+
 }  // namespace tlrk
