@@ -418,6 +418,23 @@ static hipError_t launch_gemm_t(int64_t M, int64_t N, int nseg, const GemmSeg* s
     e = run<32, 128, 2, 2, 32, 4, 0, 0, TAG>(g, zdim, s);
   } else if (M <= 64) {
     e = run<64, 128, 2, 2, 32, 4, 0, 1, TAG>(g, zdim, s);
+  } else if (TAG != 0 && splitk == 1 && g.batch.count == 1 && !g.batch.m_of && N >= 256 && N % 256 <= 64) {
+    // column update: 128 x 256 tiles (wave tile 64 x 64) over the first 256 q
+    // columns: each W slice feeds twice the MFMAs of a 128 x 128 tile, and the
+    // W panel is streamed by half as many tile columns; the rest as below
+    const int64_t n1 = N - N % 256;
+    g.N = n1;
+    e = run<128, 256, 2, 4, 16, 4, 0, 1, TAG>(g, zdim, s);
+    if (e != hipSuccess || n1 == N) return e;
+    GemmArgs g2 = g;
+    g2.N = N - n1;
+    for (int i = 0; i < g2.nseg; ++i) g2.seg[i].B.r0 += n1;
+    g2.C = C + n1 * ldc;
+    g2.ep.gcol0 += n1;
+    if (N - n1 <= 32)
+      e = run<128, 32, 2, 2, 32, 4, 0, 0, TAG>(g2, zdim, s);
+    else
+      e = run<128, 64, 2, 2, 32, 4, 0, 1, TAG>(g2, zdim, s);
   } else if (splitk == 1 && g.batch.count == 1 && !g.batch.m_of && N % 128 != 0 && N % 128 <= 64) {
     // N = 128 q + r (r <= 64): 128 x 128 tiles over the first 128 q columns,
     // 128 x r-wide tiles over the rest, instead of a mostly idle last tile column
