@@ -188,9 +188,13 @@ tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, cons
 
 tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z);
 
-/* enable != 0: bracket every launch group with hipEvents on the handle's
- * stream and accumulate per-class device time and algorithmic work (costs a
- * few microseconds per group).  Resets the counters either way. */
+/* enable = 1: bracket every launch group with hipEvents on the stream it
+ * runs on and accumulate per-class device time and algorithmic work (costs a
+ * few microseconds per group).  enable = 2: the same, and each column-update
+ * group of a gradient handle runs alone (the handle's two streams wait for
+ * each other around it), so that its events time only its own kernels; the
+ * evaluation is then slower.  enable = 0: off.  Other values: TLR_EINVAL.
+ * Resets the counters. */
 tlr_status tlr_profile(tlr_handle_t h, int32_t enable);
 
 /* Copy the TLR_K_COUNT per-class counters into out[]. */

@@ -134,9 +134,12 @@ class Handle:
         self._check(self._lib.tlr_sample(self._h, _ptr(eps), _ptr(z)), "tlr_sample")
         return z
 
-    def profile(self, enable: bool = True):
-        """Per-kernel-class hipEvent timing on/off (resets the counters)."""
-        self._check(self._lib.tlr_profile(self._h, 1 if enable else 0), "tlr_profile")
+    def profile(self, enable=True):
+        """Per-kernel-class hipEvent timing (resets the counters): False/0 off,
+        True/1 on, 2 on with every column-update group run alone so that its
+        events time only its own kernels."""
+        mode = 2 if enable == 2 else (1 if enable else 0)
+        self._check(self._lib.tlr_profile(self._h, mode), "tlr_profile")
 
     def kstats(self) -> dict:
         arr = (_lib.KStat * len(_lib.KCLASSES))()

@@ -48,6 +48,7 @@ struct tlr_handle_s {
   hipStream_t s_main = nullptr;   // the caller's stream
   hipStream_t s_side = nullptr;   // tangent chain of the lockstep factorisation (gradient handles)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_px = nullptr, ev_py = nullptr;   // profiling mode 2: isolation of update groups
   // second set of update scratch for the side stream (same capacities)
   double *Wb2 = nullptr, *Xb2 = nullptr, *Urow2 = nullptr, *skw2 = nullptr, *tw2 = nullptr;
   int device = 0;
@@ -148,7 +149,7 @@ struct tlr_handle_s {
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-kernel-class event timing (tlr_profile)
-  bool prof = false;
+  int prof = 0;         // 0 off, 1 event pairs per launch group, 2 the same with update groups run alone
   std::vector<hipEvent_t> evpool;
   size_t ev_used = 0;
   struct Pending { int cls; size_t e0, e1; double flops, bytes; };
@@ -297,6 +298,22 @@ void prof_add(tlr_handle_s* h, int cls, size_t e0, double flops, double bytes) {
   if (!h->prof) return;
   const size_t e1 = prof_mark(h);
   h->pend.push_back({cls, e0, e1, flops, bytes});
+}
+// Profiling mode 2: a column-update group runs alone.  Its stream first waits
+// for the other stream's queued work, and the other stream's later work waits
+// for the group, so that the group's event pair brackets only its own kernels
+// (with both streams busy, a kernel's workgroups can wait for CUs held by the
+// other stream's kernels, and that wait would fall between the events).
+hipStream_t other_stream(tlr_handle_s* h) { return h->s == h->s_main ? h->s_side : h->s_main; }
+void prof_alone_begin(tlr_handle_s* h) {
+  if (h->prof != 2 || !h->s_side) return;
+  HIPCHK(hipEventRecord(h->ev_px, other_stream(h)));
+  HIPCHK(hipStreamWaitEvent(h->s, h->ev_px, 0));
+}
+void prof_alone_end(tlr_handle_s* h) {
+  if (h->prof != 2 || !h->s_side) return;
+  HIPCHK(hipEventRecord(h->ev_py, h->s));
+  HIPCHK(hipStreamWaitEvent(other_stream(h), h->ev_py, 0));
 }
 // call after a stream synchronisation: folds finished pairs into the stats
 void prof_harvest(tlr_handle_s* h) {
@@ -1101,11 +1118,14 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)i0 * nb, mrows, (int64_t)j * nb, nbj, cblk, h->n,
                                epi_kind == kEpiDGenMinus, h->s));
     prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
+    prof_alone_begin(h);
     const size_t e0 = prof_mark(h);
     gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
          h->upd_tag);
+    // algorithmic bytes: W and U_row read once, C read (generated) and written
     prof_add(h, TLR_K_UPDATE, e0, 2.0 * mrows * nbj * (double)Ktrue,
-             8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + (double)mrows * nbj));
+             8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + 2.0 * (double)mrows * nbj));
+    prof_alone_end(h);
     i0 = i1;
   }
 }
@@ -1535,9 +1555,10 @@ void free_all(tlr_handle_s* h) {
     (void)hipStreamDestroy(h->s_side);
     h->s_side = nullptr;
   }
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-  h->ev_fork = h->ev_join = nullptr;
+  for (hipEvent_t* e : {&h->ev_fork, &h->ev_join, &h->ev_px, &h->ev_py}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
   for (void* p : h->dev_allocs) (void)hipFree(p);
   for (void* p : h->host_allocs) (void)hipHostFree(p);
   for (hipEvent_t& e : h->ev)
@@ -1678,6 +1699,8 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         HIPCHK(hipStreamCreateWithFlags(&h->s_side, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_px, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_py, hipEventDisableTiming));
         h->Wb2 = dalloc<double>(h, h->w_cap);
         h->Xb2 = dalloc<double>(h, h->x_cap);
         h->Urow2 = dalloc<double>(h, h->urow_cap);
@@ -1884,7 +1907,8 @@ tlr_status tlr_profile(tlr_handle_t h, int32_t enable) {
   return guarded(h, [&]() -> tlr_status {
     sync(h);
     prof_reset_pool(h);
-    h->prof = enable != 0;
+    if (enable < 0 || enable > 2) return TLR_EINVAL;
+    h->prof = enable;
     for (auto& k : h->kst) k = tlr_kstat{};
     return TLR_OK;
   });
