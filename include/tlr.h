@@ -60,10 +60,13 @@ typedef enum {
                                  rounding of a densely accumulated update is a full-rank
                                  perturbation of about 1e-7 of the update's magnitude, which the
                                  compression keeps: ranks (and dense tiles) grow unless tol is
-                                 well above that level.  On an ill-conditioned Sigma it can also
-                                 make a pivot negative: the factorisation is then repeated with
-                                 FP64 products, and the handle keeps FP64 products for its later
-                                 calls (tlr_info.prec_used, fp64_retries), so a TLR_ENOTSPD
+                                 well above that level.  The log-likelihood keeps the compression
+                                 accuracy only for a well-conditioned Sigma: where the smallest
+                                 eigenvalue is near that perturbation, the factor either loses
+                                 accuracy silently (seen: 3e-3 relative at eps = 1e-6) or meets a
+                                 negative pivot.  In the latter case the factorisation is repeated
+                                 with FP64 products and the handle keeps FP64 products for its
+                                 later calls (tlr_info.prec_used, fp64_retries), so a TLR_ENOTSPD
                                  result is never caused by the FP32 products */
 } tlr_prec;
 

@@ -49,6 +49,7 @@ struct tlr_handle_s {
   hipStream_t s_side = nullptr;   // tangent chain of the lockstep factorisation (gradient handles)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_px = nullptr, ev_py = nullptr;   // profiling mode 2: isolation of update groups
+  hipEvent_t ev_pre = nullptr, ev_fin = nullptr; // look-ahead: side-stream pre parts done / a step's compressions done
   // second set of update scratch for the side stream (same capacities)
   double *Wb2 = nullptr, *Xb2 = nullptr, *Urow2 = nullptr, *skw2 = nullptr, *tw2 = nullptr;
   int device = 0;
@@ -106,8 +107,11 @@ struct tlr_handle_s {
   } fam[2];
 
   // scratch
-  double* col = nullptr;   // n x nb, ld n
-  double* cold = nullptr;  // tangent column
+  double* colbase = nullptr;  // the column buffers, one allocation (compressions address tiles from here)
+  double* col = nullptr;      // n x nb, ld n
+  double* cold = nullptr;     // tangent column
+  double* col2 = nullptr;     // gradient handles: second primal and tangent columns, so that the
+  double* cold2 = nullptr;    //   next step's update can run while a column is compressed
   double* omega = nullptr; // nb x smax
   double* Ybuf = nullptr;  // nt blocks of nb x smax (ld nb): sketches, then small-QR workspace
   double* Q1 = nullptr;    // nt blocks of nb x smax (ld nb): range bases
@@ -137,6 +141,13 @@ struct tlr_handle_s {
   int64_t* lm_d = nullptr;
   int64_t* lm_h = nullptr;
   int64_t lm_cap = 0, lm_use = 0;
+  // the side stream's own staging set (swapped in with the side stream)
+  int* im2_d = nullptr;
+  int* im2_h = nullptr;
+  int64_t im2_cap = 0, im2_use = 0;
+  int64_t* lm2_d = nullptr;
+  int64_t* lm2_h = nullptr;
+  int64_t lm2_cap = 0, lm2_use = 0;
   QrcpTask* tk_d = nullptr;
   QrcpTask* tk_h = nullptr;
   int tk_cap = 0;
@@ -241,7 +252,7 @@ void lm_push(tlr_handle_s* h, const int64_t* hp, int64_t* dp, int64_t cnt) {
   HIPCHK(hipMemcpyAsync(dp, hp, cnt * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
 }
 void meta_reset(tlr_handle_s* h) {
-  // callers reset only after a stream synchronisation
+  // callers reset only after a synchronisation of the stream that owns the set
   h->im_use = 0;
   h->lm_use = 0;
 }
@@ -269,15 +280,23 @@ struct SideStream {
     std::swap(h->Urow, h->Urow2);
     std::swap(h->skw, h->skw2);
     std::swap(h->tw, h->tw2);
+    std::swap(h->im_d, h->im2_d);
+    std::swap(h->im_h, h->im2_h);
+    std::swap(h->im_cap, h->im2_cap);
+    std::swap(h->im_use, h->im2_use);
+    std::swap(h->lm_d, h->lm2_d);
+    std::swap(h->lm_h, h->lm2_h);
+    std::swap(h->lm_cap, h->lm2_cap);
+    std::swap(h->lm_use, h->lm2_use);
   }
 };
 
 // Make room for a group of metadata takes: when the staging buffers would
-// overflow, wait for the stream (every queued copy has then been consumed)
-// and recycle them.  Called before a group, never inside one.
+// overflow, wait for the stream that owns them (every queued copy has then
+// been consumed) and recycle them.  Called before a group, never inside one.
 void meta_reserve(tlr_handle_s* h, int64_t ints, int64_t longs) {
   if (h->im_use + ints <= h->im_cap && h->lm_use + longs <= h->lm_cap) return;
-  sync(h);
+  HIPCHK(hipStreamSynchronize(h->s));
   meta_reset(h);
   if (ints > h->im_cap || longs > h->lm_cap) NOMEM("metadata of one launch group");
 }
@@ -539,7 +558,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
       jof[g] = k;
       tloc[g] = t;
       rows[g] = tile_rows(h, jobs[k].i_first + t);
-      srow[g] = (jobs[k].src - h->col) + (int64_t)t * nb;
+      srow[g] = (jobs[k].src - h->colbase) + (int64_t)t * nb;
     }
   auto fail_rank = [&](int g) {
     h->bad_i = jobs[jof[g]].i_first + tloc[g];
@@ -586,7 +605,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
       im_push(h, m_h, m_d, 2 * (int64_t)cnt);
       lm_push(h, a_h, a_d, 2 * (int64_t)cnt);
       GemmSeg sg{};
-      sg.A = op_contig(h->col, ld, 0, 0);
+      sg.A = op_contig(h->colbase, ld, 0, 0);
       sg.B = op_contigT(h->omega, nb, 0, 0);
       sg.K = ncols;
       GemmBatch bt{};
@@ -612,7 +631,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
-    sync(h);
+    HIPCHK(hipStreamSynchronize(h->s));   // this stream only: the other may run the next step's updates
     meta_reset(h);
     throw_if_not_spd(h);
     std::vector<int> next;
@@ -686,7 +705,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
     lm_push(h, a_h, a_d, 3 * (int64_t)L);
     {
       GemmSeg sg{};
-      sg.A = op_contigT(h->col, ld, 0, 0);
+      sg.A = op_contigT(h->colbase, ld, 0, 0);
       sg.B = op_contigT(h->Q1, nb, 0, 0);
       sg.K = nb;
       GemmBatch bt{};
@@ -767,7 +786,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
     HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
     HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
-    sync(h);
+    HIPCHK(hipStreamSynchronize(h->s));
     meta_reset(h);
     for (int q = 0; q < L; ++q) {
       const int g = lr[q];
@@ -888,7 +907,8 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
     }
     im_push(h, m_h, m_d, 2 * (int64_t)ndense);
     lm_push(h, so_h, so_d, 2 * (int64_t)ndense);
-    HIPCHK(launch_batched_copy(h->col, ld, so_d, h->arena, nb, do_d, m_d, k_d, (int64_t)nb * ncols, ndense, h->s));
+    HIPCHK(launch_batched_copy(h->colbase, ld, so_d, h->arena, nb, do_d, m_d, k_d, (int64_t)nb * ncols, ndense,
+                               h->s));
   }
   prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
 }
@@ -951,7 +971,15 @@ struct LRTerm {
   const Family* Fj;   // right factor family (tiles of row j)
 };
 
-void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind) {
+// Column j of Sigma (or dSigma/dbeta, by epi_kind) minus the terms k in
+// [kb, ke) of the left-looking sum: gen = true writes the generated block
+// first, gen = false subtracts from what out already holds.  A column can so
+// take most of its terms while an earlier column is still being compressed,
+// and the rest afterwards.
+void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind, int kb,
+                       int ke, bool gen) {
+  kb = std::max(kb, 0);
+  ke = std::min(ke, j);
   const int nt = h->nt, nb = h->nb;
   const int nbj = tile_rows(h, j);
   // K layout: for each term, for each k < j, a segment of rank_j(k) columns
@@ -959,7 +987,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
   std::vector<int64_t> off((size_t)nterms * std::max(j, 1));
   int64_t R = 0, Ktrue = 0;
   for (int tm = 0; tm < nterms; ++tm)
-    for (int k = 0; k < j; ++k) {
+    for (int k = kb; k < ke; ++k) {
       off[(size_t)tm * j + k] = R;
       const int r = terms[tm].Fj->rk[tid_of(h, j, k)];
       R += r;
@@ -971,7 +999,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     if ((int64_t)nb * R > h->urow_cap) NOMEM("row factor buffer");
     int cnt = 0;
     for (int tm = 0; tm < nterms; ++tm)
-      for (int k = 0; k < j; ++k)
+      for (int k = kb; k < ke; ++k)
         if (terms[tm].Fj->rk[tid_of(h, j, k)] > 0) ++cnt;
     meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
     int *m_d, *k_d;
@@ -983,7 +1011,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     int c = 0;
     int64_t maxe = 0;
     for (int tm = 0; tm < nterms; ++tm)
-      for (int k = 0; k < j; ++k) {
+      for (int k = kb; k < ke; ++k) {
         const size_t id = tid_of(h, j, k);
         const int r = terms[tm].Fj->rk[id];
         if (r <= 0) continue;
@@ -1008,7 +1036,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       const int64_t wrows = (int64_t)(i1 + 1 - i0) * nb;
       int64_t xadd = 0;
       for (int tm = 0; tm < nterms; ++tm)
-        for (int k = 0; k < j; ++k) {
+        for (int k = kb; k < ke; ++k) {
           const int a = terms[tm].Fi->rk[tid_of(h, i1, k)];
           xadd += (int64_t)(a > h->maxrank ? nb : h->maxrank) * terms[tm].Fj->rk[tid_of(h, j, k)];
         }
@@ -1034,7 +1062,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           const Family& Fj = *terms[tm].Fj;
           int cnt = 0, maxa = 1, maxb = 1;
           for (int i = i0; i < i1; ++i)
-            for (int k = 0; k < j; ++k) {
+            for (int k = kb; k < ke; ++k) {
               const size_t ik = tid_of(h, i, k), jk = tid_of(h, j, k);
               const int a = Fi.rk[ik], b = Fj.rk[jk];
               if (a <= 0 || b <= 0 || (int)Fi.isdense[ik] != grp) continue;
@@ -1059,7 +1087,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           int64_t* wc_h = lm_take(h, cnt, &wc_d);
           int c = 0, maxrows = 1;
           for (int i = i0; i < i1; ++i)
-            for (int k = 0; k < j; ++k) {
+            for (int k = kb; k < ke; ++k) {
               const size_t ik = tid_of(h, i, k), jk = tid_of(h, j, k);
               const int a = Fi.rk[ik], b = Fj.rk[jk];
               if (a <= 0 || b <= 0 || (int)Fi.isdense[ik] != grp) continue;
@@ -1114,10 +1142,12 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     cs.K = R;
     // Matern generation of the block, then C -= W U_row^T
     double* cblk = out + (int64_t)(i0 - j) * nb;
-    const size_t eg = prof_mark(h);
-    HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)i0 * nb, mrows, (int64_t)j * nb, nbj, cblk, h->n,
-                               epi_kind == kEpiDGenMinus, h->s));
-    prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
+    if (gen) {
+      const size_t eg = prof_mark(h);
+      HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)i0 * nb, mrows, (int64_t)j * nb, nbj, cblk, h->n,
+                                 epi_kind == kEpiDGenMinus, h->s));
+      prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
+    }
     prof_alone_begin(h);
     const size_t e0 = prof_mark(h);
     gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
@@ -1266,36 +1296,49 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   family_reset(h, h->fam[0], 1);
   family_reset(h, h->fam[1], 1);
   h->dense_used = 0;
-  meta_reset(h);
   sync(h);
+  meta_reset(h);
+  h->im2_use = h->lm2_use = 0;   // the side stream's staging set (idle after the sync)
   Family& P = h->fam[0];
   Family& G = h->fam[1];
-  // generation + update + diagonal factorisation of primal column j
-  auto primal_column = [&](int j) {
-    const int nbj = tile_rows(h, j);
+  // Column buffers: with the look-ahead below, the column of step j + 1 is
+  // generated and updated while step j's columns are compressed, so even and
+  // odd columns take different buffers.
+  const bool side = tangent && h->s_side;
+  auto pbuf = [&](int j) { return (side && (j & 1)) ? h->col2 : h->col; };
+  auto tbuf = [&](int j) { return (side && (j & 1)) ? h->cold2 : h->cold; };
+  // generation and the terms k in [kb, ke) of primal column j
+  auto primal_update = [&](int j, int kb, int ke, bool gen) {
     LRTerm tm{&P, &P};
-    tlr_column_update(h, j, 1, &tm, h->col, kEpiGenMinus);
+    tlr_column_update(h, j, 1, &tm, pbuf(j), kEpiGenMinus, kb, ke, gen);
+  };
+  // diagonal factorisation of primal column j
+  auto primal_diag = [&](int j) {
+    const int nbj = tile_rows(h, j);
     const size_t e_d = prof_mark(h);
-    HIPCHK(launch_copy_block(h->col, h->n, diag_tile(h, j), nb, nbj, nbj, h->s));
+    HIPCHK(launch_copy_block(pbuf(j), h->n, diag_tile(h, j), nb, nbj, nbj, h->s));
     HIPCHK(tile_potrf_inv(diag_tile(h, j), nb, nbj, dinv_tile(h, j), nb, h->info_d, (int64_t)j * nb, h->tw, h->s));
     HIPCHK(launch_logdiag(diag_tile(h, j), nb, nbj, h->scal + j, h->s));
     prof_add(h, TLR_K_DIAG, e_d, 2.0 / 3.0 * nbj * (double)nbj * nbj, 16.0 * nbj * (double)nbj);
   };
   auto primal_job = [&](int j) {
     const int T = nt - j - 1;
-    return ColumnJob{h->col + tile_rows(h, j), j + 1, T, j, &P, predict_ranks(h, P, j, T),
+    return ColumnJob{pbuf(j) + tile_rows(h, j), j + 1, T, j, &P, predict_ranks(h, P, j, T),
                      h->dinv_off + (int64_t)j * nb * nb, 0};
   };
   // dC(:, j) = dSigma/dbeta - sum_k [dL_ik L_jk^T + L_ik dL_jk^T]; the
   // tangent of the diagonal step; dC_ij <- dC_ij - L_ij dL_jj^T (then
   // compressed: dL_ij = (that) L_jj^{-T}, low-rank V <- L_jj^{-1} V)
-  auto tangent_column = [&](int j) {
-    const int nbj = tile_rows(h, j);
+  auto tangent_update = [&](int j, int kb, int ke, bool gen) {
     LRTerm tt[2] = {{&G, &P}, {&P, &G}};
-    tlr_column_update(h, j, 2, tt, h->cold, kEpiDGenMinus);
+    tlr_column_update(h, j, 2, tt, tbuf(j), kEpiDGenMinus, kb, ke, gen);
+  };
+  auto tangent_rest = [&](int j) {
+    const int nbj = tile_rows(h, j);
+    double* cold = tbuf(j);
     double* ddj = h->Dd + (int64_t)j * nb * nb;
     const size_t e_td = prof_mark(h);
-    tangent_diag(h, j, h->cold, h->n, diag_tile(h, j), nb, ddj, nb);
+    tangent_diag(h, j, cold, h->n, diag_tile(h, j), nb, ddj, nb);
     prof_add(h, TLR_K_DIAG, e_td, 6.0 * nbj * (double)nbj * nbj, 32.0 * nbj * (double)nbj);
     const int T = nt - j - 1;
     if (T <= 0) return;
@@ -1365,13 +1408,13 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       cs.K = kmax;
       GemmBatch cb{};
       cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
-      gemm(h, mmax, nbj, 1, &cs, h->cold, h->n, epi_linear(-1.0, 1.0), &cb);
+      gemm(h, mmax, nbj, 1, &cs, cold, h->n, epi_linear(-1.0, 1.0), &cb);
     }
     prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
   };
   auto tangent_job = [&](int j) {
     const int T = nt - j - 1;
-    return ColumnJob{h->cold + tile_rows(h, j), j + 1, T, j, &G, predict_ranks(h, G, j, T),
+    return ColumnJob{tbuf(j) + tile_rows(h, j), j + 1, T, j, &G, predict_ranks(h, G, j, T),
                      h->dinv_off + (int64_t)j * nb * nb, 0};
   };
   auto finish = [&](std::vector<ColumnJob>& jobs) {
@@ -1380,32 +1423,78 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
   };
 
-  primal_column(0);
-  {
-    std::vector<ColumnJob> jobs{primal_job(0)};
-    finish(jobs);
-  }
-  for (int j = 0; j < nt; ++j) {
-    std::vector<ColumnJob> jobs;
-    const bool side = tangent && h->s_side;
-    if (side) {  // the two chains up to the shared compression run concurrently
-      HIPCHK(hipEventRecord(h->ev_fork, h->s_main));
-      HIPCHK(hipStreamWaitEvent(h->s_side, h->ev_fork, 0));
+  if (!side) {
+    // one stream: each step updates, factors and compresses its columns in turn
+    primal_update(0, 0, 0, true);
+    primal_diag(0);
+    {
+      std::vector<ColumnJob> jobs{primal_job(0)};
+      finish(jobs);
     }
-    if (j + 1 < nt) primal_column(j + 1);
-    if (tangent) {
-      if (side) {
-        SideStream ss(h);
-        tangent_column(j);
-        HIPCHK(hipEventRecord(h->ev_join, h->s_side));
-      } else {
-        tangent_column(j);
+    for (int j = 0; j < nt; ++j) {
+      std::vector<ColumnJob> jobs;
+      if (j + 1 < nt) {
+        primal_update(j + 1, 0, j + 1, true);
+        primal_diag(j + 1);
+        jobs.push_back(primal_job(j + 1));
       }
+      if (tangent) {
+        tangent_update(j, 0, j, true);
+        tangent_rest(j);
+        jobs.push_back(tangent_job(j));
+      }
+      finish(jobs);
     }
-    if (side) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_join, 0));
-    if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
-    if (tangent) jobs.push_back(tangent_job(j));
-    finish(jobs);
+  } else {
+    // Two streams, lockstep with look-ahead.  Step j compresses primal column
+    // j + 1 and tangent column j together (main stream).  Everything of those
+    // columns that does not depend on step j - 1's compressions (generation
+    // and the terms of columns up to j - 1 for the primal, up to j - 2 for the
+    // tangent: "pre") runs on the side stream while step j - 1 compresses;
+    // afterwards the last term, the diagonal steps and the tangent's
+    // correction ("post") complete them, the primal on the main stream and
+    // the tangent on the side stream.
+    auto pre = [&](int j) {   // side stream: pre parts of step j
+      SideStream ss(h);
+      if (j + 1 < nt) primal_update(j + 1, 0, j, true);
+      tangent_update(j, 0, j - 1, true);
+      HIPCHK(hipEventRecord(h->ev_pre, h->s));
+    };
+    primal_update(0, 0, 0, true);
+    primal_diag(0);
+    {
+      std::vector<ColumnJob> jobs{primal_job(0)};
+      finish(jobs);
+    }
+    HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
+    {
+      SideStream ss(h);
+      HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
+    }
+    pre(0);
+    for (int j = 0; j < nt; ++j) {
+      // main: the rest of primal column j + 1 once its pre part is done
+      HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_pre, 0));
+      if (j + 1 < nt) {
+        primal_update(j + 1, j, j + 1, false);
+        primal_diag(j + 1);
+      }
+      {
+        // side: the rest of tangent column j, after step j - 1's compressions
+        SideStream ss(h);
+        HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
+        tangent_update(j, j - 1, j, false);
+        tangent_rest(j);
+        HIPCHK(hipEventRecord(h->ev_join, h->s));
+      }
+      if (j + 1 < nt) pre(j + 1);   // overlaps the compressions below
+      HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_join, 0));
+      std::vector<ColumnJob> jobs;
+      if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
+      jobs.push_back(tangent_job(j));
+      finish(jobs);
+      HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
+    }
   }
   family_upload(h, P);
   sync(h);
@@ -1555,7 +1644,7 @@ void free_all(tlr_handle_s* h) {
     (void)hipStreamDestroy(h->s_side);
     h->s_side = nullptr;
   }
-  for (hipEvent_t* e : {&h->ev_fork, &h->ev_join, &h->ev_px, &h->ev_py}) {
+  for (hipEvent_t* e : {&h->ev_fork, &h->ev_join, &h->ev_px, &h->ev_py, &h->ev_pre, &h->ev_fin}) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
@@ -1624,9 +1713,14 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->d_tab = dalloc<double>(h, kTabSize);
     h->h_tab.assign(kTabSize, 0.0);
     if (h->dense) h->Dinv = dalloc<double>(h, nt * nb * nb);
-    // one allocation: compressions of both columns address their tiles from h->col
-    h->col = dalloc<double>(h, n * nb * (h->grad ? 2 : 1));
-    if (h->grad) h->cold = h->col + n * nb;
+    // one allocation: compressions address the tiles of every column buffer from h->colbase
+    h->colbase = dalloc<double>(h, n * nb * (h->grad ? 4 : 1));
+    h->col = h->colbase;
+    if (h->grad) {
+      h->cold = h->colbase + n * nb;
+      h->col2 = h->colbase + 2 * n * nb;
+      h->cold2 = h->colbase + 3 * n * nb;
+    }
     h->tw = dalloc<double>(h, 64 * nb + 3 * nb * nb);
     h->vec = dalloc<double>(h, 4 * n);
     h->scal = dalloc<double>(h, 4 * nt + 16);
@@ -1701,6 +1795,8 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_px, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_py, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_pre, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fin, hipEventDisableTiming));
         h->Wb2 = dalloc<double>(h, h->w_cap);
         h->Xb2 = dalloc<double>(h, h->x_cap);
         h->Urow2 = dalloc<double>(h, h->urow_cap);
@@ -1713,6 +1809,16 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->im_h = halloc<int>(h, h->im_cap);
       h->lm_d = dalloc<int64_t>(h, h->lm_cap);
       h->lm_h = halloc<int64_t>(h, h->lm_cap);
+      if (h->grad) {
+        // the side stream stages the look-ahead updates of whole columns between
+        // its recycling points (when full, the host waits for that stream)
+        h->im2_cap = 4 * h->im_cap;
+        h->lm2_cap = 4 * h->lm_cap;
+        h->im2_d = dalloc<int>(h, h->im2_cap);
+        h->im2_h = halloc<int>(h, h->im2_cap);
+        h->lm2_d = dalloc<int64_t>(h, h->lm2_cap);
+        h->lm2_h = halloc<int64_t>(h, h->lm2_cap);
+      }
       h->tk_cap = (int)gc;
       h->tk_d = dalloc<QrcpTask>(h, gc);
       h->tk_h = halloc<QrcpTask>(h, gc);
