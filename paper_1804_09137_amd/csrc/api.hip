@@ -47,9 +47,11 @@ struct tlr_handle_s {
   hipStream_t s = nullptr;        // the stream work is issued on (s_main, or s_side inside SideStream)
   hipStream_t s_main = nullptr;   // the caller's stream
   hipStream_t s_side = nullptr;   // tangent chain of the lockstep factorisation (gradient handles)
+  hipStream_t s_diag = nullptr;   // gradient handles: primal diagonal steps, beside the compressions
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_px = nullptr, ev_py = nullptr;   // profiling mode 2: isolation of update groups
   hipEvent_t ev_pre = nullptr, ev_fin = nullptr; // look-ahead: side-stream pre parts done / a step's compressions done
+  hipEvent_t ev_post = nullptr, ev_diag = nullptr; // a primal column complete / its diagonal step done
   // second set of update scratch for the side stream (same capacities)
   double *Wb2 = nullptr, *Xb2 = nullptr, *Urow2 = nullptr, *skw2 = nullptr, *tw2 = nullptr;
   int device = 0;
@@ -260,6 +262,7 @@ void prof_harvest(tlr_handle_s* h);
 void sync(tlr_handle_s* h) {
   HIPCHK(hipStreamSynchronize(h->s_main));
   if (h->s_side) HIPCHK(hipStreamSynchronize(h->s_side));
+  if (h->s_diag) HIPCHK(hipStreamSynchronize(h->s_diag));
   prof_harvest(h);
 }
 
@@ -289,6 +292,14 @@ struct SideStream {
     std::swap(h->lm_cap, h->lm2_cap);
     std::swap(h->lm_use, h->lm2_use);
   }
+};
+
+// Issue on the diagonal-step stream until destroyed (main scratch set: only
+// the diagonal factorisation's workspace is used there).
+struct DiagStream {
+  tlr_handle_s* h;
+  explicit DiagStream(tlr_handle_s* hh) : h(hh) { h->s = h->s_diag; }
+  ~DiagStream() { h->s = h->s_main; }
 };
 
 // Make room for a group of metadata takes: when the staging buffers would
@@ -1417,8 +1428,12 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     return ColumnJob{tbuf(j) + tile_rows(h, j), j + 1, T, j, &G, predict_ranks(h, G, j, T),
                      h->dinv_off + (int64_t)j * nb * nb, 0};
   };
-  auto finish = [&](std::vector<ColumnJob>& jobs) {
+  // compress, then V <- L_jj^{-1} V; with the look-ahead the diagonal step
+  // of the newest primal column runs beside the compression (only the
+  // triangular solves need it), so the main stream waits for it in between
+  auto finish = [&](std::vector<ColumnJob>& jobs, bool wait_diag) {
     compress_columns(h, jobs);
+    if (wait_diag) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_diag, 0));
     for (const ColumnJob& jb : jobs)
       if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
   };
@@ -1429,7 +1444,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     primal_diag(0);
     {
       std::vector<ColumnJob> jobs{primal_job(0)};
-      finish(jobs);
+      finish(jobs, false);
     }
     for (int j = 0; j < nt; ++j) {
       std::vector<ColumnJob> jobs;
@@ -1443,7 +1458,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         tangent_rest(j);
         jobs.push_back(tangent_job(j));
       }
-      finish(jobs);
+      finish(jobs, false);
     }
   } else {
     // Two streams, lockstep with look-ahead.  Step j compresses primal column
@@ -1464,7 +1479,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     primal_diag(0);
     {
       std::vector<ColumnJob> jobs{primal_job(0)};
-      finish(jobs);
+      finish(jobs, false);
     }
     HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
     {
@@ -1473,26 +1488,32 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     }
     pre(0);
     for (int j = 0; j < nt; ++j) {
-      // main: the rest of primal column j + 1 once its pre part is done
+      // main: the rest of primal column j + 1 waits for its pre part
       HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_pre, 0));
-      if (j + 1 < nt) {
-        primal_update(j + 1, j, j + 1, false);
-        primal_diag(j + 1);
-      }
       {
-        // side: the rest of tangent column j, after step j - 1's compressions
+        // side: the rest of tangent column j, after step j - 1's compressions.
+        // Issued first: the host issues launches about as fast as the main
+        // stream's diagonal chain runs them, and this is as urgent.
         SideStream ss(h);
         HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
         tangent_update(j, j - 1, j, false);
         tangent_rest(j);
         HIPCHK(hipEventRecord(h->ev_join, h->s));
       }
+      if (j + 1 < nt) {
+        primal_update(j + 1, j, j + 1, false);
+        HIPCHK(hipEventRecord(h->ev_post, h->s_main));
+        DiagStream ds(h);   // beside the compressions below
+        HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
+        primal_diag(j + 1);
+        HIPCHK(hipEventRecord(h->ev_diag, h->s));
+      }
       if (j + 1 < nt) pre(j + 1);   // overlaps the compressions below
       HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_join, 0));
       std::vector<ColumnJob> jobs;
       if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
       jobs.push_back(tangent_job(j));
-      finish(jobs);
+      finish(jobs, j + 1 < nt);
       HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
     }
   }
@@ -1630,6 +1651,7 @@ tlr_status guarded(tlr_handle_s* h, F&& f) {
     if (h && e.st != TLR_ENOMEM) {
       (void)hipStreamSynchronize(h->s_main);
       if (h->s_side) (void)hipStreamSynchronize(h->s_side);
+      if (h->s_diag) (void)hipStreamSynchronize(h->s_diag);
     }
     return e.st;
   } catch (const std::bad_alloc&) {
@@ -1639,12 +1661,14 @@ tlr_status guarded(tlr_handle_s* h, F&& f) {
 
 void free_all(tlr_handle_s* h) {
   if (h->s_main) (void)hipStreamSynchronize(h->s_main);
-  if (h->s_side) {
-    (void)hipStreamSynchronize(h->s_side);
-    (void)hipStreamDestroy(h->s_side);
-    h->s_side = nullptr;
+  for (hipStream_t* st : {&h->s_side, &h->s_diag}) {
+    if (!*st) continue;
+    (void)hipStreamSynchronize(*st);
+    (void)hipStreamDestroy(*st);
+    *st = nullptr;
   }
-  for (hipEvent_t* e : {&h->ev_fork, &h->ev_join, &h->ev_px, &h->ev_py, &h->ev_pre, &h->ev_fin}) {
+  for (hipEvent_t* e : {&h->ev_fork, &h->ev_join, &h->ev_px, &h->ev_py, &h->ev_pre, &h->ev_fin, &h->ev_post,
+                        &h->ev_diag}) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
@@ -1791,12 +1815,15 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       if (h->grad) {
         // the tangent column of the lockstep runs on its own stream with its own scratch
         HIPCHK(hipStreamCreateWithFlags(&h->s_side, hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&h->s_diag, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_px, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_py, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_pre, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_fin, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_post, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_diag, hipEventDisableTiming));
         h->Wb2 = dalloc<double>(h, h->w_cap);
         h->Xb2 = dalloc<double>(h, h->x_cap);
         h->Urow2 = dalloc<double>(h, h->urow_cap);
