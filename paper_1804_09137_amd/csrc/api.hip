@@ -508,6 +508,7 @@ void throw_if_not_spd(tlr_handle_s* h) {
 // Rank predictions for a column: final ranks and range-finder ranks.
 struct RankPred {
   std::vector<int> k, r1;
+  bool hist = false;   // from the same tiles of the previous factorisation (else from neighbours)
 };
 
 // ---------------------------------------------------------------------------
@@ -587,7 +588,12 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
       t1[g] = pred.r1[t];
       continue;
     }
-    sz[g] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred.r1[t] + pred.r1[t] * 3 / 20 + 16)));
+    // first sketch width: the predicted range rank plus a margin (5% when it is
+    // the same tile's rank in the previous factorisation, 15% when it comes
+    // from neighbouring tiles) plus the 8-sample tail and slack; a sketch
+    // that turns out too narrow is redone 1.3x wider
+    const int margin = pred.hist ? pred.r1[t] / 20 : pred.r1[t] * 3 / 20;
+    sz[g] = (int)std::min<int64_t>(h->smax, std::max<int64_t>(32, pad16(pred.r1[t] + margin + 16)));
     todo.push_back(g);
   }
   // 1-2. sketch and range rank; a tile with fewer than 8 samples beyond its
@@ -1280,6 +1286,7 @@ RankPred predict_ranks(const tlr_handle_s* h, const Family& F, int j, int T) {
   RankPred p;
   p.k.resize(T);
   p.r1.resize(T);
+  p.hist = F.hist;
   for (int t = 0; t < T; ++t) {
     const int i = j + 1 + t;
     if (F.hist) {
