@@ -22,6 +22,7 @@
 #include "grad.h"
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <thread>
 #include <atomic>
@@ -536,7 +537,9 @@ struct ColumnJob {
   int g0;
 };
 
-void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
+// during: host work to do while the first launches run (called once, before
+// the first wait for this stream; the caller calls it if no tile needed it).
+void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::function<void()>* during = nullptr) {
   int G = 0;
   for (ColumnJob& jb : jobs) {
     jb.g0 = G;
@@ -648,6 +651,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs) {
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
+    if (during && *during) {   // the host would otherwise wait here
+      (*during)();
+      *during = nullptr;
+    }
     HIPCHK(hipStreamSynchronize(h->s));   // this stream only: the other may run the next step's updates
     meta_reset(h);
     throw_if_not_spd(h);
@@ -1438,8 +1445,9 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   // compress, then V <- L_jj^{-1} V; with the look-ahead the diagonal step
   // of the newest primal column runs beside the compression (only the
   // triangular solves need it), so the main stream waits for it in between
-  auto finish = [&](std::vector<ColumnJob>& jobs, bool wait_diag) {
-    compress_columns(h, jobs);
+  auto finish = [&](std::vector<ColumnJob>& jobs, bool wait_diag, std::function<void()> during = nullptr) {
+    compress_columns(h, jobs, &during);
+    if (during) during();
     if (wait_diag) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_diag, 0));
     for (const ColumnJob& jb : jobs)
       if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
@@ -1510,17 +1518,24 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       if (j + 1 < nt) {
         primal_update(j + 1, j, j + 1, false);
         HIPCHK(hipEventRecord(h->ev_post, h->s_main));
-        DiagStream ds(h);   // beside the compressions below
-        HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
-        primal_diag(j + 1);
-        HIPCHK(hipEventRecord(h->ev_diag, h->s));
       }
-      if (j + 1 < nt) pre(j + 1);   // overlaps the compressions below
       HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_join, 0));
       std::vector<ColumnJob> jobs;
       if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
       jobs.push_back(tangent_job(j));
-      finish(jobs, j + 1 < nt);
+      // The compressions of step j are issued first; the diagonal step of
+      // primal column j + 1 (its own stream) and the pre parts of step j + 1
+      // (side stream) are issued while they run, in the host's first wait.
+      finish(jobs, j + 1 < nt, [&]() {
+        if (j + 1 >= nt) return;
+        {
+          DiagStream ds(h);
+          HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
+          primal_diag(j + 1);
+          HIPCHK(hipEventRecord(h->ev_diag, h->s));
+        }
+        pre(j + 1);
+      });
       HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
     }
   }
