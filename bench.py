@@ -69,7 +69,8 @@ def batched(args) -> dict:
     """Serving-style run: independent fields of uneven size (n uniform in
     [2,000, 20,000], sigma^2 ~ U(0.5, 2), beta ~ U(0.03, 0.3), nu in {0.5,
     1.5}; seeded), tile 400, one gradient handle per field on a stream of its
-    own, evaluated concurrently by tlr_loglik_grad_batched.  Handles are
+    own (one stream per handle: the fields' concurrency fills the GPU),
+    evaluated concurrently by tlr_loglik_grad_batched.  Handles are
     created ahead of the timed region (the fields' worst-case storage does not
     all fit at once, so the fields go in groups that fit); a step is one l +
     gradient of every field.  The same handles evaluated one field at a time
@@ -141,7 +142,7 @@ def batched(args) -> dict:
             run_group(cur)
             cur, used = [], 0.0
         h = P.Handle(sp.n, args.batched_nb, tol=args.eps, maxrank=args.batched_nb // 2, want_grad=True,
-                     prec=args.prec, stream=torch.cuda.Stream())
+                     prec=args.prec, stream=torch.cuda.Stream(), single_stream=not args.multi_stream)
         b = h.info().device_bytes
         used += b
         last = (sp.n, b)
@@ -164,6 +165,7 @@ def batched(args) -> dict:
                                    f"{args.batched_nb}, eps={args.eps:g}, {args.prec}, {args.threads} host threads",
                        "fields": nf, "nb": args.batched_nb, "eps": args.eps, "prec": args.prec,
                        "threads": args.threads, "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                       "streams_per_field": 3 if args.multi_stream else 1,
                        "total_n": int(sum(sp.n for sp in specs)),
                        "group_budget_GB": args.batched_budget_gb},
             "sequential_fields_per_s": nf / t_seq, "concurrency_gain": t_seq / t_bat,
@@ -215,6 +217,8 @@ def main():
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--batched-nb", type=int, default=400)
     ap.add_argument("--threads", type=int, default=16, help="host threads of the batched call")
+    ap.add_argument("--multi-stream", action="store_true",
+                    help="--batched: give each field's handle its side and diagonal streams too")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for --batched when the environment does not set it")
     ap.add_argument("--batched-budget-gb", type=float, default=200.0,

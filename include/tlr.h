@@ -73,6 +73,12 @@ typedef enum {
 /* tlr_opts.flags */
 #define TLR_FLAG_STRICT_RANK 1  /* a tile needing rank > maxrank is an error (TLR_ERANK) instead of
                                    being kept dense */
+#define TLR_FLAG_SINGLE_STREAM 2 /* TLR with want_grad: issue everything on the caller's stream.  By
+                                   default such a handle also runs the tangent chain and the diagonal
+                                   steps on two streams of its own, with a look-ahead over the
+                                   compressions (faster alone, but many handles evaluated at once,
+                                   as by tlr_loglik_grad_batched, then contend for hardware queues)
+                                   and holds two more n x nb column buffers */
 
 typedef struct {
   int64_t n;          /* number of locations (>= 1) */

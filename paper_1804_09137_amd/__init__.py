@@ -55,7 +55,7 @@ class Handle:
 
     def __init__(self, n: int, nb: int, tol: float = 1e-9, maxrank: int = 0, mode: str = "tlr",
                  prec: str = "fp64", want_grad: bool = False, seed: int = 0, strict_rank: bool = False,
-                 stream=None):
+                 stream=None, single_stream: bool = False):
         import torch
         self._lib = _lib.load()
         o = _lib.Opts()
@@ -64,7 +64,7 @@ class Handle:
         o.prec = {"fp64": _lib.PREC_FP64, "fp32_updates": _lib.PREC_FP32_UPDATES}[prec]
         o.want_grad = 1 if want_grad else 0
         o.seed = int(seed)
-        o.flags = _lib.FLAG_STRICT_RANK if strict_rank else 0
+        o.flags = (_lib.FLAG_STRICT_RANK if strict_rank else 0) | (_lib.FLAG_SINGLE_STREAM if single_stream else 0)
         self.n, self.nb, self.mode = int(n), int(nb), mode
         self.nt = (self.n + self.nb - 1) // self.nb
         if stream is None:

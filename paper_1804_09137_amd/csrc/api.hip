@@ -61,6 +61,7 @@ struct tlr_handle_s {
   int gcap = 0;         // tile slots of the compression scratch
   int upd_tag = 1;      // column-update kernels of the running factorisation: 1 FP64, 2 FP32 products
   bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
+  bool multi = false;   // side and diagonal streams (TLR gradient handles without TLR_FLAG_SINGLE_STREAM)
   bool dense = false, grad = false, strict = false;
   int64_t slot = 0;      // doubles per low-rank slot (nb * maxrank)
   int64_t vslot = 0;     // doubles per V~ staging block (nb * (maxrank + 1)): the
@@ -1746,6 +1747,9 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     mr = std::min(mr, kQrMaxCols - 96);
     h->maxrank = mr;
     h->strict = (o->flags & TLR_FLAG_STRICT_RANK) != 0;
+    // TLR gradient handles run the tangent chain and the diagonal steps on
+    // streams of their own unless asked for one stream
+    h->multi = h->grad && !h->dense && !(o->flags & TLR_FLAG_SINGLE_STREAM);
     const int mslot = mr;
     // sketch width cap: a tile whose range finder needs more columns than
     // this is (unless strict) kept dense
@@ -1760,10 +1764,10 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->h_tab.assign(kTabSize, 0.0);
     if (h->dense) h->Dinv = dalloc<double>(h, nt * nb * nb);
     // one allocation: compressions address the tiles of every column buffer from h->colbase
-    h->colbase = dalloc<double>(h, n * nb * (h->grad ? 4 : 1));
+    h->colbase = dalloc<double>(h, n * nb * (h->multi ? 4 : (h->grad ? 2 : 1)));
     h->col = h->colbase;
-    if (h->grad) {
-      h->cold = h->colbase + n * nb;
+    if (h->grad) h->cold = h->colbase + n * nb;
+    if (h->multi) {
       h->col2 = h->colbase + 2 * n * nb;
       h->cold2 = h->colbase + 3 * n * nb;
     }
@@ -1834,7 +1838,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * nb * nb);
       h->Wb = dalloc<double>(h, h->w_cap);
       h->Xb = dalloc<double>(h, h->x_cap);
-      if (h->grad) {
+      if (h->multi) {
         // the tangent column of the lockstep runs on its own stream with its own scratch
         HIPCHK(hipStreamCreateWithFlags(&h->s_side, hipStreamNonBlocking));
         HIPCHK(hipStreamCreateWithFlags(&h->s_diag, hipStreamNonBlocking));
@@ -1858,7 +1862,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->im_h = halloc<int>(h, h->im_cap);
       h->lm_d = dalloc<int64_t>(h, h->lm_cap);
       h->lm_h = halloc<int64_t>(h, h->lm_cap);
-      if (h->grad) {
+      if (h->multi) {
         // the side stream stages the look-ahead updates of whole columns between
         // its recycling points (when full, the host waits for that stream)
         h->im2_cap = 4 * h->im_cap;

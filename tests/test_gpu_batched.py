@@ -27,24 +27,26 @@ def _field(n, seed, th):
     return x, y, z
 
 
-def _handles(streams=True):
+def _handles(streams=True, single_stream=False):
     import torch
     import paper_1804_09137_amd as P
-    return [P.Handle(n, nb, tol=EPS, maxrank=nb, want_grad=True, stream=torch.cuda.Stream() if streams else None)
+    return [P.Handle(n, nb, tol=EPS, maxrank=nb, want_grad=True, stream=torch.cuda.Stream() if streams else None,
+                     single_stream=single_stream)
             for n, nb, _ in FIELDS]
 
 
-def test_batched_equals_sequential_and_oracle():
+@pytest.mark.parametrize("single_stream", [False, True])
+def test_batched_equals_sequential_and_oracle(single_stream):
     import torch
     import paper_1804_09137_amd as P
     data = [_field(n, 10 + f, th) for f, (n, nb, th) in enumerate(FIELDS)]
     dev = [to_dev(*d) for d in data]
     thetas = [th for _, _, th in FIELDS]
     torch.cuda.synchronize()
-    ll_b, g_b = P.loglik_grad_batched(_handles(), [d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev],
-                                      thetas, nthreads=4)
+    ll_b, g_b = P.loglik_grad_batched(_handles(single_stream=single_stream), [d[0] for d in dev],
+                                      [d[1] for d in dev], [d[2] for d in dev], thetas, nthreads=4)
     for f, ((n, nb, th), (x, y, z), (xd, yd, zd)) in enumerate(zip(FIELDS, data, dev)):
-        h = P.Handle(n, nb, tol=EPS, maxrank=nb, want_grad=True)
+        h = P.Handle(n, nb, tol=EPS, maxrank=nb, want_grad=True, single_stream=single_stream)
         ll, g = h.loglik_grad(xd, yd, zd, th)
         assert ll == ll_b[f] and g[0] == g_b[f, 0] and g[1] == g_b[f, 1], f
         ref = D.gradient(x, y, z, th)
@@ -87,3 +89,24 @@ def test_batched_rejects_a_repeated_handle():
     d = to_dev(*_field(FIELDS[0][0], 1, FIELDS[0][2]))
     with pytest.raises(P.TLRError):
         P.loglik_grad_batched([hs[0], hs[0]], [d[0]] * 2, [d[1]] * 2, [d[2]] * 2, [FIELDS[0][2]] * 2)
+
+
+def test_single_stream_handle_matches_the_default_one():
+    # TLR_FLAG_SINGLE_STREAM: the same factorisation issued on one stream (no
+    # look-ahead, the update of a column in one pass): equal up to the
+    # summation order of the split updates and what it does to the ranks
+    import paper_1804_09137_amd as P
+    n, nb, eps = 4000, 400, 1e-7
+    th = (1.0, 0.1, 0.5)
+    x, y, z = _field(n, 5, th)
+    xd, yd, zd = to_dev(x, y, z)
+    out = []
+    for single in (False, True):
+        h = P.Handle(n, nb, tol=eps, maxrank=nb // 2, want_grad=True, single_stream=single)
+        out.append(h.loglik_grad(xd, yd, zd, th))
+        log(f"single_stream={single}: ll {out[-1][0]!r} grad {out[-1][1]}")
+    # each is within about 3e-9 (l) and 6e-7 (score) of the exact values at
+    # this eps; rounding may move a rank decision at the threshold
+    assert abs(out[0][0] - out[1][0]) <= 1e-8 * abs(out[0][0])
+    for i in range(2):
+        assert abs(out[0][1][i] - out[1][1][i]) <= 5e-6 * abs(out[0][1][i])
