@@ -184,12 +184,12 @@ tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y,
  * fields concurrently so that their kernels overlap on the GPU.  ll, info and
  * status (per-field tlr_status) may be null.  Returns the first failing
  * field's status (in field order), else TLR_OK; tlr_last_error on the calling
- * thread then describes that field's failure.  A handle uses two streams; the
- * HIP runtime spreads all streams of a process over GPU_MAX_HW_QUEUES hardware
- * queues (4 unless set before the runtime starts), so fields overlap only as
- * far as that allows (16 threads over 16 queues evaluated 32 fields of
- * n <= 20,000 3.6x faster than one at a time; 32 queues slow every stream
- * down).  Batched evaluation is not in the paper: it serves many small
+ * thread then describes that field's failure.  The HIP runtime spreads all
+ * streams of a process over GPU_MAX_HW_QUEUES hardware queues (4 unless set
+ * before the runtime starts), so fields overlap only as far as that allows:
+ * with handles created with TLR_FLAG_SINGLE_STREAM, 16 threads over 16 queues
+ * evaluated 32 fields of n <= 20,000 5.6x faster than one at a time; 32
+ * queues slow every stream down.  Batched evaluation is not in the paper: it serves many small
  * fields, whose individual evaluations cannot fill the GPU. */
 tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, const double* const* d_x,
                                    const double* const* d_y, const double* const* d_z, const double* theta,
