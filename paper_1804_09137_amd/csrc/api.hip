@@ -687,6 +687,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   std::vector<int> k2(G, 0);
   if (L > 0) {
     // Q1 = Q_y [I_t1; 0]
+    int max_kx = 0;
     for (int q = 0; q < L; ++q) {
       const int g = lr[q];
       HqrTask& tk = hq_ay[q];
@@ -700,10 +701,11 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.ldx = nb;
       tk.kx = t1[g];
       tk.identity = 1;
+      max_kx = std::max(max_kx, tk.kx);
       cflops += 2.0 * tk.m * t1[g] * t1[g];
     }
     HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s));
+    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx));
     meta_reserve(h, 3 * (int64_t)L, 3 * (int64_t)L);
     // 3. project: Bt_g = C_g^T Q1_g (ncols x t1)
     int *m_d, *n_d, *k_d;
@@ -863,9 +865,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   // 6. V~ = Q_b [Q_r; 0] and U_g = Q1_g Z_g (m_g x k_g) for the low-rank tiles
   meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
   if (nlr > 0) {
-    int q = 0;
+    int q = 0, max_kx = 0;
     for (int g = 0; g < G; ++g) {
       if (dense[g] || k2[g] == 0) continue;
+      max_kx = std::max(max_kx, k2[g]);
       HqrTask& tk = hq_ab[q++];
       tk = HqrTask{};
       tk.A = h->Bt + (int64_t)g * nb * h->smax;
@@ -879,7 +882,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.xrows = t1[g];
     }
     HIPCHK(hipMemcpyAsync(h->hq_d + 3 * gc, hq_ab, nlr * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s));
+    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s, max_kx));
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, nlr, &m_d);
     int* n_h = im_take(h, nlr, &n_d);

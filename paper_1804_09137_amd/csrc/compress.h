@@ -55,7 +55,11 @@ struct HqrTask {
 hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s, int max_m = kQrMaxRows);
 hipError_t launch_qrcp_reg(const QrcpTask* d_tasks, int count, hipStream_t s);
 hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
-hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s);
+// X columns are split over workgroups kApplyCols at a time: max_kx must be
+// at least every task's kx (columns beyond the split it covers are left
+// untouched).
+constexpr int kApplyCols = 32;
+hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx);
 hipError_t launch_copy_upper(const double* src, int64_t sld, const int64_t* soff, double* dst, int64_t dld,
                              const int64_t* doff, const int* nn, int nmax, int count, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint32_t seed, hipStream_t s);

@@ -329,31 +329,36 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
 // X starts as [I_kx; 0] (then only columns >= c0 change in panel c0);
 // otherwise rows >= xrows of X are cleared first.
 // ---------------------------------------------------------------------------
+// Workgroup (task, y) applies Q to columns [y * kApplyCols, (y + 1) *
+// kApplyCols) of X: the columns are independent, so a wide X (the largest
+// tile of a column sets the launch time) is spread over several CUs.
 __global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict__ tasks) {
   const HqrTask tk = tasks[blockIdx.x];
   __shared__ double P[PB * LDP];
   __shared__ double red[NW * RS];
   __shared__ double Wf[256], Wp[256], Ts[256];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int m = tk.m, s = tk.s, kx = tk.kx;
-  if (m <= 0 || kx <= 0) return;
+  const int m = tk.m, s = tk.s;
+  const int x0 = blockIdx.y * kApplyCols;
+  const int kx = tk.kx < x0 + kApplyCols ? tk.kx : x0 + kApplyCols;   // this workgroup: columns [x0, kx)
+  if (m <= 0 || kx <= x0) return;
   double* X = tk.X;
   const int64_t ldx = tk.ldx;
   const double* A = tk.A;
   const int64_t lda = tk.lda;
   if (tk.identity) {
-    for (int c = 0; c < kx; ++c)
+    for (int c = x0; c < kx; ++c)
       for (int r = tid; r < m; r += NT) X[(int64_t)c * ldx + r] = (r == c) ? 1.0 : 0.0;
   } else {
     const int rz = tk.xrows < 0 ? 0 : tk.xrows;
-    for (int c = 0; c < kx; ++c)
+    for (int c = x0; c < kx; ++c)
       for (int r = rz + tid; r < m; r += NT) X[(int64_t)c * ldx + r] = 0.0;
   }
   const int nref = m < s ? m : s;
   const int np = (nref + PB - 1) / PB;
   for (int p = np - 1; p >= 0; --p) {
     const int c0 = p * PB;
-    if (tk.identity && c0 >= kx) continue;
+    if (tk.identity && c0 >= kx) continue;   // columns left of the panel are still unit vectors
     const int mm = m - c0;
     const int nlive = nref - c0;
     __syncthreads();   // previous panel done with P, Ts and X
@@ -375,7 +380,7 @@ __global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict
         const int cx = lane & 15;
         vx[b][q] = (b < nblk) ? vval_lds(P, rb + 16 * b + 4 * q + (lane >> 4), cx, mm, cx < nlive) : 0.0;
       }
-    for (int col0 = tk.identity ? c0 : 0; col0 < kx; col0 += PB)
+    for (int col0 = (tk.identity && c0 > x0) ? c0 : x0; col0 < kx; col0 += PB)
       wy_update<false>(X, ldx, c0, mm, col0, kx, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
   }
 }
@@ -708,9 +713,10 @@ hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s) {
+hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)count), dim3(NT), 0, s, d_tasks);
+  const int chunks = max_kx > kApplyCols ? (max_kx + kApplyCols - 1) / kApplyCols : 1;
+  hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)count, (unsigned)chunks), dim3(NT), 0, s, d_tasks);
   return hipGetLastError();
 }
 
