@@ -1152,7 +1152,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
           if (grp == 0 && maxa <= kThinMaxK) {
             // W_ik = U_ik X_ik, inner dimension a rank: a streaming kernel
-            HIPCHK(launch_thin_gemm(h->arena, nb, h->Xb, maxa, h->Wb, ldw, wb, maxrows, maxa, h->s));
+            HIPCHK(launch_thin_gemm(h->arena, nb, h->Xb, maxa, h->Wb, ldw, wb, maxrows, maxa, maxb, h->s));
           } else {
             GemmSeg ws{};
             ws.A = op_contig(h->arena, nb, 0, 0);
@@ -1431,13 +1431,18 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       }
       im_push(h, m2_h, m_d, 3 * (int64_t)cnt);
       lm_push(h, a2_h, a_d, 3 * (int64_t)cnt);
-      GemmSeg cs{};
-      cs.A = op_contig(h->arena, nb, 0, 0);
-      cs.B = op_contig(h->Ptmp, nb, 0, 0);
-      cs.K = kmax;
+      // dC_ij -= U_ij P_t^T: inner dimension a rank, streamed over the column
       GemmBatch cb{};
       cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
-      gemm(h, mmax, nbj, 1, &cs, cold, h->n, epi_linear(-1.0, 1.0), &cb);
+      if (kmax <= kThinMaxK) {
+        HIPCHK(launch_thin_gemm(h->arena, nb, h->Ptmp, nb, cold, h->n, cb, mmax, kmax, nbj, h->s, -1.0, 1.0, true));
+      } else {
+        GemmSeg cs{};
+        cs.A = op_contig(h->arena, nb, 0, 0);
+        cs.B = op_contig(h->Ptmp, nb, 0, 0);
+        cs.K = kmax;
+        gemm(h, mmax, nbj, 1, &cs, cold, h->n, epi_linear(-1.0, 1.0), &cb);
+      }
     }
     prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
   };

@@ -469,17 +469,21 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
 }
 
 // ---------------------------------------------------------------------------
-// Batched products with a small inner dimension, C_p = A_p B_p (A_p: m_p x
-// k_p, B_p: k_p x n_p, column-major at element offsets a_off[p], b_off[p],
-// c_off[p]).  In the column update these are W_ik = U_ik X_ik: 800 rows, k and
-// n ranks of a few tens, thousands of pairs.  Memory-bound: A is streamed
+// Batched products with a small inner dimension, C_p = alpha A_p B_p + beta
+// C_p (A_p: m_p x k_p, B_p: k_p x n_p -- or its transpose stored, btrans --
+// column-major at element offsets a_off[p], b_off[p], c_off[p]).  In the
+// column update these are W_ik = U_ik X_ik: 800 rows, k and n ranks of a few
+// tens, thousands of pairs; in the tangent's correction dC_ij -= U_ij P_ij^T
+// (n = 800).  Memory-bound: A is streamed
 // (once per 16 columns of C, re-reads hit L2), B is staged in LDS 16
 // columns at a time and read as broadcasts, each thread owns one row of C.
-// Workgroup (p, y) covers rows [256 y, 256 y + 256) of pair p.
+// Workgroup (p, y, z) covers rows [256 y, 256 y + 256) and columns
+// [64 z, 64 z + 64) of pair p.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kThinRows = 256;
 constexpr int kThinCols = 16;
+constexpr int kThinGroup = 64;   // columns per workgroup
 }  // namespace
 
 __global__ void __launch_bounds__(kThinRows) thin_gemm_kernel(const double* __restrict__ A, int64_t lda,
@@ -490,7 +494,8 @@ __global__ void __launch_bounds__(kThinRows) thin_gemm_kernel(const double* __re
                                                               const int* __restrict__ k_of,
                                                               const int64_t* __restrict__ a_off,
                                                               const int64_t* __restrict__ b_off,
-                                                              const int64_t* __restrict__ c_off) {
+                                                              const int64_t* __restrict__ c_off, double alpha,
+                                                              double beta, int btrans) {
   extern __shared__ double xs[];   // [k][kThinCols]
   const int p = blockIdx.x;
   const int m = m_of[p], n = n_of[p], k = k_of[p];
@@ -500,12 +505,20 @@ __global__ void __launch_bounds__(kThinRows) thin_gemm_kernel(const double* __re
   const double* a = A + a_off[p];
   const double* b = B + b_off[p];
   double* c = C + c_off[p];
-  for (int n0 = 0; n0 < n; n0 += kThinCols) {
-    const int nc = (n - n0 < kThinCols) ? n - n0 : kThinCols;
+  const int n1 = (n < (int)(blockIdx.z + 1) * kThinGroup) ? n : (int)(blockIdx.z + 1) * kThinGroup;
+  for (int n0 = blockIdx.z * kThinGroup; n0 < n1; n0 += kThinCols) {
+    const int nc = (n1 - n0 < kThinCols) ? n1 - n0 : kThinCols;
     __syncthreads();   // the previous slice has been read
-    for (int e = threadIdx.x; e < k * kThinCols; e += kThinRows) {
-      const int q = e / k, t = e - q * k;   // consecutive threads: consecutive rows of B
-      xs[t * kThinCols + q] = (q < nc) ? b[t + (int64_t)(n0 + q) * ldb] : 0.0;
+    if (btrans) {   // B^T stored: element (t, q) at b[q + t ldb]
+      for (int e = threadIdx.x; e < k * kThinCols; e += kThinRows) {
+        const int t = e / kThinCols, q = e - t * kThinCols;
+        xs[e] = (q < nc) ? b[(n0 + q) + (int64_t)t * ldb] : 0.0;
+      }
+    } else {
+      for (int e = threadIdx.x; e < k * kThinCols; e += kThinRows) {
+        const int q = e / k, t = e - q * k;   // consecutive threads: consecutive rows of B
+        xs[t * kThinCols + q] = (q < nc) ? b[t + (int64_t)(n0 + q) * ldb] : 0.0;
+      }
     }
     __syncthreads();
     if (r < m) {
@@ -522,21 +535,27 @@ __global__ void __launch_bounds__(kThinRows) thin_gemm_kernel(const double* __re
       }
 #pragma unroll
       for (int q = 0; q < kThinCols; ++q)
-        if (q < nc) c[r + (int64_t)(n0 + q) * ldc] = acc[q];
+        if (q < nc) {
+          double* cq = c + r + (int64_t)(n0 + q) * ldc;
+          *cq = beta == 0.0 ? alpha * acc[q] : alpha * acc[q] + beta * *cq;
+        }
     }
   }
 }
 
 hipError_t launch_thin_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                            const GemmBatch& batch, int maxm, int maxk, hipStream_t s) {
+                            const GemmBatch& batch, int maxm, int maxk, int maxn, hipStream_t s, double alpha,
+                            double beta, bool btrans) {
   if (batch.count <= 0 || maxm <= 0) return hipSuccess;
   if (maxk < 0 || maxk > kThinMaxK || !batch.m_of || !batch.n_of || !batch.k_of || !batch.a_off ||
       !batch.b_off || !batch.c_off)
     return hipErrorInvalidValue;
   const size_t lds = (size_t)(maxk > 0 ? maxk : 1) * kThinCols * sizeof(double);
-  hipLaunchKernelGGL(thin_gemm_kernel, dim3((unsigned)batch.count, (unsigned)((maxm + kThinRows - 1) / kThinRows)),
+  const unsigned groups = (unsigned)((maxn + kThinGroup - 1) / kThinGroup);
+  hipLaunchKernelGGL(thin_gemm_kernel,
+                     dim3((unsigned)batch.count, (unsigned)((maxm + kThinRows - 1) / kThinRows), groups > 0 ? groups : 1),
                      dim3(kThinRows), lds, s, A, lda, B, ldb, C, ldc, batch.m_of, batch.n_of, batch.k_of,
-                     batch.a_off, batch.b_off, batch.c_off);
+                     batch.a_off, batch.b_off, batch.c_off, alpha, beta, btrans ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@
 //  * pair_quad_kernel: a^T dSigma/dbeta a = sum_{a,b} a_a a_b dC/dbeta(r_ab),
 //    entries regenerated on the fly (never stored), lower-triangle blocks of
 //    128 x 128 pairs, one partial per workgroup, reduced in a fixed order.
-//  * phi_trace_kernel: tangent of the diagonal Cholesky step,
+//  * diag_trace_kernel + phi_kernel: tangent of the diagonal Cholesky step,
 //    M = L^{-1} dC L^{-T},  Phi(M) = tril(M) with the diagonal halved,
 //    and tr(M) (the tile's share of d log|Sigma|).
 #include "kernels.h"
@@ -86,23 +86,33 @@ hipError_t launch_pair_quad(const MaternParams& p, const double* x, const double
 }
 
 // M (m x m, ld) <- Phi(M) = tril(M) with halved diagonal; *trace_out = tr(M).
-__global__ void __launch_bounds__(256) phi_trace_kernel(double* M, int64_t ld, int64_t m, double* trace_out) {
+// trace of the m x m block (one workgroup, fixed summation order), read
+// before phi_kernel halves the diagonal
+__global__ void __launch_bounds__(256) diag_trace_kernel(const double* __restrict__ M, int64_t ld, int64_t m,
+                                                         double* trace_out) {
   __shared__ double red[4];
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < m * m; e += 256) {
-    const int64_t i = e % m, k = e / m;
-    double* p = M + k * ld + i;
-    if (i < k) *p = 0.0;
-    else if (i == k) { s += *p; *p *= 0.5; }
-  }
+  for (int64_t i = threadIdx.x; i < m; i += 256) s += M[i * ld + i];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) *trace_out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Phi(M): zero above the diagonal, halve the diagonal; block (x, k) takes
+// rows 256 x.. of column k
+__global__ void __launch_bounds__(256) phi_kernel(double* __restrict__ M, int64_t ld, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (i > k || k >= m) return;
+  double* p = M + k * ld + i;
+  *p = (i == k) ? 0.5 * *p : 0.0;
+}
+
 hipError_t launch_phi_trace(double* M, int64_t ld, int64_t m, double* trace_out, hipStream_t s) {
-  hipLaunchKernelGGL(phi_trace_kernel, dim3(1), dim3(256), 0, s, M, ld, m, trace_out);
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(diag_trace_kernel, dim3(1), dim3(256), 0, s, M, ld, m, trace_out);
+  hipLaunchKernelGGL(phi_kernel, dim3((unsigned)((m + 255) / 256), (unsigned)m), dim3(256), 0, s, M, ld, m);
   return hipGetLastError();
 }
 

@@ -67,13 +67,16 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
                        const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
                        int tile_m = 0, int tile_n = 0, int tag = 0);
 
-// C_p = A_p B_p for a batch of products with a small inner dimension (k_p <=
-// kThinMaxK) and few columns: batch supplies m_of, n_of, k_of and the element
-// offsets a_off, b_off, c_off (device arrays, all required); A, B and C are
-// column-major with leading dimensions lda, ldb, ldc.  maxm, maxk: the
-// largest m_p and k_p.  Returns hipErrorInvalidValue for maxk > kThinMaxK.
+// C_p = alpha A_p B_p + beta C_p for a batch of products with a small inner
+// dimension (k_p <= kThinMaxK): batch supplies m_of, n_of, k_of and the
+// element offsets a_off, b_off, c_off (device arrays, all required); A, B and
+// C are column-major with leading dimensions lda, ldb, ldc; btrans: B_p^T is
+// stored instead (element (t, q) of B_p at b[q + t ldb]).  maxm, maxk, maxn:
+// the largest m_p, k_p and n_p.  Returns hipErrorInvalidValue for maxk >
+// kThinMaxK.
 constexpr int kThinMaxK = 512;   // B slice in LDS: kThinMaxK x 16 doubles (64 KB)
 hipError_t launch_thin_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                            const GemmBatch& batch, int maxm, int maxk, hipStream_t s);
+                            const GemmBatch& batch, int maxm, int maxk, int maxn, hipStream_t s,
+                            double alpha = 1.0, double beta = 0.0, bool btrans = false);
 
 }  // namespace tlrk
