@@ -122,6 +122,7 @@ struct tlr_handle_s {
   double* Bt = nullptr;    // nt x (nb x smax)
   double* Vtmp = nullptr;  // gcap x vslot: V~ of the tiles being compressed
   double* Ptmp = nullptr;  // nt x nb x nb (gradient: dL_jj V_ij products)
+  int64_t ptmp_cap = 0;
   double* Zb = nullptr;    // nt x (smax x maxrank)
   double* Wb = nullptr;
   int64_t w_cap = 0;
@@ -1215,18 +1216,18 @@ void tangent_diag(tlr_handle_s* h, int j, const double* dc, int64_t ldc, const d
   a.A = op_contig(dinv_tile(h, j), nb, 0, 0);
   a.B = op_contigT(dc, ldc, 0, 0);
   a.K = nbj;
-  gemm(h, nbj, nbj, 1, &a, T1, nb, epi_linear(1.0, 0.0));
+  gemm(h, nbj, nbj, 1, &a, T1, nb, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
   GemmSeg b{};
   b.A = op_contig(T1, nb, 0, 0);
   b.B = op_contig(dinv_tile(h, j), nb, 0, 0);
   b.K = nbj;
-  gemm(h, nbj, nbj, 1, &b, Mj, nb, epi_linear(1.0, 0.0));
+  gemm(h, nbj, nbj, 1, &b, Mj, nb, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
   HIPCHK(launch_phi_trace(Mj, nb, nbj, h->scal + h->nt + j, h->s));
   GemmSeg c{};
   c.A = op_contig(L, ldl, 0, 0);
   c.B = op_contigT(Mj, nb, 0, 0);
   c.K = nbj;
-  gemm(h, nbj, nbj, 1, &c, out, ldo, epi_linear(1.0, 0.0));
+  gemm(h, nbj, nbj, 1, &c, out, ldo, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
 }
 
 void factor_dense(tlr_handle_s* h, bool tangent) {
@@ -1379,7 +1380,69 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     }
     const size_t e_c = prof_mark(h);
     double cf = 0.0;
-    if (cnt > 0) {
+    int64_t rsum = 0;
+    for (int t = 0; t < T; ++t) rsum += std::max(P.rk[tid_of(h, j + 1 + t, j)], 0);
+    if (cnt > 0 && kmax <= kThinMaxK && 2 * (int64_t)nb * rsum <= h->ptmp_cap) {
+      // P_t = dL_jj V_t for all tiles at once: the V_t side by side (Vcat,
+      // nbj x rsum) and one GEMM, then dC_t -= U_t P_t^T streamed per tile
+      double* vcat = h->Ptmp;
+      double* pcat = h->Ptmp + (int64_t)nb * rsum;
+      meta_reserve(h, 5 * (int64_t)cnt, 5 * (int64_t)cnt);
+      int *m_d, *k_d, *n_d;
+      int* m_h = im_take(h, cnt, &m_d);
+      int* k_h = im_take(h, cnt, &k_d);
+      int64_t *so_d, *do_d;
+      int64_t* so_h = lm_take(h, cnt, &so_d);
+      int64_t* do_h = lm_take(h, cnt, &do_d);
+      int q = 0;
+      int64_t off = 0, maxe = 0;
+      std::vector<int64_t> offs((size_t)T, -1);
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (P.rk[id] <= 0) continue;
+        m_h[q] = nbj; k_h[q] = P.rk[id];
+        so_h[q] = P.voff[id];
+        do_h[q] = off * nb;
+        offs[(size_t)t] = off;
+        maxe = std::max<int64_t>(maxe, (int64_t)nbj * P.rk[id]);
+        off += P.rk[id];
+        ++q;
+      }
+      im_push(h, m_h, m_d, 2 * (int64_t)cnt);
+      lm_push(h, so_h, so_d, 2 * (int64_t)cnt);
+      HIPCHK(launch_batched_copy(h->arena, nb, so_d, vcat, nb, do_d, m_d, k_d, maxe, cnt, h->s));
+      GemmSeg ps{};
+      ps.A = op_contig(ddj, nb, 0, 0);
+      ps.B = op_contigT(vcat, nb, 0, 0);
+      ps.K = nbj;
+      gemm(h, nbj, rsum, 1, &ps, pcat, nb, epi_linear(1.0, 0.0));
+      cf += 2.0 * nbj * nbj * (double)rsum;
+      int* m2_h = im_take(h, cnt, &m_d);
+      int* n2_h = im_take(h, cnt, &n_d);
+      int* k2_h = im_take(h, cnt, &k_d);
+      int64_t *a_d, *b_d, *c_d;
+      int64_t* a2_h = lm_take(h, cnt, &a_d);
+      int64_t* b2_h = lm_take(h, cnt, &b_d);
+      int64_t* c2_h = lm_take(h, cnt, &c_d);
+      int mmax = 1;
+      q = 0;
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (P.rk[id] <= 0) continue;
+        m2_h[q] = tile_rows(h, j + 1 + t); n2_h[q] = nbj; k2_h[q] = P.rk[id];
+        a2_h[q] = P.uoff[id];
+        b2_h[q] = offs[(size_t)t] * nb;
+        c2_h[q] = (int64_t)nbj + (int64_t)t * nb;
+        mmax = std::max(mmax, m2_h[q]);
+        cf += 2.0 * m2_h[q] * nbj * P.rk[id];
+        ++q;
+      }
+      im_push(h, m2_h, m_d, 3 * (int64_t)cnt);
+      lm_push(h, a2_h, a_d, 3 * (int64_t)cnt);
+      GemmBatch cb{};
+      cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
+      HIPCHK(launch_thin_gemm(h->arena, nb, pcat, nb, cold, h->n, cb, mmax, kmax, nbj, h->s, -1.0, 1.0, true));
+    } else if (cnt > 0) {
       meta_reserve(h, 6 * (int64_t)cnt, 6 * (int64_t)cnt);
       int *m_d, *n_d, *k_d;
       int* m_h = im_take(h, cnt, &m_d);
@@ -1824,7 +1887,10 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->Dinv = h->arena + h->dinv_off;
       HIPCHK(launch_fill(h->arena + h->ident_off, nb, nb, nb, 0.0, h->s));
       HIPCHK(launch_identity(h->arena + h->ident_off, nb, nb, h->s));
-      if (h->grad) h->Ptmp = dalloc<double>(h, nt * nb * nb);
+      if (h->grad) {
+        h->ptmp_cap = nt * nb * nb;
+        h->Ptmp = dalloc<double>(h, h->ptmp_cap);
+      }
       h->omega = dalloc<double>(h, nb * h->smax);
       h->gcap = (int)(h->grad ? 2 * nt : nt);   // tiles compressed together: two columns with the tangent
       const int64_t gc = h->gcap;
