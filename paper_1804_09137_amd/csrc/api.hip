@@ -22,6 +22,7 @@
 #include "grad.h"
 
 #include <algorithm>
+#include <chrono>
 #include <functional>
 #include <string>
 #include <thread>
@@ -61,6 +62,7 @@ struct tlr_handle_s {
   int gcap = 0;         // tile slots of the compression scratch
   int upd_tag = 1;      // column-update kernels of the running factorisation: 1 FP64, 2 FP32 products
   bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
+  double host_ms[4] = {0, 0, 0, 0};   // TLR_DEBUG: host time in the compressions' two waits and their callbacks
   bool multi = false;   // side and diagonal streams (TLR gradient handles without TLR_FLAG_SINGLE_STREAM)
   bool dense = false, grad = false, strict = false;
   int64_t slot = 0;      // doubles per low-rank slot (nb * maxrank)
@@ -156,10 +158,13 @@ struct tlr_handle_s {
   QrcpTask* tk_d = nullptr;
   QrcpTask* tk_h = nullptr;
   int tk_cap = 0;
-  HqrTask* hq_d = nullptr;  // 4 x gcap: one region per launch between synchronisations
+  HqrTask* hq_d = nullptr;  // 6 x gcap: one region per launch between synchronisations
   HqrTask* hq_h = nullptr;
   double* Tw = nullptr;     // nt x tw_stride compact-WY factors
   int64_t tw_stride = 0;
+  double* Tr = nullptr;     // gcap x tr_stride compact-WY factors of the truncation QR's reflectors
+  int64_t tr_stride = 0;
+  double* Tau = nullptr;    // gcap x kRegQrBig reflector scalars of the truncation QR
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags
   int* qr_h = nullptr;
 
@@ -539,8 +544,11 @@ struct ColumnJob {
   int g0;
 };
 
-// during: host work to do while the first launches run (called once, before
-// the first wait for this stream; the caller calls it if no tile needed it).
+// during[0], during[1]: host work to do while the compression's launches run,
+// each called once: the first before the wait for the range ranks, the second
+// before the wait for the truncation ranks (the caller calls what is left when
+// no tile needed that wait).  Each host wait then costs the main stream no
+// launch time: the launches that follow it are issued as soon as it ends.
 void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::function<void()>* during = nullptr) {
   int G = 0;
   for (ColumnJob& jb : jobs) {
@@ -566,6 +574,8 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   HqrTask* hq_ay = h->hq_h + gc;       // Q1 = Q_y [I; 0]
   HqrTask* hq_fb = h->hq_h + 2 * gc;   // factor B^T
   HqrTask* hq_ab = h->hq_h + 3 * gc;   // V~ = Q_b [Q_r; 0]
+  HqrTask* hq_wr = h->hq_h + 4 * gc;   // compact-WY factors of the truncation QR's reflectors
+  HqrTask* hq_qr = h->hq_h + 5 * gc;   // Q_r = H_0 ... H_{k-1} [I_k; 0]
   // global slot -> job, local tile, source row offset (from the workspace base)
   std::vector<int> jof(G), tloc(G), rows(G);
   std::vector<int64_t> srow(G);
@@ -653,11 +663,18 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
-    if (during && *during) {   // the host would otherwise wait here
-      (*during)();
-      *during = nullptr;
+    auto h0 = std::chrono::steady_clock::now();
+    if (during && during[0]) {   // the host would otherwise wait here
+      during[0]();
+      during[0] = nullptr;
     }
+    auto h1 = std::chrono::steady_clock::now();
     HIPCHK(hipStreamSynchronize(h->s));   // this stream only: the other may run the next step's updates
+    if (h->debug) {
+      const auto h2 = std::chrono::steady_clock::now();
+      h->host_ms[0] += std::chrono::duration<double, std::milli>(h1 - h0).count();
+      h->host_ms[1] += std::chrono::duration<double, std::milli>(h2 - h1).count();
+    }
     meta_reset(h);
     throw_if_not_spd(h);
     std::vector<int> next;
@@ -772,8 +789,11 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.tol = tol_trunc;
       tk.max_rank = maxrank + 1;
       tk.min_tail = 0;
-      tk.Q = h->Vtmp + (int64_t)g * h->vslot;
+      // on chip only the reflectors: Q_r is formed afterwards by hqr_apply,
+      // spread over several workgroups per tile
+      tk.Q = small ? nullptr : h->Vtmp + (int64_t)g * h->vslot;
       tk.ldq = nb;
+      tk.tau = small ? h->Tau + (int64_t)g * kRegQrBig : nullptr;
       tk.Z = h->Zb + (int64_t)g * h->smax * (maxrank + 1);
       tk.ldz = h->smax;
       tk.rank = h->qr_d + g;
@@ -814,7 +834,18 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
     HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    auto h0 = std::chrono::steady_clock::now();
+    if (during && during[1]) {
+      during[1]();
+      during[1] = nullptr;
+    }
+    auto h1 = std::chrono::steady_clock::now();
     HIPCHK(hipStreamSynchronize(h->s));
+    if (h->debug) {
+      const auto h2 = std::chrono::steady_clock::now();
+      h->host_ms[2] += std::chrono::duration<double, std::milli>(h1 - h0).count();
+      h->host_ms[3] += std::chrono::duration<double, std::milli>(h2 - h1).count();
+    }
     meta_reset(h);
     for (int q = 0; q < L; ++q) {
       const int g = lr[q];
@@ -866,6 +897,35 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   // 6. V~ = Q_b [Q_r; 0] and U_g = Q1_g Z_g (m_g x k_g) for the low-rank tiles
   meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
   if (nlr > 0) {
+    // Q_r of the tiles pivoted on chip, from their reflectors (in the Y
+    // workspace) and scalars
+    int nq = 0, max_k = 0;
+    for (int g = 0; g < G; ++g) {
+      if (dense[g] || k2[g] == 0 || t1[g] > kRegQrBig) continue;
+      HqrTask& tw = hq_wr[nq];
+      tw = HqrTask{};
+      tw.A = h->Ybuf + (int64_t)g * nb * h->smax;
+      tw.lda = nb;
+      tw.m = t1[g];
+      tw.s = k2[g];
+      tw.T = h->Tr + (int64_t)g * h->tr_stride;
+      tw.tau = h->Tau + (int64_t)g * kRegQrBig;
+      HqrTask& tq = hq_qr[nq];
+      tq = tw;
+      tq.tau = nullptr;
+      tq.X = h->Vtmp + (int64_t)g * h->vslot;
+      tq.ldx = nb;
+      tq.kx = k2[g];
+      tq.identity = 1;
+      max_k = std::max(max_k, k2[g]);
+      cflops += 4.0 * t1[g] * k2[g] * (double)k2[g];
+      ++nq;
+    }
+    if (nq > 0) {
+      HIPCHK(hipMemcpyAsync(h->hq_d + 4 * gc, hq_wr, 2 * (size_t)gc * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+      HIPCHK(launch_wy_build(h->hq_d + 4 * gc, nq, h->s, max_k));
+      HIPCHK(launch_hqr_apply(h->hq_d + 5 * gc, nq, h->s, max_k));
+    }
     int q = 0, max_kx = 0;
     for (int g = 0; g < G; ++g) {
       if (dense[g] || k2[g] == 0) continue;
@@ -1517,9 +1577,12 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   // compress, then V <- L_jj^{-1} V; with the look-ahead the diagonal step
   // of the newest primal column runs beside the compression (only the
   // triangular solves need it), so the main stream waits for it in between
-  auto finish = [&](std::vector<ColumnJob>& jobs, bool wait_diag, std::function<void()> during = nullptr) {
-    compress_columns(h, jobs, &during);
-    if (during) during();
+  auto finish = [&](std::vector<ColumnJob>& jobs, bool wait_diag, std::function<void()> during0 = nullptr,
+                    std::function<void()> during1 = nullptr) {
+    std::function<void()> during[2] = {std::move(during0), std::move(during1)};
+    compress_columns(h, jobs, during);
+    for (auto& f : during)
+      if (f) f();
     if (wait_diag) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_diag, 0));
     for (const ColumnJob& jb : jobs)
       if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
@@ -1595,24 +1658,33 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       std::vector<ColumnJob> jobs;
       if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
       jobs.push_back(tangent_job(j));
-      // The compressions of step j are issued first; the diagonal step of
-      // primal column j + 1 (its own stream) and the pre parts of step j + 1
-      // (side stream) are issued while they run, in the host's first wait.
-      finish(jobs, j + 1 < nt, [&]() {
-        if (j + 1 >= nt) return;
-        {
-          DiagStream ds(h);
-          HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
-          primal_diag(j + 1);
-          HIPCHK(hipEventRecord(h->ev_diag, h->s));
-        }
-        pre(j + 1);
-      });
+      // The compressions of step j are issued first.  The host issues the pre
+      // parts of step j + 1 (side stream) in its first wait, for the range
+      // ranks, and the diagonal step of primal column j + 1 (its own stream;
+      // only the triangular solves after the compression need it) in its
+      // second wait, for the truncation ranks.
+      finish(
+          jobs, j + 1 < nt,
+          [&]() {
+            if (j + 1 < nt) pre(j + 1);
+          },
+          [&]() {
+            if (j + 1 >= nt) return;
+            DiagStream ds(h);
+            HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
+            primal_diag(j + 1);
+            HIPCHK(hipEventRecord(h->ev_diag, h->s));
+          });
       HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
     }
   }
   family_upload(h, P);
   sync(h);
+  if (h->debug) {
+    std::fprintf(stderr, "[tlr] host ms: issue in wait 1 %.1f, wait 1 %.1f, issue in wait 2 %.1f, wait 2 %.1f\n",
+                 h->host_ms[0], h->host_ms[1], h->host_ms[2], h->host_ms[3]);
+    for (double& v : h->host_ms) v = 0.0;
+  }
   P.done_kind = 1;
   if (tangent) G.done_kind = 1;
 }
@@ -1949,10 +2021,13 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->tk_cap = (int)gc;
       h->tk_d = dalloc<QrcpTask>(h, gc);
       h->tk_h = halloc<QrcpTask>(h, gc);
-      h->hq_d = dalloc<HqrTask>(h, 4 * gc);
-      h->hq_h = halloc<HqrTask>(h, 4 * gc);
+      h->hq_d = dalloc<HqrTask>(h, 6 * gc);
+      h->hq_h = halloc<HqrTask>(h, 6 * gc);
       h->tw_stride = (int64_t)((h->smax + 15) / 16) * 256;
       h->Tw = dalloc<double>(h, gc * h->tw_stride);
+      h->tr_stride = (int64_t)((kRegQrBig + 15) / 16) * 256;
+      h->Tr = dalloc<double>(h, gc * h->tr_stride);
+      h->Tau = dalloc<double>(h, gc * (int64_t)kRegQrBig);
       h->qr_d = dalloc<int>(h, 2 * gc);
       h->qr_h = halloc<int>(h, 2 * gc);
       HIPCHK(launch_gaussian(h->omega, nb * h->smax, (uint32_t)o->seed, h->s));

@@ -26,6 +26,8 @@ struct QrcpTask {
   int upper;       // qrcp_reg: read only the upper triangle of Y (zeros below)
   double* W;       // qrcp_reg: m x rank workspace for the reflectors (ldw)
   int64_t ldw;
+  double* tau;     // qrcp_reg, optional: the rank reflector scalars (with W, the
+                   // input of wy_build and hqr_apply when Q is not formed here)
 };
 
 // On-chip pivoted QR (qrcp_reg_kernel): all in registers up to kRegQrMax
@@ -50,6 +52,7 @@ struct HqrTask {
   int kx;
   int xrows;        // apply (identity == 0): rows >= xrows of X are cleared first
   int identity;     // apply: X starts as [I_kx; 0]
+  const double* tau;   // wy_build: the s reflector scalars
 };
 
 hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s, int max_m = kQrMaxRows);
@@ -60,6 +63,10 @@ hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
 // untouched).
 constexpr int kApplyCols = 32;
 hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx);
+// The compact-WY factors T (per 16 reflectors, the layout hqr_factor writes)
+// of s Householder vectors stored as hqr_factor stores them (A, lda, m rows,
+// unit diagonal implied) with scalars tau; max_s >= every task's min(m, s).
+hipError_t launch_wy_build(const HqrTask* d_tasks, int count, hipStream_t s, int max_s);
 hipError_t launch_copy_upper(const double* src, int64_t sld, const int64_t* soff, double* dst, int64_t dld,
                              const int64_t* doff, const int* nn, int nmax, int count, hipStream_t s);
 hipError_t launch_gaussian(double* out, int64_t count, uint32_t seed, hipStream_t s);

@@ -617,6 +617,8 @@ __device__ __forceinline__ void qrcp_reg_body(const QrcpTask& tk, const QrShared
       if (st < rank) tk.W[(int64_t)st * tk.ldw + r] = (r > st) ? v : 0.0;
     }
   }
+  if (tk.tau)
+    for (int i = tid; i < rank; i += NT) tk.tau[i] = taus[i];
   if (!tk.Q || rank == 0) return;
   __syncthreads();
   // explicit Q = H_0 ... H_{rank-1} [I; 0]: column c still equals e_c before
@@ -705,6 +707,64 @@ __global__ void copy_upper_kernel(const double* __restrict__ src, int64_t sld, c
   if (e >= (int64_t)n * n) return;
   const int64_t r = e % n, c = e / n;
   dst[doff[b] + c * dld + r] = (r <= c) ? src[soff[b] + c * sld + r] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Compact-WY factor of reflectors 16p .. 16p + 15 (workgroup (task, p)): the
+// Gram matrix G = V^T V of the unit lower trapezoidal V, staged through LDS
+// 256 rows at a time, then T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i]
+// G[0:i, i] (Schreiber-Van Loan), as hqr_factor builds it.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) wy_build_kernel(const HqrTask* __restrict__ tasks) {
+  const HqrTask tk = tasks[blockIdx.x];
+  const int p = blockIdx.y;
+  const int nref = tk.m < tk.s ? tk.m : tk.s;
+  const int c0 = PB * p;
+  if (c0 >= nref) return;   // uniform over the workgroup
+  const int nlive = nref - c0 < PB ? nref - c0 : PB;
+  const int mm = tk.m - c0;
+  __shared__ double V[PB][257];
+  __shared__ double G[PB * PB];
+  const int tid = threadIdx.x;
+  const int a = tid >> 4, b = tid & 15;
+  double g = 0.0;
+  for (int r0 = 0; r0 < mm; r0 += 256) {
+    const int r = r0 + tid;
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      double v = 0.0;
+      if (c < nlive && r < mm) v = (r == c) ? 1.0 : (r > c ? tk.A[(int64_t)(c0 + c) * tk.lda + c0 + r] : 0.0);
+      V[c][tid] = v;
+    }
+    __syncthreads();
+    const int rn = mm - r0 < 256 ? mm - r0 : 256;
+    for (int q = 0; q < rn; ++q) g += V[a][q] * V[b][q];
+    __syncthreads();
+  }
+  G[a * PB + b] = g;
+  __syncthreads();
+  if (tid < PB) {
+    const int lane = tid;
+    double tr[PB] = {};
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < PB; ++l)
+        if (l < i && l >= lane) acc += tr[l] * G[l * PB + i];
+      const double ti = (i < nlive) ? tk.tau[c0 + i] : 0.0;
+      tr[i] = (lane < i) ? -ti * acc : (lane == i ? ti : 0.0);
+    }
+#pragma unroll
+    for (int l = 0; l < PB; ++l) tk.T[(int64_t)p * 256 + lane * PB + l] = tr[l];
+  }
+}
+
+hipError_t launch_wy_build(const HqrTask* d_tasks, int count, hipStream_t s, int max_s) {
+  if (count <= 0 || max_s <= 0) return hipSuccess;
+  hipLaunchKernelGGL(wy_build_kernel, dim3((unsigned)count, (unsigned)((max_s + PB - 1) / PB)), dim3(256), 0, s,
+                     d_tasks);
+  return hipGetLastError();
 }
 
 hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s) {
