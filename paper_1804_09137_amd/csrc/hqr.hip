@@ -153,9 +153,8 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
   __shared__ double red[NW * RS];
   __shared__ double Wf[256], Wp[256], Ts[256];
   __shared__ double taus[PB];
-  __shared__ double nred[NW];
-  __shared__ double dred[NW * PB];
-  __shared__ double sh_alpha;
+  __shared__ double dred[2 * NW * PB];   // per-wave column sums, two buffers (by column parity)
+  __shared__ double rowc[2 * PB];        // row c of the panel, two buffers
   __shared__ int sh_t1;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -185,20 +184,35 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
       a0[c] = (c < pw && r0 < mm) ? ac[r0] : 0.0;
       a1[c] = (c < pw && r1 < mm) ? ac[r1] : 0.0;
     }
-    // 2. factor the panel
+    // 2. factor the panel.  Column c's reflector and its products with the
+    // columns k > c come from one reduction: with x = A[c:, c], alpha = x_c,
+    // sigma = |x_{>c}|^2 and p_k = x_{>c}^T A[>c, k], the reflector
+    // v = (x - beta e_c) / (alpha - beta) has v^T A[c:, k] = A[c, k] +
+    // p_k / (alpha - beta).  So each column costs one barrier.
 #pragma unroll
     for (int c = 0; c < PB; ++c) {
       if (c0 + c < nref) {
         const double x0 = a0[c], x1 = a1[c];
-        double sq = (r0 > c ? x0 * x0 : 0.0) + x1 * x1;
-        sq = wave::sum(sq);
-        if (lane == 0) nred[w] = sq;
-        if (tid == c) sh_alpha = x0;
-        __syncthreads();
-        double sig = 0.0;
+        const double y0 = (r0 > c) ? x0 : 0.0;   // rows below c
+        double part[16];
 #pragma unroll
-        for (int v = 0; v < NW; ++v) sig += nred[v];
-        const double alpha = sh_alpha;
+        for (int k = 0; k < 16; ++k)
+          part[k] = (k == c) ? y0 * x0 + x1 * x1 : (k > c ? y0 * a0[k] + x1 * a1[k] : 0.0);
+        const double tot = wave::bfly<16>(part, lane);
+        double* dr = dred + (c & 1) * NW * PB;
+        double* rc = rowc + (c & 1) * PB;
+        if ((lane & 3) == 0) dr[w * PB + ((lane >> 2) & 15)] = tot;
+        if (tid == c) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) rc[k] = a0[k];
+        }
+        __syncthreads();
+        const int kl = lane & 15;
+        double sk = 0.0;   // lane kl: sigma (kl == c) or p_kl
+#pragma unroll
+        for (int v = 0; v < NW; ++v) sk += dr[v * PB + kl];
+        const double sig = wave::read(sk, c);
+        const double alpha = rc[c];
         double ta, beta, sc;
         if (sig == 0.0) {
           ta = 0.0; beta = alpha; sc = 0.0;
@@ -208,30 +222,19 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
           ta = (beta - alpha) / beta;
           sc = 1.0 / (alpha - beta);
         }
+        const double dl = ta * (rc[kl] + sc * sk);   // lane k: tau v^T A[c:, k]
         const double v0 = (r0 > c) ? x0 * sc : (r0 == c ? 1.0 : 0.0);
         const double v1 = x1 * sc;
         a0[c] = (r0 == c) ? beta : (r0 > c ? v0 : x0);
         a1[c] = v1;
         if (tid == 0) taus[c] = ta;
-        if (c + 1 < PB) {
-          double part[16];
 #pragma unroll
-          for (int k = 0; k < 16; ++k) part[k] = (k > c) ? v0 * a0[k] + v1 * a1[k] : 0.0;
-          const double tot = wave::bfly<16>(part, lane);
-          if ((lane & 3) == 0) dred[w * PB + ((lane >> 2) & 15)] = tot;
-          __syncthreads();
-          double d = 0.0;
-#pragma unroll
-          for (int v = 0; v < NW; ++v) d += dred[v * PB + (lane & 15)];
-          d *= ta;
-#pragma unroll
-          for (int k = 0; k < 16; ++k)
-            if (k > c) {
-              const double dk = wave::read(d, k);
-              a0[k] -= dk * v0;
-              a1[k] -= dk * v1;
-            }
-        }
+        for (int k = 0; k < 16; ++k)
+          if (k > c) {
+            const double dk = wave::read(dl, k);
+            a0[k] -= dk * v0;
+            a1[k] -= dk * v1;
+          }
       } else if (tid == 0) {
         taus[c] = 0.0;
       }
