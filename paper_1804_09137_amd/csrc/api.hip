@@ -428,33 +428,40 @@ int choose_splitk(const tlr_handle_s* h, int64_t M, int64_t N, int64_t K) {
 
 // mh / nh: host copies of a hinted batch's per-item M and N.  With them the
 // launch gets a flat list of the real tiles (one workgroup each) instead of
-// the launch maximum's tile grid per item.
+// the launch maximum's tile grid per item.  flat_tiles uploads that list into
+// b (unless b has one already) and returns the number of tiles; callers may
+// build it ahead of the launch, gemm builds it otherwise.
+int64_t flat_tiles(tlr_handle_s* h, GemmBatch& b, int tm, int tn, const int* mh, const int* nh) {
+  int64_t tot = 0;
+  for (int q = 0; q < b.count; ++q) tot += ((int64_t)mh[q] + tm - 1) / tm * (((int64_t)nh[q] + tn - 1) / tn);
+  if (tot == 0 || b.tile_item) return tot;
+  if (h->im_use + b.count + tot <= h->im_cap - h->im_cap / 4) {   // headroom for the caller's later takes
+    int* first_d;
+    int* first = im_take(h, b.count + tot, &first_d);
+    int* item = first + b.count;
+    int64_t acc = 0;
+    for (int q = 0; q < b.count; ++q) {
+      first[q] = (int)acc;
+      const int64_t t = ((int64_t)mh[q] + tm - 1) / tm * (((int64_t)nh[q] + tn - 1) / tn);
+      for (int64_t e = 0; e < t; ++e) item[acc + e] = q;
+      acc += t;
+    }
+    im_push(h, first, first_d, b.count + tot);
+    b.tile_first = first_d;
+    b.tile_item = first_d + b.count;
+    b.ntiles = tot;
+  }
+  return tot;
+}
+
 void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
           const GemmEpi& ep, const GemmBatch* b = nullptr, bool allow_split = false, int tm = 0, int tn = 0,
           const int* mh = nullptr, const int* nh = nullptr, int tag = 0) {
   GemmBatch fb;
   if (b && mh && nh && tm && tn) {
-    int64_t tot = 0;
-    for (int q = 0; q < b->count; ++q) tot += ((int64_t)mh[q] + tm - 1) / tm * (((int64_t)nh[q] + tn - 1) / tn);
-    if (tot == 0) return;
-    if (h->im_use + b->count + tot <= h->im_cap - h->im_cap / 4) {   // headroom for the caller's later takes
-      int* first_d;
-      int* first = im_take(h, b->count + tot, &first_d);
-      int* item = first + b->count;
-      int64_t acc = 0;
-      for (int q = 0; q < b->count; ++q) {
-        first[q] = (int)acc;
-        const int64_t t = ((int64_t)mh[q] + tm - 1) / tm * (((int64_t)nh[q] + tn - 1) / tn);
-        for (int64_t e = 0; e < t; ++e) item[acc + e] = q;
-        acc += t;
-      }
-      im_push(h, first, first_d, b->count + tot);
-      fb = *b;
-      fb.tile_first = first_d;
-      fb.tile_item = first_d + b->count;
-      fb.ntiles = tot;
-      b = &fb;
-    }
+    fb = *b;
+    if (flat_tiles(h, fb, tm, tn, mh, nh) == 0) return;
+    b = &fb;
   }
   int sk = 1;
   if (allow_split && !b) {
@@ -617,6 +624,23 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     int swide = 0;
     for (int g : todo) swide = std::max(swide, sz[g]);
     const int cnt = (int)todo.size();
+    // the factor's task list is uploaded before the sketch (no upload
+    // between the two launches)
+    for (int q = 0; q < cnt; ++q) {
+      const int g = todo[q];
+      HqrTask& tk = hq_fy[q];
+      tk = HqrTask{};
+      tk.A = h->Ybuf + (int64_t)g * nb * h->smax;
+      tk.lda = nb;
+      tk.m = rows[g];
+      tk.s = sz[g];
+      tk.T = h->Tw + (int64_t)g * h->tw_stride;
+      tk.tol = tol_range;
+      tk.min_tail = 8;
+      tk.rank = h->qr_d + g;
+      tk.flag = h->qr_d + gc + g;
+    }
+    HIPCHK(hipMemcpyAsync(h->hq_d, hq_fy, cnt * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
     meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
     {
       int *m_d, *n_d;
@@ -645,21 +669,6 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       gemm(h, maxm, swide, 1, &sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, swide <= 64 ? 64 : 128, m_h,
            n_h);
     }
-    for (int q = 0; q < cnt; ++q) {
-      const int g = todo[q];
-      HqrTask& tk = hq_fy[q];
-      tk = HqrTask{};
-      tk.A = h->Ybuf + (int64_t)g * nb * h->smax;
-      tk.lda = nb;
-      tk.m = rows[g];
-      tk.s = sz[g];
-      tk.T = h->Tw + (int64_t)g * h->tw_stride;
-      tk.tol = tol_range;
-      tk.min_tail = 8;
-      tk.rank = h->qr_d + g;
-      tk.flag = h->qr_d + gc + g;
-    }
-    HIPCHK(hipMemcpyAsync(h->hq_d, hq_fy, cnt * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
     HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
@@ -704,6 +713,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   const int L = (int)lr.size();
   std::vector<int> k2(G, 0);
   if (L > 0) {
+    // Every task list and metadata array of the launches up to the truncation
+    // is uploaded first: an upload is a small copy kernel, and one issued
+    // between two compression launches waits for a free CU, which the other
+    // stream's update GEMM may hold for hundreds of microseconds.
     // Q1 = Q_y [I_t1; 0]
     int max_kx = 0;
     for (int q = 0; q < L; ++q) {
@@ -722,10 +735,63 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       max_kx = std::max(max_kx, tk.kx);
       cflops += 2.0 * tk.m * t1[g] * t1[g];
     }
-    HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx));
-    meta_reserve(h, 3 * (int64_t)L, 3 * (int64_t)L);
-    // 3. project: Bt_g = C_g^T Q1_g (ncols x t1)
+    // B^T = Q_b R_b
+    for (int q = 0; q < L; ++q) {
+      const int g = lr[q];
+      HqrTask& tk = hq_fb[q];
+      tk = HqrTask{};
+      tk.A = h->Bt + (int64_t)g * nb * h->smax;
+      tk.lda = nb;
+      tk.m = ncols;
+      tk.s = t1[g];
+      tk.T = h->Tw + (int64_t)g * h->tw_stride;
+      cflops += 2.0 * ncols * t1[g] * t1[g];
+    }
+    // truncation by pivoted QR of R_b (t1 x t1): Z = Pi R_r[:k, :]^T.  Small
+    // factors stay on chip (reflectors into the Y workspace, which Q1 no
+    // longer needs; Q_r is formed afterwards); larger ones are copied out and
+    // pivoted in place, Q_r into Vtmp.
+    std::vector<int> big;
+    int nsmall = 0;
+    for (int q = 0; q < L; ++q)
+      if (t1[lr[q]] <= kRegQrBig) ++nsmall;
+    int qs = 0, qb = nsmall;
+    for (int q = 0; q < L; ++q) {
+      const int g = lr[q];
+      const bool small = t1[g] <= kRegQrBig;
+      QrcpTask& tk = h->tk_h[small ? qs++ : qb++];
+      tk = QrcpTask{};
+      tk.m = t1[g];
+      tk.q = t1[g];
+      tk.tol = tol_trunc;
+      tk.max_rank = maxrank + 1;
+      tk.min_tail = 0;
+      tk.Q = small ? nullptr : h->Vtmp + (int64_t)g * h->vslot;
+      tk.ldq = nb;
+      tk.tau = small ? h->Tau + (int64_t)g * kRegQrBig : nullptr;
+      tk.Z = h->Zb + (int64_t)g * h->smax * (maxrank + 1);
+      tk.ldz = h->smax;
+      tk.rank = h->qr_d + g;
+      tk.flag = h->qr_d + gc + g;
+      if (small) {
+        tk.Y = h->Bt + (int64_t)g * nb * h->smax;
+        tk.ldy = nb;
+        tk.upper = 1;
+        tk.W = h->Ybuf + (int64_t)g * nb * h->smax;
+        tk.ldw = nb;
+      } else {
+        tk.Y = h->Ybuf + (int64_t)g * nb * h->smax;
+        tk.ldy = nb;
+        big.push_back(g);
+      }
+      cflops += 4.0 * t1[g] * t1[g] * t1[g] / 3.0;
+    }
+    // regions 1 and 2 (Q1, B^T) in one upload, then the truncation tasks
+    HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, (gc + L) * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+    const int nbg = (int)big.size();
+    meta_reserve(h, 3 * (int64_t)L + nbg, 3 * (int64_t)L + 2 * (int64_t)nbg);
+    // projection Bt_g = C_g^T Q1_g (ncols x t1)
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, L, &m_d);
     int* n_h = im_take(h, L, &n_d);
@@ -748,76 +814,11 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     }
     im_push(h, m_h, m_d, 3 * (int64_t)L);
     lm_push(h, a_h, a_d, 3 * (int64_t)L);
-    {
-      GemmSeg sg{};
-      sg.A = op_contigT(h->colbase, ld, 0, 0);
-      sg.B = op_contigT(h->Q1, nb, 0, 0);
-      sg.K = nb;
-      GemmBatch bt{};
-      bt.count = L; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
-      gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
-    }
-    // 4. B^T = Q_b R_b
-    for (int q = 0; q < L; ++q) {
-      const int g = lr[q];
-      HqrTask& tk = hq_fb[q];
-      tk = HqrTask{};
-      tk.A = h->Bt + (int64_t)g * nb * h->smax;
-      tk.lda = nb;
-      tk.m = ncols;
-      tk.s = t1[g];
-      tk.T = h->Tw + (int64_t)g * h->tw_stride;
-      cflops += 2.0 * ncols * t1[g] * t1[g];
-    }
-    HIPCHK(hipMemcpyAsync(h->hq_d + 2 * gc, hq_fb, L * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
-    // 5. truncation by pivoted QR of R_b (t1 x t1): Q_r into Vtmp, Z = Pi R_r[:k, :]^T.
-    // Small factors stay in registers; larger ones are copied out and pivoted
-    // in place (reflectors in the Y workspace, which Q1 no longer needs).
-    std::vector<int> big;
-    int nsmall = 0;
-    for (int q = 0; q < L; ++q)
-      if (t1[lr[q]] <= kRegQrBig) ++nsmall;
-    int qs = 0, qb = nsmall;
-    for (int q = 0; q < L; ++q) {
-      const int g = lr[q];
-      const bool small = t1[g] <= kRegQrBig;
-      QrcpTask& tk = h->tk_h[small ? qs++ : qb++];
-      tk = QrcpTask{};
-      tk.m = t1[g];
-      tk.q = t1[g];
-      tk.tol = tol_trunc;
-      tk.max_rank = maxrank + 1;
-      tk.min_tail = 0;
-      // on chip only the reflectors: Q_r is formed afterwards by hqr_apply,
-      // spread over several workgroups per tile
-      tk.Q = small ? nullptr : h->Vtmp + (int64_t)g * h->vslot;
-      tk.ldq = nb;
-      tk.tau = small ? h->Tau + (int64_t)g * kRegQrBig : nullptr;
-      tk.Z = h->Zb + (int64_t)g * h->smax * (maxrank + 1);
-      tk.ldz = h->smax;
-      tk.rank = h->qr_d + g;
-      tk.flag = h->qr_d + gc + g;
-      if (small) {
-        tk.Y = h->Bt + (int64_t)g * nb * h->smax;
-        tk.ldy = nb;
-        tk.upper = 1;
-        tk.W = h->Ybuf + (int64_t)g * nb * h->smax;
-        tk.ldw = nb;
-      } else {
-        tk.Y = h->Ybuf + (int64_t)g * nb * h->smax;
-        tk.ldy = nb;
-        big.push_back(g);
-      }
-      cflops += 4.0 * t1[g] * t1[g] * t1[g] / 3.0;
-    }
     int big_m = 0;
-    if (!big.empty()) {
-      const int nbg = (int)big.size();
-      meta_reserve(h, nbg, 2 * (int64_t)nbg);
-      int* nn_d;
+    int* nn_d = nullptr;
+    int64_t *so_d = nullptr, *do_d = nullptr;
+    if (nbg > 0) {
       int* nn_h = im_take(h, nbg, &nn_d);
-      int64_t *so_d, *do_d;
       int64_t* so_h = lm_take(h, nbg, &so_d);
       int64_t* do_h = lm_take(h, nbg, &do_d);
       for (int q = 0; q < nbg; ++q) {
@@ -828,9 +829,20 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       }
       im_push(h, nn_h, nn_d, nbg);
       lm_push(h, so_h, so_d, 2 * (int64_t)nbg);
-      HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
     }
-    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+    GemmBatch bt{};
+    bt.count = L; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
+    flat_tiles(h, bt, 128, 32, m_h, n_h);
+    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx));
+    {
+      GemmSeg sg{};
+      sg.A = op_contigT(h->colbase, ld, 0, 0);
+      sg.B = op_contigT(h->Q1, nb, 0, 0);
+      sg.K = nb;
+      gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+    }
+    HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
+    if (nbg > 0) HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
     HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
     HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
@@ -921,11 +933,6 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       cflops += 4.0 * t1[g] * k2[g] * (double)k2[g];
       ++nq;
     }
-    if (nq > 0) {
-      HIPCHK(hipMemcpyAsync(h->hq_d + 4 * gc, hq_wr, 2 * (size_t)gc * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-      HIPCHK(launch_wy_build(h->hq_d + 4 * gc, nq, h->s, max_k));
-      HIPCHK(launch_hqr_apply(h->hq_d + 5 * gc, nq, h->s, max_k));
-    }
     int q = 0, max_kx = 0;
     for (int g = 0; g < G; ++g) {
       if (dense[g] || k2[g] == 0) continue;
@@ -942,8 +949,9 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.kx = k2[g];
       tk.xrows = t1[g];
     }
-    HIPCHK(hipMemcpyAsync(h->hq_d + 3 * gc, hq_ab, nlr * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s, max_kx));
+    // regions 3 (V~), 4 and 5 (Q_r) in one upload, before the launches
+    HIPCHK(hipMemcpyAsync(h->hq_d + 3 * gc, hq_ab, (nq > 0 ? 2 * (size_t)gc + nq : (size_t)nlr) * sizeof(HqrTask),
+                          hipMemcpyHostToDevice, h->s));
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, nlr, &m_d);
     int* n_h = im_take(h, nlr, &n_d);
@@ -968,12 +976,18 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     }
     im_push(h, m_h, m_d, 3 * (int64_t)nlr);
     lm_push(h, a_h, a_d, 3 * (int64_t)nlr);
+    GemmBatch bt{};
+    bt.count = nlr; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
+    flat_tiles(h, bt, 128, 32, m_h, n_h);
+    if (nq > 0) {
+      HIPCHK(launch_wy_build(h->hq_d + 4 * gc, nq, h->s, max_k));
+      HIPCHK(launch_hqr_apply(h->hq_d + 5 * gc, nq, h->s, max_k));
+    }
+    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s, max_kx));
     GemmSeg sg{};
     sg.A = op_contig(h->Q1, nb, 0, 0);
     sg.B = op_contigT(h->Zb, h->smax, 0, 0);
     sg.K = h->smax;
-    GemmBatch bt{};
-    bt.count = nlr; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
     gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
   }
   // dense tiles: copy the tile into its block
