@@ -549,6 +549,7 @@ struct ColumnJob {
   RankPred pred;
   int64_t dense_voff;
   int g0;
+  hipEvent_t wait = nullptr;   // the compression stream waits for it before reading this column
 };
 
 // during[0], during[1]: host work to do while the compression's launches run,
@@ -620,9 +621,8 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   }
   // 1-2. sketch and range rank; a tile with fewer than 8 samples beyond its
   // rank estimate is sketched again, alone, 1.3 times as wide
+  bool waited = false;   // the jobs' wait events are on the stream
   while (!todo.empty()) {
-    int swide = 0;
-    for (int g : todo) swide = std::max(swide, sz[g]);
     const int cnt = (int)todo.size();
     // the factor's task list is uploaded before the sketch (no upload
     // between the two launches)
@@ -641,33 +641,51 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.flag = h->qr_d + gc + g;
     }
     HIPCHK(hipMemcpyAsync(h->hq_d, hq_fy, cnt * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    meta_reserve(h, 2 * (int64_t)cnt, 2 * (int64_t)cnt);
-    {
+    // Sketch of todo[sb, se).  In the first round each job's tiles get their
+    // own launch after that job's wait event, so a column that is complete
+    // early is sketched while another is still being finished elsewhere.
+    auto sketch = [&](int sb, int se) {
+      const int sn = se - sb;
+      meta_reserve(h, 2 * (int64_t)sn, 2 * (int64_t)sn);
       int *m_d, *n_d;
-      int* m_h = im_take(h, cnt, &m_d);
-      int* n_h = im_take(h, cnt, &n_d);
+      int* m_h = im_take(h, sn, &m_d);
+      int* n_h = im_take(h, sn, &n_d);
       int64_t *a_d, *c_d;
-      int64_t* a_h = lm_take(h, cnt, &a_d);
-      int64_t* c_h = lm_take(h, cnt, &c_d);
-      int maxm = 1;
-      for (int q = 0; q < cnt; ++q) {
-        const int g = todo[q];
+      int64_t* a_h = lm_take(h, sn, &a_d);
+      int64_t* c_h = lm_take(h, sn, &c_d);
+      int maxm = 1, sw = 0;
+      for (int q = 0; q < sn; ++q) {
+        const int g = todo[sb + q];
         m_h[q] = rows[g];
         n_h[q] = sz[g];
         a_h[q] = srow[g];
         c_h[q] = (int64_t)g * nb * h->smax;
         maxm = std::max(maxm, m_h[q]);
+        sw = std::max(sw, sz[g]);
       }
-      im_push(h, m_h, m_d, 2 * (int64_t)cnt);
-      lm_push(h, a_h, a_d, 2 * (int64_t)cnt);
+      im_push(h, m_h, m_d, 2 * (int64_t)sn);
+      lm_push(h, a_h, a_d, 2 * (int64_t)sn);
       GemmSeg sg{};
       sg.A = op_contig(h->colbase, ld, 0, 0);
       sg.B = op_contigT(h->omega, nb, 0, 0);
       sg.K = ncols;
       GemmBatch bt{};
-      bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
-      gemm(h, maxm, swide, 1, &sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, swide <= 64 ? 64 : 128, m_h,
+      bt.count = sn; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
+      gemm(h, maxm, sw, 1, &sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, sw <= 64 ? 64 : 128, m_h,
            n_h);
+    };
+    if (!waited) {
+      int b0 = 0;
+      for (int k = 0; k < (int)jobs.size(); ++k) {
+        int e0 = b0;
+        while (e0 < cnt && jof[todo[e0]] == k) ++e0;   // todo is in job order
+        if (jobs[k].wait) HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
+        if (e0 > b0) sketch(b0, e0);
+        b0 = e0;
+      }
+      waited = true;
+    } else {
+      sketch(0, cnt);
     }
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
@@ -707,6 +725,9 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     todo.swap(next);
     ++rounds;
   }
+  if (!waited)
+    for (const ColumnJob& jb : jobs)
+      if (jb.wait) HIPCHK(hipStreamWaitEvent(h->s, jb.wait, 0));
   std::vector<int> lr;  // tiles still headed for a low-rank form, t1 > 0
   for (int g = 0; g < G; ++g)
     if (!dense[g] && t1[g] > 0) lr.push_back(g);
@@ -1668,10 +1689,12 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         primal_update(j + 1, j, j + 1, false);
         HIPCHK(hipEventRecord(h->ev_post, h->s_main));
       }
-      HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_join, 0));
+      // the primal column is sketched as soon as it is complete; the
+      // compression waits for the tangent column only before sketching it
       std::vector<ColumnJob> jobs;
       if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
       jobs.push_back(tangent_job(j));
+      jobs.back().wait = h->ev_join;
       // The compressions of step j are issued first.  The host issues the pre
       // parts of step j + 1 (side stream) in its first wait, for the range
       // ranks, and the diagonal step of primal column j + 1 (its own stream;
