@@ -1510,7 +1510,8 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       ps.A = op_contig(ddj, nb, 0, 0);
       ps.B = op_contigT(vcat, nb, 0, 0);
       ps.K = nbj;
-      gemm(h, nbj, rsum, 1, &ps, pcat, nb, epi_linear(1.0, 0.0));
+      // 64 x 64 tiles: the product is nbj x rsum, under 200 tiles of 128 x 128
+      gemm(h, nbj, rsum, 1, &ps, pcat, nb, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
       cf += 2.0 * nbj * nbj * (double)rsum;
       int* m2_h = im_take(h, cnt, &m_d);
       int* n2_h = im_take(h, cnt, &n_d);
