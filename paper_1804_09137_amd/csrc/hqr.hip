@@ -144,8 +144,8 @@ __device__ inline void wy_update(double* M, int64_t ldm, int c0, int mm, int col
 // min_tail samples back that estimate (and t1 < m).
 //
 // The panel is factored in registers (thread: rows tid, tid + 512); per
-// column one norm reduction and one batched reduction of the 15 reflector
-// products, each finished across waves through 8 LDS partials.
+// column one batched reduction (the norm and the 15 reflector products
+// together), finished across waves through 8 LDS partials.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restrict__ tasks) {
   const HqrTask tk = tasks[blockIdx.x];
