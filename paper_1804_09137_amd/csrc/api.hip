@@ -550,6 +550,10 @@ struct ColumnJob {
   int64_t dense_voff;
   int g0;
   hipEvent_t wait = nullptr;   // the compression stream waits for it before reading this column
+  // optional: the stream that completes this column; its first sketch is
+  // launched there (after the column, ahead of that stream's later work) and
+  // `wait` is recorded after it
+  hipStream_t sketch_stream = nullptr;
 };
 
 // during[0], during[1]: host work to do while the compression's launches run,
@@ -644,9 +648,11 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     // Sketch of todo[sb, se).  In the first round each job's tiles get their
     // own launch after that job's wait event, so a column that is complete
     // early is sketched while another is still being finished elsewhere.
-    auto sketch = [&](int sb, int se) {
+    auto sketch = [&](int sb, int se, hipStream_t on) {
       const int sn = se - sb;
-      meta_reserve(h, 2 * (int64_t)sn, 2 * (int64_t)sn);
+      meta_reserve(h, 2 * (int64_t)sn, 2 * (int64_t)sn);   // on the compression stream, which owns the set
+      hipStream_t own = h->s;
+      h->s = on ? on : own;
       int *m_d, *n_d;
       int* m_h = im_take(h, sn, &m_d);
       int* n_h = im_take(h, sn, &n_d);
@@ -673,19 +679,29 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       bt.count = sn; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
       gemm(h, maxm, sw, 1, &sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, sw <= 64 ? 64 : 128, m_h,
            n_h);
+      h->s = own;
     };
     if (!waited) {
+      // A job completed on another stream is sketched there (its metadata
+      // staged in this stream's set: this stream waits for that sketch before
+      // the factor, so the set is consumed before this stream recycles it).
       int b0 = 0;
       for (int k = 0; k < (int)jobs.size(); ++k) {
         int e0 = b0;
         while (e0 < cnt && jof[todo[e0]] == k) ++e0;   // todo is in job order
-        if (jobs[k].wait) HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
-        if (e0 > b0) sketch(b0, e0);
+        if (jobs[k].sketch_stream) {
+          if (e0 > b0) sketch(b0, e0, jobs[k].sketch_stream);
+          HIPCHK(hipEventRecord(jobs[k].wait, jobs[k].sketch_stream));
+          HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
+        } else {
+          if (jobs[k].wait) HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
+          if (e0 > b0) sketch(b0, e0, nullptr);
+        }
         b0 = e0;
       }
       waited = true;
     } else {
-      sketch(0, cnt);
+      sketch(0, cnt, nullptr);
     }
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
@@ -1690,12 +1706,13 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         primal_update(j + 1, j, j + 1, false);
         HIPCHK(hipEventRecord(h->ev_post, h->s_main));
       }
-      // the primal column is sketched as soon as it is complete; the
-      // compression waits for the tangent column only before sketching it
+      // each column is sketched as soon as it is complete: the primal one on
+      // the main stream, the tangent one on the side stream after its chain
       std::vector<ColumnJob> jobs;
       if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
       jobs.push_back(tangent_job(j));
       jobs.back().wait = h->ev_join;
+      jobs.back().sketch_stream = h->s_side;
       // The compressions of step j are issued first.  The host issues the pre
       // parts of step j + 1 (side stream) in its first wait, for the range
       // ranks, and the diagonal step of primal column j + 1 (its own stream;
