@@ -165,6 +165,9 @@ struct tlr_handle_s {
   double* Tr = nullptr;     // gcap x tr_stride compact-WY factors of the truncation QR's reflectors
   int64_t tr_stride = 0;
   double* Tau = nullptr;    // gcap x kRegQrBig reflector scalars of the truncation QR
+  double* zst = nullptr;    // smax x maxrank: -(Omega^T U) of a folded column update
+  double* gbuf = nullptr;   // -(W_i^T Q1_i) of a folded column's tiles, gbuf_cap doubles
+  int64_t gbuf_cap = 0;
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags
   int* qr_h = nullptr;
 
@@ -309,6 +312,22 @@ struct DiagStream {
   explicit DiagStream(tlr_handle_s* hh) : h(hh) { h->s = h->s_diag; }
   ~DiagStream() { h->s = h->s_main; }
 };
+
+// The compression's host waits for the rank read-backs.  A handle with the
+// look-ahead streams polls the stream (the wait is on its critical path, and
+// a blocking wait adds the wake-up latency to every step); single-stream
+// handles, which run many to a process, block.
+void rank_wait(tlr_handle_s* h) {
+  if (!h->multi) {
+    HIPCHK(hipStreamSynchronize(h->s));
+    return;
+  }
+  for (;;) {
+    const hipError_t e = hipStreamQuery(h->s);
+    if (e == hipSuccess) return;
+    if (e != hipErrorNotReady) HIPCHK(e);
+  }
+}
 
 // Make room for a group of metadata takes: when the staging buffers would
 // overflow, wait for the stream that owns them (every queued copy has then
@@ -542,6 +561,18 @@ struct RankPred {
 //   tails; Q1 = Q_y[:, :t1]; B^T = C^T Q1 = Q_b R_b; R_b Pi = Q_r R_r cut at
 //   k; V~ = Q_b [Q_r; 0]; U = Q1 Pi R_r[:k, :]^T.
 // ---------------------------------------------------------------------------
+// A column update whose rows below the diagonal tile are left to the
+// compression: those tiles still owe C_i -= W_i U^T (W: the update's left
+// factor, rows from the diagonal tile on, leading dimension ldw; U: the row
+// factor, nb x K).  The compression applies it inside its sketch and
+// projection products instead of rewriting the whole column.
+struct FoldOut {
+  const double* W = nullptr;
+  int64_t ldw = 0;
+  const double* U = nullptr;
+  int K = 0;
+};
+
 struct ColumnJob {
   const double* src;
   int i_first, T, col;
@@ -554,6 +585,7 @@ struct ColumnJob {
   // launched there (after the column, ahead of that stream's later work) and
   // `wait` is recorded after it
   hipStream_t sketch_stream = nullptr;
+  FoldOut fold;   // K > 0: tile t still owes C -= W[(1 + t) nb rows..] U^T
 };
 
 // during[0], during[1]: host work to do while the compression's launches run,
@@ -599,6 +631,36 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       rows[g] = tile_rows(h, jobs[k].i_first + t);
       srow[g] = (jobs[k].src - h->colbase) + (int64_t)t * nb;
     }
+  // the pending term of the folded job, applied to tiles gs of it:
+  // C_g -= W_g U^T (W_g: rows (1 + t) nb.. of W for tile t)
+  auto fold_apply = [&](const std::vector<int>& gs) {
+    const FoldOut& fo = jobs[0].fold;
+    const int cntf = (int)gs.size();
+    if (cntf == 0 || fo.K <= 0) return;
+    meta_reserve(h, cntf, 2 * (int64_t)cntf);
+    int* fm_d;
+    int* fm_h = im_take(h, cntf, &fm_d);
+    int64_t *fa_d, *fc_d;
+    int64_t* fa_h = lm_take(h, cntf, &fa_d);
+    int64_t* fc_h = lm_take(h, cntf, &fc_d);
+    int maxm = 1;
+    for (int q = 0; q < cntf; ++q) {
+      const int g = gs[q];
+      fm_h[q] = rows[g];
+      fa_h[q] = (int64_t)(1 + tloc[g]) * nb;
+      fc_h[q] = srow[g];
+      maxm = std::max(maxm, rows[g]);
+    }
+    im_push(h, fm_h, fm_d, cntf);
+    lm_push(h, fa_h, fa_d, 2 * (int64_t)cntf);
+    GemmSeg fs{};
+    fs.A = op_contig(fo.W, fo.ldw, 0, 0);
+    fs.B = op_contig(fo.U, nb, 0, 0);
+    fs.K = fo.K;
+    GemmBatch fb{};
+    fb.count = cntf; fb.m_of = fm_d; fb.a_off = fa_d; fb.c_off = fc_d;
+    gemm(h, maxm, ncols, 1, &fs, h->colbase, ld, epi_linear(-1.0, 1.0), &fb);
+  };
   auto fail_rank = [&](int g) {
     h->bad_i = jobs[jof[g]].i_first + tloc[g];
     h->bad_j = jobs[jof[g]].col;
@@ -625,6 +687,17 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   }
   // 1-2. sketch and range rank; a tile with fewer than 8 samples beyond its
   // rank estimate is sketched again, alone, 1.3 times as wide
+  // a folded job: Zs = -(Omega^T U) (smax x K), the sketch of its pending term
+  for (const ColumnJob& jb : jobs) {
+    if (jb.fold.K <= 0) continue;
+    if (jb.fold.K > h->maxrank || &jb != &jobs[0]) throw Fail{TLR_EINVAL};   // one folded job, listed first
+    GemmSeg zs{};
+    zs.A = op_contigT(h->omega, nb, 0, 0);
+    zs.B = op_contigT(jb.fold.U, nb, 0, 0);
+    zs.K = ncols;
+    gemm(h, h->smax, jb.fold.K, 1, &zs, h->zst, h->smax, epi_linear(-1.0, 0.0));
+    cflops += 2.0 * h->smax * (double)jb.fold.K * ncols;
+  }
   bool waited = false;   // the jobs' wait events are on the stream
   while (!todo.empty()) {
     const int cnt = (int)todo.size();
@@ -648,17 +721,19 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     // Sketch of todo[sb, se).  In the first round each job's tiles get their
     // own launch after that job's wait event, so a column that is complete
     // early is sketched while another is still being finished elsewhere.
-    auto sketch = [&](int sb, int se, hipStream_t on) {
+    auto sketch = [&](int sb, int se, hipStream_t on, const ColumnJob& jb) {
       const int sn = se - sb;
-      meta_reserve(h, 2 * (int64_t)sn, 2 * (int64_t)sn);   // on the compression stream, which owns the set
+      const bool fo = jb.fold.K > 0;
+      meta_reserve(h, 2 * (int64_t)sn, (fo ? 3 : 2) * (int64_t)sn);   // on the compression stream, which owns the set
       hipStream_t own = h->s;
       h->s = on ? on : own;
       int *m_d, *n_d;
       int* m_h = im_take(h, sn, &m_d);
       int* n_h = im_take(h, sn, &n_d);
-      int64_t *a_d, *c_d;
+      int64_t *a_d, *c_d, *a1_d = nullptr;
       int64_t* a_h = lm_take(h, sn, &a_d);
       int64_t* c_h = lm_take(h, sn, &c_d);
+      int64_t* a1_h = fo ? lm_take(h, sn, &a1_d) : nullptr;
       int maxm = 1, sw = 0;
       for (int q = 0; q < sn; ++q) {
         const int g = todo[sb + q];
@@ -666,42 +741,58 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         n_h[q] = sz[g];
         a_h[q] = srow[g];
         c_h[q] = (int64_t)g * nb * h->smax;
+        if (fo) a1_h[q] = (int64_t)(1 + tloc[g]) * nb;   // rows of W for this tile
         maxm = std::max(maxm, m_h[q]);
         sw = std::max(sw, sz[g]);
       }
       im_push(h, m_h, m_d, 2 * (int64_t)sn);
-      lm_push(h, a_h, a_d, 2 * (int64_t)sn);
-      GemmSeg sg{};
-      sg.A = op_contig(h->colbase, ld, 0, 0);
-      sg.B = op_contigT(h->omega, nb, 0, 0);
-      sg.K = ncols;
+      lm_push(h, a_h, a_d, (fo ? 3 : 2) * (int64_t)sn);
+      // Y = C Omega, and with a fold + W (-(Omega^T U))^T = (C - W U^T) Omega
+      GemmSeg sg[2] = {};
+      sg[0].A = op_contig(h->colbase, ld, 0, 0);
+      sg[0].B = op_contigT(h->omega, nb, 0, 0);
+      sg[0].K = ncols;
+      if (fo) {
+        sg[1].A = op_contig(jb.fold.W, jb.fold.ldw, 0, 0);
+        sg[1].B = op_contig(h->zst, h->smax, 0, 0);
+        sg[1].K = jb.fold.K;
+        cflops += 2.0 * maxm * sw * (double)jb.fold.K * sn;
+      }
       GemmBatch bt{};
-      bt.count = sn; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
-      gemm(h, maxm, sw, 1, &sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, sw <= 64 ? 64 : 128, m_h,
-           n_h);
+      bt.count = sn; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d; bt.a_off1 = a1_d;
+      gemm(h, maxm, sw, fo ? 2 : 1, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, sw <= 64 ? 64 : 128,
+           m_h, n_h);
       h->s = own;
+    };
+    // todo is in job order: [b, e) ranges of one job each
+    auto job_ranges = [&](auto&& f) {
+      int b0 = 0;
+      for (int k = 0; k < (int)jobs.size(); ++k) {
+        int e0 = b0;
+        while (e0 < cnt && jof[todo[e0]] == k) ++e0;
+        f(k, b0, e0);
+        b0 = e0;
+      }
     };
     if (!waited) {
       // A job completed on another stream is sketched there (its metadata
       // staged in this stream's set: this stream waits for that sketch before
       // the factor, so the set is consumed before this stream recycles it).
-      int b0 = 0;
-      for (int k = 0; k < (int)jobs.size(); ++k) {
-        int e0 = b0;
-        while (e0 < cnt && jof[todo[e0]] == k) ++e0;   // todo is in job order
+      job_ranges([&](int k, int b0, int e0) {
         if (jobs[k].sketch_stream) {
-          if (e0 > b0) sketch(b0, e0, jobs[k].sketch_stream);
+          if (e0 > b0) sketch(b0, e0, jobs[k].sketch_stream, jobs[k]);
           HIPCHK(hipEventRecord(jobs[k].wait, jobs[k].sketch_stream));
           HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
         } else {
           if (jobs[k].wait) HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
-          if (e0 > b0) sketch(b0, e0, nullptr);
+          if (e0 > b0) sketch(b0, e0, nullptr, jobs[k]);
         }
-        b0 = e0;
-      }
+      });
       waited = true;
     } else {
-      sketch(0, cnt, nullptr);
+      job_ranges([&](int k, int b0, int e0) {
+        if (e0 > b0) sketch(b0, e0, nullptr, jobs[k]);
+      });
     }
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
@@ -712,7 +803,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       during[0] = nullptr;
     }
     auto h1 = std::chrono::steady_clock::now();
-    HIPCHK(hipStreamSynchronize(h->s));   // this stream only: the other may run the next step's updates
+    rank_wait(h);   // this stream only: the other may run the next step's updates
     if (h->debug) {
       const auto h2 = std::chrono::steady_clock::now();
       h->host_ms[0] += std::chrono::duration<double, std::milli>(h1 - h0).count();
@@ -827,7 +918,22 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, (gc + L) * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
     HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
     const int nbg = (int)big.size();
-    meta_reserve(h, 3 * (int64_t)L + nbg, 3 * (int64_t)L + 2 * (int64_t)nbg);
+    // A folded job's tiles lead lr (job 0 holds the lowest slots).  Their
+    // projection is C^T Q1 - U (W^T Q1): G = -(W^T Q1) first, then a second
+    // segment U G.  Should G not fit its buffer, the pending term is applied
+    // to those tiles instead.
+    int nf = 0;
+    const FoldOut fo = jobs[0].fold;
+    if (fo.K > 0) {
+      while (nf < L && jof[lr[nf]] == 0) ++nf;
+      int64_t need = 0;
+      for (int q = 0; q < nf; ++q) need += (int64_t)fo.K * t1[lr[q]];
+      if (need > h->gbuf_cap) {
+        fold_apply(std::vector<int>(lr.begin(), lr.begin() + nf));
+        nf = 0;
+      }
+    }
+    meta_reserve(h, 3 * (int64_t)L + nbg + 3 * (int64_t)nf, 3 * (int64_t)L + 2 * (int64_t)nbg + 4 * (int64_t)nf);
     // projection Bt_g = C_g^T Q1_g (ncols x t1)
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, L, &m_d);
@@ -867,16 +973,64 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       im_push(h, nn_h, nn_d, nbg);
       lm_push(h, so_h, so_d, 2 * (int64_t)nbg);
     }
-    GemmBatch bt{};
-    bt.count = L; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
-    flat_tiles(h, bt, 128, 32, m_h, n_h);
+    GemmBatch gbt{};   // G_q = -(W_q^T Q1_q): fold.K x t1, at gbuf + offset
+    int* gm_h = nullptr;
+    int* gn_h = nullptr;
+    int64_t* b1_d = nullptr;
+    if (nf > 0) {
+      int *gm_d, *gn_d, *gk_d;
+      gm_h = im_take(h, nf, &gm_d);
+      gn_h = im_take(h, nf, &gn_d);
+      int* gk_h = im_take(h, nf, &gk_d);
+      int64_t *ga_d, *gb_d, *gc_d;
+      int64_t* ga_h = lm_take(h, nf, &ga_d);
+      int64_t* gb_h = lm_take(h, nf, &gb_d);
+      int64_t* gc_h = lm_take(h, nf, &gc_d);
+      int64_t* b1_h = lm_take(h, nf, &b1_d);
+      int64_t goff = 0;
+      for (int q = 0; q < nf; ++q) {
+        const int g = lr[q];
+        gm_h[q] = fo.K;
+        gn_h[q] = t1[g];
+        gk_h[q] = rows[g];
+        ga_h[q] = (int64_t)(1 + tloc[g]) * nb;        // W rows of the tile
+        gb_h[q] = (int64_t)g * nb * h->smax;          // Q1 block
+        gc_h[q] = goff;
+        b1_h[q] = goff;
+        goff += (int64_t)fo.K * t1[g];
+        cflops += 2.0 * fo.K * t1[g] * (double)rows[g] + 2.0 * ncols * t1[g] * (double)fo.K;
+      }
+      im_push(h, gm_h, gm_d, 3 * (int64_t)nf);
+      lm_push(h, ga_h, ga_d, 4 * (int64_t)nf);
+      gbt.count = nf; gbt.m_of = gm_d; gbt.n_of = gn_d; gbt.k_of = gk_d;
+      gbt.a_off = ga_d; gbt.b_off = gb_d; gbt.c_off = gc_d;
+      flat_tiles(h, gbt, 64, 64, gm_h, gn_h);
+    }
+    GemmBatch btf{}, btr{};   // projections of the folded tiles and of the rest
+    btf.count = nf; btf.m_of = m_d; btf.n_of = n_d; btf.k_of = k_d;
+    btf.a_off = a_d; btf.b_off = b_d; btf.c_off = c_d; btf.b_off1 = b1_d;
+    btr.count = L - nf; btr.m_of = m_d + nf; btr.n_of = n_d + nf; btr.k_of = k_d + nf;
+    btr.a_off = a_d + nf; btr.b_off = b_d + nf; btr.c_off = c_d + nf;
+    if (nf > 0) flat_tiles(h, btf, 128, 32, m_h, n_h);
+    if (L > nf) flat_tiles(h, btr, 128, 32, m_h + nf, n_h + nf);
     HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx));
     {
-      GemmSeg sg{};
-      sg.A = op_contigT(h->colbase, ld, 0, 0);
-      sg.B = op_contigT(h->Q1, nb, 0, 0);
-      sg.K = nb;
-      gemm(h, ncols, maxn, 1, &sg, h->Bt, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+      GemmSeg sg[2] = {};
+      sg[0].A = op_contigT(h->colbase, ld, 0, 0);
+      sg[0].B = op_contigT(h->Q1, nb, 0, 0);
+      sg[0].K = nb;
+      if (nf > 0) {
+        GemmSeg gs{};
+        gs.A = op_contigT(fo.W, fo.ldw, 0, 0);
+        gs.B = op_contigT(h->Q1, nb, 0, 0);
+        gs.K = nb;
+        gemm(h, fo.K, maxn, 1, &gs, h->gbuf, fo.K, epi_linear(-1.0, 0.0), &gbt, false, 64, 64, gm_h, gn_h);
+        sg[1].A = op_contig(fo.U, nb, 0, 0);
+        sg[1].B = op_contigT(h->gbuf, fo.K, 0, 0);
+        sg[1].K = fo.K;
+        gemm(h, ncols, maxn, 2, sg, h->Bt, nb, epi_linear(1.0, 0.0), &btf, false, 128, 32, m_h, n_h);
+      }
+      if (L > nf) gemm(h, ncols, maxn, 1, sg, h->Bt, nb, epi_linear(1.0, 0.0), &btr, false, 128, 32, m_h + nf, n_h + nf);
     }
     HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
     if (nbg > 0) HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
@@ -889,7 +1043,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       during[1] = nullptr;
     }
     auto h1 = std::chrono::steady_clock::now();
-    HIPCHK(hipStreamSynchronize(h->s));
+    rank_wait(h);
     if (h->debug) {
       const auto h2 = std::chrono::steady_clock::now();
       h->host_ms[2] += std::chrono::duration<double, std::milli>(h1 - h0).count();
@@ -942,6 +1096,13 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       std::fprintf(stderr, "[tlr] col %d%s tiles %d rounds %d sketch<=%d t1<=%d k<=%d big %d dense %d\n", jb.col,
                    jb.F == &h->fam[1] ? "'" : "", jb.T, rounds, s_max, t1_max, k_max, nbig, nd);
     }
+  }
+  // a folded job's dense tiles take their pending term before they are copied
+  if (ndense > 0 && jobs[0].fold.K > 0) {
+    std::vector<int> gs;
+    for (int g = 0; g < G; ++g)
+      if (dense[g] && jof[g] == 0) gs.push_back(g);
+    fold_apply(gs);
   }
   // 6. V~ = Q_b [Q_r; 0] and U_g = Q1_g Z_g (m_g x k_g) for the low-rank tiles
   meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
@@ -1117,7 +1278,7 @@ struct LRTerm {
 // take most of its terms while an earlier column is still being compressed,
 // and the rest afterwards.
 void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind, int kb,
-                       int ke, bool gen) {
+                       int ke, bool gen, FoldOut* fold = nullptr) {
   kb = std::max(kb, 0);
   ke = std::min(ke, j);
   const int nt = h->nt, nb = h->nb;
@@ -1288,14 +1449,25 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
                                  epi_kind == kEpiDGenMinus, h->s));
       prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
     }
+    // fold: one chunk from the diagonal tile to the last row, no generation;
+    // only the diagonal tile is updated here (W and U_row stay in this
+    // stream's scratch for the compression)
+    const bool folding = fold && !gen && i0 == j && i1 == nt && R > 0 && R <= h->maxrank;
+    const int64_t grows = folding ? nbj : mrows;
     prof_alone_begin(h);
     const size_t e0 = prof_mark(h);
-    gemm(h, mrows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
+    gemm(h, grows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
          h->upd_tag);
     // algorithmic bytes: W and U_row read once, C read (generated) and written
-    prof_add(h, TLR_K_UPDATE, e0, 2.0 * mrows * nbj * (double)Ktrue,
-             8.0 * ((double)mrows * Ktrue + (double)nbj * Ktrue + 2.0 * (double)mrows * nbj));
+    prof_add(h, TLR_K_UPDATE, e0, 2.0 * grows * nbj * (double)Ktrue,
+             8.0 * ((double)grows * Ktrue + (double)nbj * Ktrue + 2.0 * (double)grows * nbj));
     prof_alone_end(h);
+    if (folding) {
+      fold->W = h->Wb;
+      fold->ldw = ldw;
+      fold->U = h->Urow;
+      fold->K = (int)R;
+    }
     i0 = i1;
   }
 }
@@ -1449,9 +1621,9 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   auto pbuf = [&](int j) { return (side && (j & 1)) ? h->col2 : h->col; };
   auto tbuf = [&](int j) { return (side && (j & 1)) ? h->cold2 : h->cold; };
   // generation and the terms k in [kb, ke) of primal column j
-  auto primal_update = [&](int j, int kb, int ke, bool gen) {
+  auto primal_update = [&](int j, int kb, int ke, bool gen, FoldOut* fold = nullptr) {
     LRTerm tm{&P, &P};
-    tlr_column_update(h, j, 1, &tm, pbuf(j), kEpiGenMinus, kb, ke, gen);
+    tlr_column_update(h, j, 1, &tm, pbuf(j), kEpiGenMinus, kb, ke, gen, fold);
   };
   // diagonal factorisation of primal column j
   auto primal_diag = [&](int j) {
@@ -1692,24 +1864,31 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     for (int j = 0; j < nt; ++j) {
       // main: the rest of primal column j + 1 waits for its pre part
       HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_pre, 0));
+      // Issued first: the primal column's rest and then its sketch are the
+      // longer chain to the next compression; the host issues launches about
+      // as fast as the GPU runs these short kernels.
+      // The last term of primal column j + 1 updates only its diagonal tile
+      // here; the tiles below take it inside their compression (fold).
+      FoldOut pfold;
+      if (j + 1 < nt) {
+        primal_update(j + 1, j, j + 1, false, &pfold);
+        HIPCHK(hipEventRecord(h->ev_post, h->s_main));
+      }
       {
-        // side: the rest of tangent column j, after step j - 1's compressions.
-        // Issued first: the host issues launches about as fast as the main
-        // stream's diagonal chain runs them, and this is as urgent.
+        // side: the rest of tangent column j, after step j - 1's compressions
         SideStream ss(h);
         HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
         tangent_update(j, j - 1, j, false);
         tangent_rest(j);
         HIPCHK(hipEventRecord(h->ev_join, h->s));
       }
-      if (j + 1 < nt) {
-        primal_update(j + 1, j, j + 1, false);
-        HIPCHK(hipEventRecord(h->ev_post, h->s_main));
-      }
       // each column is sketched as soon as it is complete: the primal one on
       // the main stream, the tangent one on the side stream after its chain
       std::vector<ColumnJob> jobs;
-      if (j + 1 < nt) jobs.push_back(primal_job(j + 1));
+      if (j + 1 < nt) {
+        jobs.push_back(primal_job(j + 1));
+        jobs.back().fold = pfold;
+      }
       jobs.push_back(tangent_job(j));
       jobs.back().wait = h->ev_join;
       jobs.back().sketch_stream = h->s_side;
@@ -2083,6 +2262,11 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->tr_stride = (int64_t)((kRegQrBig + 15) / 16) * 256;
       h->Tr = dalloc<double>(h, gc * h->tr_stride);
       h->Tau = dalloc<double>(h, gc * (int64_t)kRegQrBig);
+      if (h->multi) {   // folded column updates (look-ahead factorisations only)
+        h->zst = dalloc<double>(h, h->smax * (int64_t)h->maxrank);
+        h->gbuf_cap = gc * (int64_t)h->maxrank * 256;
+        h->gbuf = dalloc<double>(h, h->gbuf_cap);
+      }
       h->qr_d = dalloc<int>(h, 2 * gc);
       h->qr_h = halloc<int>(h, 2 * gc);
       HIPCHK(launch_gaussian(h->omega, nb * h->smax, (uint32_t)o->seed, h->s));

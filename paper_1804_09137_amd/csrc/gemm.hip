@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
     const int64_t chunk = (g.kt_total + g.splitk - 1) / g.splitk;
     ks = z * chunk;
     ke = ks + chunk < g.kt_total ? ks + chunk : g.kt_total;
-  } else if (g.batch.count > 1 || g.batch.a_off || g.batch.m_of || flat) {
+  } else if (g.batch.count > 1 || g.batch.a_off || g.batch.m_of || g.batch.a_off1 || flat) {
     c_off = g.batch.c_off ? g.batch.c_off[z] : z * g.batch.c_bstride;
     grow0 += z * g.ep.grow_bstride;
     for (int s = 0; s < g.nseg; ++s) {
@@ -200,6 +200,8 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
     }
     if (g.batch.a_off) aofs[0] = g.batch.a_off[z];
     if (g.batch.b_off) bofs[0] = g.batch.b_off[z];
+    if (g.batch.a_off1) aofs[1] = g.batch.a_off1[z];
+    if (g.batch.b_off1) bofs[1] = g.batch.b_off1[z];
     if (g.batch.m_of) M = g.batch.m_of[z];
     if (g.batch.n_of) N = g.batch.n_of[z];
     if (g.batch.k_of) { Kb[0] = g.batch.k_of[z]; }

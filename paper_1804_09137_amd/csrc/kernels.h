@@ -52,6 +52,9 @@ struct GemmBatch {
   const int* tile_item;
   const int* tile_first;
   int64_t ntiles;
+  // optional device arrays: per-batch element offsets of segment 1's A and B
+  const int64_t* a_off1;
+  const int64_t* b_off1;
 };
 
 // Returns hipErrorInvalidValue on bad shapes.  work (may be null) must hold
