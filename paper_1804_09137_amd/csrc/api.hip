@@ -54,6 +54,8 @@ struct tlr_handle_s {
   hipEvent_t ev_px = nullptr, ev_py = nullptr;   // profiling mode 2: isolation of update groups
   hipEvent_t ev_pre = nullptr, ev_fin = nullptr; // look-ahead: side-stream pre parts done / a step's compressions done
   hipEvent_t ev_post = nullptr, ev_diag = nullptr; // a primal column complete / its diagonal step done
+  hipEvent_t ev_rw = nullptr, ev_rest = nullptr;   // split update: W ready / rows below the diagonal tile done
+  bool rest_pending = false;                       // ev_rest recorded, not yet waited for
   // second set of update scratch for the side stream (same capacities)
   double *Wb2 = nullptr, *Xb2 = nullptr, *Urow2 = nullptr, *skw2 = nullptr, *tw2 = nullptr;
   int device = 0;
@@ -1277,8 +1279,11 @@ struct LRTerm {
 // first, gen = false subtracts from what out already holds.  A column can so
 // take most of its terms while an earlier column is still being compressed,
 // and the rest afterwards.
+// rest_on: the rows below the diagonal tile are updated on that stream
+// (ev_rest recorded there, rest_pending set): the diagonal tile is ready
+// sooner for what follows on this stream.
 void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, double* out, int epi_kind, int kb,
-                       int ke, bool gen, FoldOut* fold = nullptr) {
+                       int ke, bool gen, FoldOut* fold = nullptr, hipStream_t rest_on = nullptr) {
   kb = std::max(kb, 0);
   ke = std::min(ke, j);
   const int nt = h->nt, nb = h->nb;
@@ -1453,7 +1458,8 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     // only the diagonal tile is updated here (W and U_row stay in this
     // stream's scratch for the compression)
     const bool folding = fold && !gen && i0 == j && i1 == nt && R > 0 && R <= h->maxrank;
-    const int64_t grows = folding ? nbj : mrows;
+    const bool split = !folding && rest_on && !gen && i0 == j && i1 == nt && mrows > nbj && h->prof != 2;
+    const int64_t grows = (folding || split) ? nbj : mrows;
     prof_alone_begin(h);
     const size_t e0 = prof_mark(h);
     gemm(h, grows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
@@ -1462,6 +1468,26 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     prof_add(h, TLR_K_UPDATE, e0, 2.0 * grows * nbj * (double)Ktrue,
              8.0 * ((double)grows * Ktrue + (double)nbj * Ktrue + 2.0 * (double)grows * nbj));
     prof_alone_end(h);
+    if (split) {
+      // the rows below on rest_on, after W (no split-K: its workspace belongs
+      // to this stream); this stream's scratch stays untouched until the
+      // caller has waited for ev_rest
+      HIPCHK(hipEventRecord(h->ev_rw, h->s));
+      HIPCHK(hipStreamWaitEvent(rest_on, h->ev_rw, 0));
+      hipStream_t own = h->s;
+      h->s = rest_on;
+      GemmSeg rs = cs;
+      rs.A = op_contig(h->Wb + nbj, ldw, 0, 0);
+      const int64_t rrows = mrows - nbj;
+      const size_t e1 = prof_mark(h);
+      gemm(h, rrows, nbj, 1, &rs, cblk + nbj, h->n, epi_linear(-1.0, 1.0), nullptr, false, 0, 0, nullptr, nullptr,
+           h->upd_tag);
+      prof_add(h, TLR_K_UPDATE, e1, 2.0 * rrows * nbj * (double)Ktrue,
+               8.0 * ((double)rrows * Ktrue + (double)nbj * Ktrue + 2.0 * (double)rrows * nbj));
+      HIPCHK(hipEventRecord(h->ev_rest, h->s));
+      h->s = own;
+      h->rest_pending = true;
+    }
     if (folding) {
       fold->W = h->Wb;
       fold->ldw = ldw;
@@ -1642,9 +1668,15 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   // dC(:, j) = dSigma/dbeta - sum_k [dL_ik L_jk^T + L_ik dL_jk^T]; the
   // tangent of the diagonal step; dC_ij <- dC_ij - L_ij dL_jj^T (then
   // compressed: dL_ij = (that) L_jj^{-T}, low-rank V <- L_jj^{-1} V)
-  auto tangent_update = [&](int j, int kb, int ke, bool gen) {
+  auto tangent_update = [&](int j, int kb, int ke, bool gen, hipStream_t rest_on = nullptr) {
     LRTerm tt[2] = {{&G, &P}, {&P, &G}};
-    tlr_column_update(h, j, 2, tt, tbuf(j), kEpiDGenMinus, kb, ke, gen);
+    tlr_column_update(h, j, 2, tt, tbuf(j), kEpiDGenMinus, kb, ke, gen, nullptr, rest_on);
+  };
+  // the correction below reads and writes the rows below the diagonal tile
+  auto rest_wait = [&]() {
+    if (!h->rest_pending) return;
+    HIPCHK(hipStreamWaitEvent(h->s, h->ev_rest, 0));
+    h->rest_pending = false;
   };
   auto tangent_rest = [&](int j) {
     const int nbj = tile_rows(h, j);
@@ -1725,6 +1757,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       lm_push(h, a2_h, a_d, 3 * (int64_t)cnt);
       GemmBatch cb{};
       cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
+      rest_wait();
       HIPCHK(launch_thin_gemm(h->arena, nb, pcat, nb, cold, h->n, cb, mmax, kmax, nbj, h->s, -1.0, 1.0, true));
     } else if (cnt > 0) {
       meta_reserve(h, 6 * (int64_t)cnt, 6 * (int64_t)cnt);
@@ -1781,6 +1814,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       // dC_ij -= U_ij P_t^T: inner dimension a rank, streamed over the column
       GemmBatch cb{};
       cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
+      rest_wait();
       if (kmax <= kThinMaxK) {
         HIPCHK(launch_thin_gemm(h->arena, nb, h->Ptmp, nb, cold, h->n, cb, mmax, kmax, nbj, h->s, -1.0, 1.0, true));
       } else {
@@ -1878,8 +1912,11 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         // side: the rest of tangent column j, after step j - 1's compressions
         SideStream ss(h);
         HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
-        tangent_update(j, j - 1, j, false);
+        // the tangent's rows below its diagonal tile on the diagonal-step stream
+        // (idle here), beside the tangent of the diagonal step
+        tangent_update(j, j - 1, j, false, h->s_diag);
         tangent_rest(j);
+        rest_wait();
         HIPCHK(hipEventRecord(h->ev_join, h->s));
       }
       // each column is sketched as soon as it is complete: the primal one on
@@ -2068,7 +2105,7 @@ void free_all(tlr_handle_s* h) {
     *st = nullptr;
   }
   for (hipEvent_t* e : {&h->ev_fork, &h->ev_join, &h->ev_px, &h->ev_py, &h->ev_pre, &h->ev_fin, &h->ev_post,
-                        &h->ev_diag}) {
+                        &h->ev_diag, &h->ev_rw, &h->ev_rest}) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
@@ -2230,6 +2267,8 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         HIPCHK(hipEventCreateWithFlags(&h->ev_fin, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_post, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_diag, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_rw, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming));
         h->Wb2 = dalloc<double>(h, h->w_cap);
         h->Xb2 = dalloc<double>(h, h->x_cap);
         h->Urow2 = dalloc<double>(h, h->urow_cap);
