@@ -635,8 +635,15 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     }
   // the pending term of the folded job, applied to tiles gs of it:
   // C_g -= W_g U^T (W_g: rows (1 + t) nb.. of W for tile t)
-  auto fold_apply = [&](const std::vector<int>& gs) {
+  std::vector<char> fold_done(G, 0);   // tile g has taken the pending term
+  auto fold_apply = [&](const std::vector<int>& gs_in) {
     const FoldOut& fo = jobs[0].fold;
+    std::vector<int> gs;
+    for (int g : gs_in)
+      if (!fold_done[g]) {
+        fold_done[g] = 1;
+        gs.push_back(g);
+      }
     const int cntf = (int)gs.size();
     if (cntf == 0 || fo.K <= 0) return;
     meta_reserve(h, cntf, 2 * (int64_t)cntf);
@@ -2304,6 +2311,9 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       if (h->multi) {   // folded column updates (look-ahead factorisations only)
         h->zst = dalloc<double>(h, h->smax * (int64_t)h->maxrank);
         h->gbuf_cap = gc * (int64_t)h->maxrank * 256;
+        // TLR_FOLD_GBUF (doubles) lowers the capacity, so that tests reach the
+        // fallback that applies the folded term to the tiles instead
+        if (const char* fb = std::getenv("TLR_FOLD_GBUF")) h->gbuf_cap = std::min<int64_t>(h->gbuf_cap, std::atoll(fb));
         h->gbuf = dalloc<double>(h, h->gbuf_cap);
       }
       h->qr_d = dalloc<int>(h, 2 * gc);

@@ -102,3 +102,37 @@ def test_tlr_gradient_with_dense_tiles():
     assert h.info().dense_tiles > 0
     assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
     assert abs(gb - ref["dbeta"]) <= 100 * eps * scale
+
+
+def test_tlr_gradient_folded_term_fallbacks(monkeypatch):
+    # The primal column's last update term is folded into the compression of
+    # the tiles below its diagonal tile.  When the per-tile products of that
+    # term do not fit their buffer (forced here by a zero capacity) the term is
+    # applied to the tiles instead; tiles that end dense take it before they
+    # are copied.  The last tile's points are spread over the whole domain, so
+    # its tiles are dense while the columns above stay low rank and fold.  z
+    # need not be a sample of the field for the formula to hold.
+    n, nb, eps = 1600, 320, 1e-9
+    th = (1.0, 0.1, 0.5)
+    x, y, z = field(n, 0, th)
+    rng = np.random.default_rng(7)
+    x, y = x.copy(), y.copy()
+    x[-nb:] = rng.uniform(x.min(), x.max(), nb)
+    y[-nb:] = rng.uniform(y.min(), y.max(), nb)
+    ref = D.gradient(x, y, z, th)
+    scale = 0.5 * (abs(ref["tr_beta"]) + abs(ref["qf_beta"]))
+    xd, yd, zd = to_dev(x, y, z)
+    for cap in (None, "0"):
+        if cap is None:
+            monkeypatch.delenv("TLR_FOLD_GBUF", raising=False)
+        else:
+            monkeypatch.setenv("TLR_FOLD_GBUF", cap)
+        h = _handle(n, nb, tol=eps, maxrank=160)
+        ll, (gs, gb) = h.loglik_grad(xd, yd, zd, th)
+        info = h.info()
+        log(f"fold cap {cap}: {info.dense_tiles} dense tiles, rank_max {info.rank_max}, "
+            f"ll rel {abs(ll - ref['ll']) / abs(ref['ll']):.2e}, dbeta rel {abs(gb - ref['dbeta']) / scale:.2e}")
+        assert 0 < info.dense_tiles and info.rank_max > 0   # dense and low-rank tiles in the same columns
+        assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
+        assert abs(gb - ref["dbeta"]) <= 100 * eps * scale
+        assert abs(gs - ref["dsigma2"]) <= 100 * eps * (n / (2 * th[0]))
