@@ -1528,22 +1528,76 @@ void tangent_diag(tlr_handle_s* h, int j, const double* dc, int64_t ldc, const d
   const int nb = h->nb, nbj = tile_rows(h, j);
   double* T1 = h->tw + 64 * (int64_t)nb;
   double* Mj = T1 + (int64_t)nb * nb;
+  const double* Di = dinv_tile(h, j);
+  // The three products as batches of 64 x 64 output blocks, each with the
+  // inner range its triangular factors leave: L^{-1} is lower triangular, M
+  // is symmetric (its lower blocks suffice: Phi zeroes the rest), and L and
+  // Phi(M) are lower triangular (so is dL; its upper blocks get K = 0).
+  constexpr int TB = 64;
+  const int nq = (nbj + TB - 1) / TB;
+  const int nall = nq * nq, nlow = nq * (nq + 1) / 2;
+  meta_reserve(h, 5 * (int64_t)(2 * nall + nlow), 3 * (int64_t)(2 * nall + nlow));
+  auto blk = [&](int q) { return std::min(TB, nbj - q * TB); };
+  struct Item { int m, n, k; int64_t a, b, c; };
+  auto run = [&](const std::vector<Item>& it, const GemmSeg& sg, double* C, int64_t ldcc) {
+    const int cnt = (int)it.size();
+    int *m_d, *n_d, *k_d;
+    int* m_h = im_take(h, cnt, &m_d);
+    int* n_h = im_take(h, cnt, &n_d);
+    int* k_h = im_take(h, cnt, &k_d);
+    int64_t *a_d, *b_d, *c_d;
+    int64_t* a_h = lm_take(h, cnt, &a_d);
+    int64_t* b_h = lm_take(h, cnt, &b_d);
+    int64_t* c_h = lm_take(h, cnt, &c_d);
+    for (int q = 0; q < cnt; ++q) {
+      m_h[q] = it[q].m; n_h[q] = it[q].n; k_h[q] = it[q].k;
+      a_h[q] = it[q].a; b_h[q] = it[q].b; c_h[q] = it[q].c;
+    }
+    im_push(h, m_h, m_d, 3 * (int64_t)cnt);
+    lm_push(h, a_h, a_d, 3 * (int64_t)cnt);
+    GemmBatch bt{};
+    bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
+    gemm(h, TB, TB, 1, &sg, C, ldcc, epi_linear(1.0, 0.0), &bt, false, TB, TB, m_h, n_h);
+  };
+  std::vector<Item> it;
+  // T1 = L^{-1} dC: row block mt needs columns k < (mt + 1) 64 of L^{-1}
+  for (int mt = 0; mt < nq; ++mt)
+    for (int nt = 0; nt < nq; ++nt)
+      it.push_back({blk(mt), blk(nt), std::min(nbj, (mt + 1) * TB), (int64_t)mt * TB, (int64_t)nt * TB * ldc,
+                    (int64_t)mt * TB + (int64_t)nt * TB * nb});
   GemmSeg a{};
-  a.A = op_contig(dinv_tile(h, j), nb, 0, 0);
+  a.A = op_contig(Di, nb, 0, 0);
   a.B = op_contigT(dc, ldc, 0, 0);
   a.K = nbj;
-  gemm(h, nbj, nbj, 1, &a, T1, nb, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
+  run(it, a, T1, nb);
+  // M = T1 L^{-T}, lower blocks: column block nt needs k < (nt + 1) 64
+  it.clear();
+  for (int mt = 0; mt < nq; ++mt)
+    for (int nt = 0; nt <= mt; ++nt)
+      it.push_back({blk(mt), blk(nt), std::min(nbj, (nt + 1) * TB), (int64_t)mt * TB, (int64_t)nt * TB,
+                    (int64_t)mt * TB + (int64_t)nt * TB * nb});
   GemmSeg b{};
   b.A = op_contig(T1, nb, 0, 0);
-  b.B = op_contig(dinv_tile(h, j), nb, 0, 0);
+  b.B = op_contig(Di, nb, 0, 0);
   b.K = nbj;
-  gemm(h, nbj, nbj, 1, &b, Mj, nb, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
+  run(it, b, Mj, nb);
   HIPCHK(launch_phi_trace(Mj, nb, nbj, h->scal + h->nt + j, h->s));
+  // dL = L Phi(M): block (mt, nt) sums k in [nt 64, (mt + 1) 64); zero above
+  it.clear();
+  for (int mt = 0; mt < nq; ++mt)
+    for (int nt = 0; nt < nq; ++nt) {
+      const int k1 = std::min(nbj, (mt + 1) * TB), k0 = nt * TB;
+      if (nt <= mt)
+        it.push_back({blk(mt), blk(nt), k1 - k0, (int64_t)mt * TB + (int64_t)k0 * ldl,
+                      (int64_t)nt * TB * nb + k0, (int64_t)mt * TB + (int64_t)nt * TB * ldo});
+      else
+        it.push_back({blk(mt), blk(nt), 0, 0, 0, (int64_t)mt * TB + (int64_t)nt * TB * ldo});
+    }
   GemmSeg c{};
   c.A = op_contig(L, ldl, 0, 0);
   c.B = op_contigT(Mj, nb, 0, 0);
   c.K = nbj;
-  gemm(h, nbj, nbj, 1, &c, out, ldo, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
+  run(it, c, out, ldo);
 }
 
 void factor_dense(tlr_handle_s* h, bool tangent) {
@@ -2202,7 +2256,16 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->skw = dalloc<double>(h, h->sk_cap);
     if (h->dense) {
       h->Lp = dalloc<double>(h, panels_size(n, nb));
-      if (h->grad) h->Ldp = dalloc<double>(h, panels_size(n, nb));
+      if (h->grad) {
+        h->Ldp = dalloc<double>(h, panels_size(n, nb));
+        // metadata of the tangent's batched diagonal products
+        h->im_cap = 1 << 16;
+        h->lm_cap = 1 << 15;
+        h->im_d = dalloc<int>(h, h->im_cap);
+        h->im_h = halloc<int>(h, h->im_cap);
+        h->lm_d = dalloc<int64_t>(h, h->lm_cap);
+        h->lm_h = halloc<int64_t>(h, h->lm_cap);
+      }
     } else {
       h->D = dalloc<double>(h, nt * nb * nb);
       if (h->grad) h->Dd = dalloc<double>(h, nt * nb * nb);

@@ -204,7 +204,14 @@ __global__ void __launch_bounds__(WM * WN * 64) gemm_kernel(GemmArgs g) {
     if (g.batch.b_off1) bofs[1] = g.batch.b_off1[z];
     if (g.batch.m_of) M = g.batch.m_of[z];
     if (g.batch.n_of) N = g.batch.n_of[z];
-    if (g.batch.k_of) { Kb[0] = g.batch.k_of[z]; }
+    if (g.batch.k_of) {
+      Kb[0] = g.batch.k_of[z];
+      // one segment: the K loop stops at this item's own K
+      if (g.nseg == 1) {
+        const int64_t kz = (Kb[0] + BK - 1) / BK;
+        ke = kz < ke ? kz : ke;
+      }
+    }
   }
   const int64_t m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
