@@ -156,29 +156,39 @@ hipError_t launch_logdiag(const double* A, int64_t lda, int64_t m, double* out, 
   return hipGetLastError();
 }
 
-// y[0:m] = beta * y + alpha * A[0:m, 0:k] x   (A column-major, one thread per row)
+// y[0:m] = beta * y + alpha * A[0:m, 0:k] x   (A column-major).  Workgroup
+// of 64 rows; its four waves take a quarter of the columns each, eight loads
+// in flight per lane, and add their sums through LDS.
 __global__ void __launch_bounds__(256) gemv_n_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t k,
                                                      const double* __restrict__ x, double alpha, double beta,
                                                      double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= m) return;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t c = 0;
-  for (; c + 4 <= k; c += 4) {
-    a0 += A[c * lda + i] * x[c];
-    a1 += A[(c + 1) * lda + i] * x[c + 1];
-    a2 += A[(c + 2) * lda + i] * x[c + 2];
-    a3 += A[(c + 3) * lda + i] * x[c + 3];
+  __shared__ double red[4][64];
+  const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + rl;
+  const int64_t ic = i < m ? i : m - 1;   // rows past m read row m - 1 (not stored)
+  const int64_t kq = (k + 3) / 4;
+  const int64_t c0 = g * kq, c1 = (c0 + kq < k) ? c0 + kq : k;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  int64_t c = c0;
+  for (; c + 8 <= c1; c += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += A[(c + u) * lda + ic] * x[c + u];
   }
-  for (; c < k; ++c) a0 += A[c * lda + i] * x[c];
-  const double v = (a0 + a1) + (a2 + a3);
-  y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * v;
+  for (; c < c1; ++c) acc[0] += A[c * lda + ic] * x[c];
+  red[g][rl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (g == 0 && i < m) {
+    const double v = (red[0][rl] + red[1][rl]) + (red[2][rl] + red[3][rl]);
+    y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * v;
+  }
 }
 
 hipError_t launch_gemv_n(const double* A, int64_t lda, int64_t m, int64_t k, const double* x, double alpha,
                          double beta, double* y, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A, lda, m, k, x, alpha,
+  hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, A, lda, m, k, x, alpha,
                      beta, y);
   return hipGetLastError();
 }
