@@ -168,6 +168,7 @@ struct tlr_handle_s {
   int64_t tr_stride = 0;
   double* Tau = nullptr;    // gcap x kRegQrBig reflector scalars of the truncation QR
   double* zst = nullptr;    // smax x maxrank: -(Omega^T U) of a folded column update
+  double* lrtws = nullptr;  // nt x kLrMaxRank: the low-rank apply's t = B^T v per tile
   double* gbuf = nullptr;   // -(W_i^T Q1_i) of a folded column's tiles, gbuf_cap doubles
   int64_t gbuf_cap = 0;
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags
@@ -2022,6 +2023,18 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
 }
 
 // log|Sigma~| and y = L^{-1} z (into vec[1]); returns (logdet, quad)
+// largest rank of the tiles below the diagonal in column j (col) or left of
+// it in row j (!col), for the low-rank apply launches
+int lr_kmax(const tlr_handle_s* h, int j, bool col) {
+  const Family& F = h->fam[0];
+  int km = 0;
+  if (col)
+    for (int i = j + 1; i < h->nt; ++i) km = std::max(km, F.rk[tid_of(h, i, j)]);
+  else
+    for (int k = 0; k < j; ++k) km = std::max(km, F.rk[tid_of(h, j, k)]);
+  return km;
+}
+
 void solve_forward(tlr_handle_s* h, const double* z, double* logdet, double* quad) {
   const int nt = h->nt, nb = h->nb;
   const int64_t n = h->n;
@@ -2041,7 +2054,8 @@ void solve_forward(tlr_handle_s* h, const double* z, double* logdet, double* qua
         LowRankApply a{};
         a.arena = h->arena; a.uoff = h->fam[0].uoff_d; a.voff = h->fam[0].voff_d; a.ranks = h->fam[0].rk_d;
         a.n = n; a.nb = nb; a.nt = nt; a.fixed = j; a.forward = 1; a.v = ys; a.out = w; a.scale = -1.0;
-        HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s));
+        a.tws = h->lrtws;
+        HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s, lr_kmax(h, j, true)));
       }
     }
   }
@@ -2074,7 +2088,8 @@ void solve_backward(tlr_handle_s* h) {
       LowRankApply a{};
       a.arena = h->arena; a.uoff = h->fam[0].uoff_d; a.voff = h->fam[0].voff_d; a.ranks = h->fam[0].rk_d;
       a.n = n; a.nb = nb; a.nt = nt; a.fixed = i; a.forward = 0; a.v = al; a.out = r; a.scale = -1.0;
-      HIPCHK(launch_lowrank_apply(a, i, h->s));
+      a.tws = h->lrtws;
+      HIPCHK(launch_lowrank_apply(a, i, h->s, lr_kmax(h, i, false)));
     }
   }
 }
@@ -2269,6 +2284,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     } else {
       h->D = dalloc<double>(h, nt * nb * nb);
       if (h->grad) h->Dd = dalloc<double>(h, nt * nb * nb);
+      h->lrtws = dalloc<double>(h, nt * (int64_t)kLrMaxRank);
       // arena: [U0 | V0 | U1 | V1] slots, dense blocks, identity, Dinv tiles
       const int nfam = h->grad ? 2 : 1;
       const int64_t nslots = std::max<int64_t>(h->ntiles, 1);
@@ -2553,7 +2569,8 @@ tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z) {
         LowRankApply a{};
         a.arena = h->arena; a.uoff = h->fam[0].uoff_d; a.voff = h->fam[0].voff_d; a.ranks = h->fam[0].rk_d;
         a.n = n; a.nb = nb; a.nt = nt; a.fixed = j; a.forward = 1; a.v = d_eps; a.out = d_z; a.scale = 1.0;
-        HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s));
+        a.tws = h->lrtws;
+        HIPCHK(launch_lowrank_apply(a, nt - j - 1, h->s, lr_kmax(h, j, true)));
       }
     }
     sync(h);

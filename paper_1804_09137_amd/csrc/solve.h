@@ -20,8 +20,12 @@ struct LowRankApply {
   const double* v;     // full-length vector read
   double* out;         // full-length vector updated
   double scale;        // out += scale * (product); the solves use -1
+  double* tws;         // workspace: kLrMaxRank doubles per tile of the launch (t = B^T v)
 };
+constexpr int kLrMaxRank = 1024;   // ranks (and dense tiles' nb) up to this
 
-hipError_t launch_lowrank_apply(const LowRankApply& a, int count, hipStream_t s);
+// kmax: the largest rank among the launch's tiles (<= kLrMaxRank); a.tws holds
+// count * kLrMaxRank doubles.
+hipError_t launch_lowrank_apply(const LowRankApply& a, int count, hipStream_t s, int kmax);
 
 }  // namespace tlrk
