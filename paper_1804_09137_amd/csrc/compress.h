@@ -61,7 +61,7 @@ hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
 // X columns are split over workgroups kApplyCols at a time: max_kx must be
 // at least every task's kx (columns beyond the split it covers are left
 // untouched).
-constexpr int kApplyCols = 32;
+constexpr int kApplyCols = 16;
 hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx);
 // The compact-WY factors T (per 16 reflectors, the layout hqr_factor writes)
 // of s Householder vectors stored as hqr_factor stores them (A, lda, m rows,
