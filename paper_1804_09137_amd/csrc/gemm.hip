@@ -487,12 +487,12 @@ hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, doub
 // (once per 16 columns of C, re-reads hit L2), B is staged in LDS 16
 // columns at a time and read as broadcasts, each thread owns one row of C.
 // Workgroup (p, y, z) covers rows [256 y, 256 y + 256) and columns
-// [64 z, 64 z + 64) of pair p.
+// [kThinGroup z, kThinGroup (z + 1)) of pair p.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kThinRows = 256;
 constexpr int kThinCols = 16;
-constexpr int kThinGroup = 64;   // columns per workgroup
+constexpr int kThinGroup = 32;   // columns per workgroup
 }  // namespace
 
 __global__ void __launch_bounds__(kThinRows) thin_gemm_kernel(const double* __restrict__ A, int64_t lda,
