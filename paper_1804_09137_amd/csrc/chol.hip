@@ -157,16 +157,17 @@ hipError_t launch_logdiag(const double* A, int64_t lda, int64_t m, double* out, 
 }
 
 // y[0:m] = beta * y + alpha * A[0:m, 0:k] x   (A column-major).  Workgroup
-// of 64 rows; its four waves take a quarter of the columns each, eight loads
-// in flight per lane, and add their sums through LDS.
-__global__ void __launch_bounds__(256) gemv_n_kernel(const double* __restrict__ A, int64_t lda, int64_t m, int64_t k,
-                                                     const double* __restrict__ x, double alpha, double beta,
-                                                     double* __restrict__ y) {
-  __shared__ double red[4][64];
+// of 64 rows; its sixteen waves take a sixteenth of the columns each, eight
+// loads in flight per lane, and add their sums through LDS.
+constexpr int kGemvWaves = 16;
+__global__ void __launch_bounds__(64 * kGemvWaves) gemv_n_kernel(const double* __restrict__ A, int64_t lda, int64_t m,
+                                                                 int64_t k, const double* __restrict__ x,
+                                                                 double alpha, double beta, double* __restrict__ y) {
+  __shared__ double red[kGemvWaves][64];
   const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + rl;
   const int64_t ic = i < m ? i : m - 1;   // rows past m read row m - 1 (not stored)
-  const int64_t kq = (k + 3) / 4;
+  const int64_t kq = (k + kGemvWaves - 1) / kGemvWaves;
   const int64_t c0 = g * kq, c1 = (c0 + kq < k) ? c0 + kq : k;
   double acc[8];
 #pragma unroll
@@ -180,7 +181,9 @@ __global__ void __launch_bounds__(256) gemv_n_kernel(const double* __restrict__ 
   red[g][rl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   if (g == 0 && i < m) {
-    const double v = (red[0][rl] + red[1][rl]) + (red[2][rl] + red[3][rl]);
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGemvWaves; ++q) v += red[q][rl];
     y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * v;
   }
 }
@@ -188,8 +191,8 @@ __global__ void __launch_bounds__(256) gemv_n_kernel(const double* __restrict__ 
 hipError_t launch_gemv_n(const double* A, int64_t lda, int64_t m, int64_t k, const double* x, double alpha,
                          double beta, double* y, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, A, lda, m, k, x, alpha,
-                     beta, y);
+  hipLaunchKernelGGL(gemv_n_kernel, dim3((unsigned)((m + 63) / 64)), dim3(64 * kGemvWaves), 0, s, A, lda, m, k, x,
+                     alpha, beta, y);
   return hipGetLastError();
 }
 
