@@ -1234,40 +1234,48 @@ void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt
   }
   const int cnt = (int)ts.size();
   if (cnt == 0) return;
-  meta_reserve(h, 3 * (int64_t)cnt, 3 * (int64_t)cnt);
-  int *m_d, *n_d, *k_d;
-  int* m_h = im_take(h, cnt, &m_d);
-  int* n_h = im_take(h, cnt, &n_d);
-  int* k_h = im_take(h, cnt, &k_d);
-  int64_t *a_d, *b_d, *c_d;
-  int64_t* a_h = lm_take(h, cnt, &a_d);
-  int64_t* b_h = lm_take(h, cnt, &b_d);
-  int64_t* c_h = lm_take(h, cnt, &c_d);
+  // one item per 128-row block of each tile: L_jj^{-1} is lower triangular,
+  // so rows [128 b, 128 b + 128) need only its first 128 (b + 1) columns
+  constexpr int RB = 128;
   const int nbj = tile_rows(h, col);
+  const int nrb = (nbj + RB - 1) / RB;
+  const int items = cnt * nrb;
+  meta_reserve(h, 3 * (int64_t)items, 3 * (int64_t)items);
+  int *m_d, *n_d, *k_d;
+  int* m_h = im_take(h, items, &m_d);
+  int* n_h = im_take(h, items, &n_d);
+  int* k_h = im_take(h, items, &k_d);
+  int64_t *a_d, *b_d, *c_d;
+  int64_t* a_h = lm_take(h, items, &a_d);
+  int64_t* b_h = lm_take(h, items, &b_d);
+  int64_t* c_h = lm_take(h, items, &c_d);
   int maxk = 0;
   double kt = 0.0;
   for (int q = 0; q < cnt; ++q) {
     const int t = ts[q];
     const size_t id = tid_of(h, i_first + t, col);
-    m_h[q] = nbj;
-    n_h[q] = F.rk[id];
-    k_h[q] = nbj;
-    a_h[q] = 0;
-    b_h[q] = (int64_t)t * h->vslot;
-    c_h[q] = F.voff[id];
-    maxk = std::max(maxk, n_h[q]);
-    kt += n_h[q];
+    for (int rb = 0; rb < nrb; ++rb) {
+      const int e = q * nrb + rb;
+      m_h[e] = std::min(RB, nbj - rb * RB);
+      n_h[e] = F.rk[id];
+      k_h[e] = std::min(nbj, (rb + 1) * RB);
+      a_h[e] = (int64_t)rb * RB;
+      b_h[e] = (int64_t)t * h->vslot;
+      c_h[e] = F.voff[id] + (int64_t)rb * RB;
+    }
+    maxk = std::max(maxk, (int)F.rk[id]);
+    kt += F.rk[id];
   }
-  im_push(h, m_h, m_d, 3 * (int64_t)cnt);
-  lm_push(h, a_h, a_d, 3 * (int64_t)cnt);
+  im_push(h, m_h, m_d, 3 * (int64_t)items);
+  lm_push(h, a_h, a_d, 3 * (int64_t)items);
   GemmSeg sg{};
   sg.A = op_contig(dinv_tile(h, col), h->nb, 0, 0);
   sg.B = op_contigT(vt, h->nb, 0, 0);
   sg.K = nbj;
   GemmBatch bt{};
-  bt.count = cnt; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
+  bt.count = items; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
   const size_t e_t = prof_mark(h);
-  gemm(h, nbj, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+  gemm(h, RB, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
   prof_add(h, TLR_K_LOWRANK, e_t, 2.0 * nbj * nbj * kt, 8.0 * (2.0 * nbj * kt + (double)nbj * nbj));
 }
 
