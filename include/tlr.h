@@ -78,7 +78,9 @@ typedef enum {
                                    steps on two streams of its own, with a look-ahead over the
                                    compressions (faster alone, but many handles evaluated at once,
                                    as by tlr_loglik_grad_batched, then contend for hardware queues)
-                                   and holds two more n x nb column buffers */
+                                   and holds two more n x nb column buffers.  Such a handle's host
+                                   thread polls the GPU while a compression's ranks are read back;
+                                   single-stream handles block */
 
 typedef struct {
   int64_t n;          /* number of locations (>= 1) */
