@@ -220,7 +220,7 @@ def main():
     ap.add_argument("--multi-stream", action="store_true",
                     help="--batched: give each field's handle its side and diagonal streams too")
     ap.add_argument("--hw-queues", type=int, default=16,
-                    help="GPU_MAX_HW_QUEUES for --batched when the environment does not set it")
+                    help="GPU_MAX_HW_QUEUES for --batched (replaces the inherited value; 1..32)")
     ap.add_argument("--batched-budget-gb", type=float, default=200.0,
                     help="device memory the handles of one group of fields may hold")
     args = ap.parse_args()
@@ -241,11 +241,14 @@ def main():
         sys.exit(2)
 
     if args.batched:
-        # Every field runs on two streams of its own; the HIP runtime maps all
+        # Every field runs on a stream of its own; the HIP runtime maps all
         # streams of the process onto GPU_MAX_HW_QUEUES hardware queues (4 by
-        # default), which serialises the fields.  Read when the runtime
-        # starts, so it is set before torch touches the GPU.
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(args.hw_queues))
+        # default, and environments often export that default), which
+        # serialises the fields.  The runtime reads it when it starts, so it
+        # is set here, before torch touches the GPU, over any inherited value.
+        if not 1 <= args.hw_queues <= 32:
+            sys.exit("--hw-queues must be in 1..32")
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
         print(json.dumps(batched(args)), flush=True)
         return
 

@@ -190,7 +190,7 @@ tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y,
  * streams of a process over GPU_MAX_HW_QUEUES hardware queues (4 unless set
  * before the runtime starts), so fields overlap only as far as that allows:
  * with handles created with TLR_FLAG_SINGLE_STREAM, 16 threads over 16 queues
- * evaluated 32 fields of n <= 20,000 5.6x faster than one at a time; 32
+ * evaluated 64 fields of n <= 20,000 4.6x faster than one at a time; 32
  * queues slow every stream down.  Batched evaluation is not in the paper: it serves many small
  * fields, whose individual evaluations cannot fill the GPU. */
 tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, const double* const* d_x,
