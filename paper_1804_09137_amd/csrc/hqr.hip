@@ -31,6 +31,18 @@ namespace tlrk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Global-memory views of the task pointers.  The tasks live in device memory,
+// so a plain pointer read from one could name any address space as far as
+// the compiler knows, and it emits flat loads and stores.  Flat operations
+// also count against the LDS counter: each wait for an LDS read would then
+// wait for the outstanding global traffic too.  Every task pointer addresses
+// global memory (device or host-mapped; never LDS or scratch).
+typedef __attribute__((address_space(1))) double gdouble;
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 namespace {
 
 constexpr int NT = 512;                 // threads per workgroup
@@ -58,7 +70,7 @@ __device__ inline double vval_lds(const double* P, int r, int c, int mm, bool li
 // block through a wave-private 16 x 17 LDS tile (its slot of `red`) for
 // V^T M.  Three barriers.
 template <bool TRANS>
-__device__ inline void wy_update(double* M, int64_t ldm, int c0, int mm, int col0, int ncol, int rb, int nblk,
+__device__ inline void wy_update(gdouble* M, int64_t ldm, int c0, int mm, int col0, int ncol, int rb, int nblk,
                                  const double (&vx)[MB][4], const double* P, int nlive, double* red, double* Wf,
                                  double* Wp, const double* Ts, int tid, int lane, int w) {
   double* tile = red + w * RS;   // 16 x 17 transpose tile; later this wave's partial W
@@ -166,7 +178,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
     }
     return;
   }
-  double* A = tk.A;
+  gdouble* A = gptr(tk.A);
   const int64_t lda = tk.lda;
   const int nref = m < s ? m : s;
   const int np = (nref + PB - 1) / PB;
@@ -180,7 +192,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
     double a0[PB], a1[PB];
 #pragma unroll
     for (int c = 0; c < PB; ++c) {
-      const double* ac = A + (int64_t)(c0 + c) * lda + c0;
+      const gdouble* ac = A + (int64_t)(c0 + c) * lda + c0;
       a0[c] = (c < pw && r0 < mm) ? ac[r0] : 0.0;
       a1[c] = (c < pw && r1 < mm) ? ac[r1] : 0.0;
     }
@@ -244,7 +256,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
     for (int c = 0; c < PB; ++c) {
       if (r0 < mm) P[c * LDP + r0] = a0[c];
       if (r1 < mm) P[c * LDP + r1] = a1[c];
-      double* ac = A + (int64_t)(c0 + c) * lda + c0;
+      gdouble* ac = A + (int64_t)(c0 + c) * lda + c0;
       if (c < pw && r0 < mm) ac[r0] = a0[c];
       if (c < pw && r1 < mm) ac[r1] = a1[c];
     }
@@ -289,7 +301,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
 #pragma unroll
       for (int l = 0; l < 16; ++l) {
         Ts[lane * 16 + l] = tr[l];
-        tk.T[(int64_t)p * 256 + lane * 16 + l] = tr[l];
+        gptr(tk.T)[(int64_t)p * 256 + lane * 16 + l] = tr[l];
       }
     }
     __syncthreads();
@@ -305,7 +317,7 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
     const double tol2 = tk.tol * tk.tol;
     for (int i = tid; i < s; i += NT) {
       const int top = i < m - 1 ? i : m - 1;
-      const double* ci = A + (int64_t)i * lda;
+      const gdouble* ci = A + (int64_t)i * lda;
       double acc = 0.0;
       int ti = top + 1;
       for (int l = top; l >= 0; --l) {
@@ -345,9 +357,9 @@ __global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict
   const int x0 = blockIdx.y * kApplyCols;
   const int kx = tk.kx < x0 + kApplyCols ? tk.kx : x0 + kApplyCols;   // this workgroup: columns [x0, kx)
   if (m <= 0 || kx <= x0) return;
-  double* X = tk.X;
+  gdouble* X = gptr(tk.X);
   const int64_t ldx = tk.ldx;
-  const double* A = tk.A;
+  const gdouble* A = gptr(tk.A);
   const int64_t lda = tk.lda;
   if (tk.identity) {
     for (int c = x0; c < kx; ++c)
@@ -365,10 +377,10 @@ __global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict
     const int mm = m - c0;
     const int nlive = nref - c0;
     __syncthreads();   // previous panel done with P, Ts and X
-    if (tid < 256) Ts[tid] = tk.T[(int64_t)p * 256 + tid];
+    if (tid < 256) Ts[tid] = gptr(tk.T)[(int64_t)p * 256 + tid];
 #pragma unroll
     for (int c = 0; c < PB; ++c) {
-      const double* ac = A + (int64_t)(c0 + c) * lda + c0;
+      const gdouble* ac = A + (int64_t)(c0 + c) * lda + c0;
       for (int r = tid; r < mm; r += NT) P[c * LDP + r] = (c < nlive) ? ac[r] : 0.0;
     }
     __syncthreads();
@@ -458,7 +470,7 @@ __device__ __forceinline__ void qrcp_reg_body(const QrcpTask& tk, const QrShared
   double* vs = sh.vs;
   double* taus = sh.taus;
   int* step_of = sh.step_of;
-  const double* Y = tk.Y;
+  const gdouble* Y = gptr(tk.Y);
   const int64_t ldy = tk.ldy;
   Share a;
   a.xr = sh.xr;
@@ -616,12 +628,12 @@ __device__ __forceinline__ void qrcp_reg_body(const QrcpTask& tk, const QrShared
       const int r = lane + 64 * i;
       if (r >= m) continue;
       const double v = a.get(j, i);
-      if (tk.Z && r < rank) tk.Z[(int64_t)r * tk.ldz + c] = (st >= r) ? v : 0.0;
-      if (st < rank) tk.W[(int64_t)st * tk.ldw + r] = (r > st) ? v : 0.0;
+      if (tk.Z && r < rank) gptr(tk.Z)[(int64_t)r * tk.ldz + c] = (st >= r) ? v : 0.0;
+      if (st < rank) gptr(tk.W)[(int64_t)st * tk.ldw + r] = (r > st) ? v : 0.0;
     }
   }
   if (tk.tau)
-    for (int i = tid; i < rank; i += NT) tk.tau[i] = taus[i];
+    for (int i = tid; i < rank; i += NT) gptr(tk.tau)[i] = taus[i];
   if (!tk.Q || rank == 0) return;
   __syncthreads();
   // explicit Q = H_0 ... H_{rank-1} [I; 0]: column c still equals e_c before
@@ -642,7 +654,7 @@ __device__ __forceinline__ void qrcp_reg_body(const QrcpTask& tk, const QrShared
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int r = lane + 64 * i;
-      vv[i] = (r == st) ? 1.0 : ((r > st && r < m) ? tk.W[(int64_t)st * tk.ldw + r] : 0.0);
+      vv[i] = (r == st) ? 1.0 : ((r > st && r < m) ? gptr(tk.W)[(int64_t)st * tk.ldw + r] : 0.0);
     }
     double lo, hi;
     reduce_cols([&](int j) {
@@ -671,7 +683,7 @@ __device__ __forceinline__ void qrcp_reg_body(const QrcpTask& tk, const QrShared
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
       const int r = lane + 64 * i;
-      if (r < m) tk.Q[(int64_t)c * tk.ldq + r] = qa.get(j, i);
+      if (r < m) gptr(tk.Q)[(int64_t)c * tk.ldq + r] = qa.get(j, i);
     }
   }
 }
@@ -736,7 +748,7 @@ __global__ void __launch_bounds__(256) wy_build_kernel(const HqrTask* __restrict
 #pragma unroll
     for (int c = 0; c < PB; ++c) {
       double v = 0.0;
-      if (c < nlive && r < mm) v = (r == c) ? 1.0 : (r > c ? tk.A[(int64_t)(c0 + c) * tk.lda + c0 + r] : 0.0);
+      if (c < nlive && r < mm) v = (r == c) ? 1.0 : (r > c ? gptr(tk.A)[(int64_t)(c0 + c) * tk.lda + c0 + r] : 0.0);
       V[c][tid] = v;
     }
     __syncthreads();
@@ -755,11 +767,11 @@ __global__ void __launch_bounds__(256) wy_build_kernel(const HqrTask* __restrict
 #pragma unroll
       for (int l = 0; l < PB; ++l)
         if (l < i && l >= lane) acc += tr[l] * G[l * PB + i];
-      const double ti = (i < nlive) ? tk.tau[c0 + i] : 0.0;
+      const double ti = (i < nlive) ? gptr(tk.tau)[c0 + i] : 0.0;
       tr[i] = (lane < i) ? -ti * acc : (lane == i ? ti : 0.0);
     }
 #pragma unroll
-    for (int l = 0; l < PB; ++l) tk.T[(int64_t)p * 256 + lane * PB + l] = tr[l];
+    for (int l = 0; l < PB; ++l) gptr(tk.T)[(int64_t)p * 256 + lane * PB + l] = tr[l];
   }
 }
 
