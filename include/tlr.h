@@ -40,7 +40,8 @@ typedef enum {
   TLR_OK = 0,
   TLR_ENOTSPD = 1,     /* Sigma not positive definite: *info = 1-based global row of the first bad pivot */
   TLR_EINVAL = -1,     /* bad argument (null pointer, size, non-positive or non-finite theta, ...) */
-  TLR_ENOMEM = -2,     /* device allocation failed in tlr_create */
+  TLR_ENOMEM = -2,     /* device allocation failed in tlr_create, or the tile storage fixed by
+                          tlr_opts.arena_bytes is too small for the factor */
   TLR_EHIP = -3,       /* a HIP runtime call failed */
   TLR_ERANK = -4,      /* a tile needed a rank above opts.maxrank; see tlr_get_info().bad_tile_* */
   TLR_ENOTIMPL = -5,   /* requested combination not available */
@@ -60,14 +61,18 @@ typedef enum {
                                  rounding of a densely accumulated update is a full-rank
                                  perturbation of about 1e-7 of the update's magnitude, which the
                                  compression keeps: ranks (and dense tiles) grow unless tol is
-                                 well above that level.  The log-likelihood keeps the compression
-                                 accuracy only for a well-conditioned Sigma: where the smallest
-                                 eigenvalue is near that perturbation, the factor either loses
-                                 accuracy silently (seen: 3e-3 relative at eps = 1e-6) or meets a
-                                 negative pivot.  In the latter case the factorisation is repeated
-                                 with FP64 products and the handle keeps FP64 products for its
-                                 later calls (tlr_info.prec_used, fp64_retries), so a TLR_ENOTSPD
-                                 result is never caused by the FP32 products */
+                                 well above that level.  Where Sigma is ill-conditioned the
+                                 perturbation can cost far more than tol (seen: 3e-3 relative at
+                                 eps = 1e-6) or produce a negative pivot.  Both are caught: a
+                                 negative pivot, and a first-order estimate of the change of
+                                 log|Sigma| (sum over diagonal tiles of
+                                 2^-24 ||update_jj||_F ||(L_jj L_jj^T)^{-1}||_F) above 5 tol |l|,
+                                 checked by tlr_loglik and tlr_loglik_grad once l is known,
+                                 make the library factor again with FP64 products; the handle then
+                                 keeps FP64 products for its later calls (tlr_info.prec_used,
+                                 fp64_retries, fp32_err_bound).  A TLR_ENOTSPD result is never
+                                 caused by the FP32 products.  tlr_potrf alone does not check:
+                                 tlr_sample and tlr_get_tile see the FP32-product factor */
 } tlr_prec;
 
 /* tlr_opts.flags */
@@ -95,6 +100,14 @@ typedef struct {
   int32_t seed;       /* seed of the Gaussian sketch matrix used by TLR compression */
   int32_t flags;      /* TLR_FLAG_* */
   int32_t reserved;   /* must be 0 */
+  int64_t arena_bytes; /* TLR: device bytes for the storage of the off-diagonal tiles (U and V of
+                          each low-rank tile at its rank, nb x nb for a dense one; the factor and,
+                          with want_grad, its tangent).  > 0: exactly that much, allocated by
+                          tlr_create; a factorisation (or tlr_compress) that needs more fails with
+                          TLR_ENOMEM, and the handle stays usable.  0: sized for every tile at rank
+                          max(16, maxrank / 8) plus two dense tiles per tile column, and doubled
+                          (reallocated, the pass started again) whenever a pass needs more.
+                          < 0: TLR_EINVAL.  Ignored in DENSE mode */
 } tlr_opts;
 
 typedef struct {
@@ -106,11 +119,20 @@ typedef struct {
   int32_t dense_tiles;        /* strictly-lower tiles kept dense */
   int32_t bad_tile_i, bad_tile_j; /* TLR_ERANK: offending tile */
   int32_t prec_used;          /* tlr_prec of the last factor: TLR_PREC_FP64 when an FP32-update
-                                 factor lost definiteness and was computed again in FP64 */
+                                 factor lost definiteness or failed the accuracy check and was
+                                 computed again in FP64 */
   int32_t fp64_retries;       /* such repeated factorisations over the handle's life (0 or 1) */
   double t_factor_ms;         /* device time of the last factorisation (hipEvents) */
   double t_solve_ms;          /* device time of the last log-det + solves */
   double t_grad_ms;           /* device time of the gradient terms of the last tlr_loglik_grad */
+  int64_t tile_bytes_used;    /* TLR: tile storage taken by the last factor (or tlr_compress) */
+  int64_t tile_bytes_cap;     /* TLR: tile storage available (see tlr_opts.arena_bytes) */
+  int32_t arena_grows;        /* TLR, arena_bytes = 0: times the tile storage was doubled */
+  int32_t splitk_launches;    /* GEMM launches of the last factorisation that split their K range
+                                 over several workgroups (long inner dimension, few output tiles) */
+  double fp32_err_bound;      /* TLR_PREC_FP32_UPDATES: estimated |l_FP32 - l_FP64| / |l| of the last
+                                 log-likelihood computed from a factor with FP32 products (see
+                                 TLR_PREC_FP32_UPDATES); 0 when the factor used FP64 products */
 } tlr_info;
 
 /* Kernel classes timed by tlr_profile (each a group of launches). */
@@ -215,6 +237,12 @@ tlr_status tlr_get_kstats(tlr_handle_t h, tlr_kstat* out);
  * for i > j (other entries 0); a tile kept dense reports its width.
  * nt = ceil(n / nb). */
 tlr_status tlr_get_ranks(tlr_handle_t h, int32_t* host_ranks);
+
+/* Rank table of the tangent factor dL/dbeta of the last tlr_loglik_grad
+ * (want_grad handles; the forward-mode derivative of the TLR Cholesky, whose
+ * off-diagonal tiles are compressed like L's), laid out as tlr_get_ranks.
+ * TLR_ESTATE without want_grad. */
+tlr_status tlr_get_tangent_ranks(tlr_handle_t h, int32_t* host_ranks);
 
 /* Sizes, memory, rank statistics and timings of the handle. */
 tlr_status tlr_get_info(tlr_handle_t h, tlr_info* out);

@@ -55,7 +55,7 @@ class Handle:
 
     def __init__(self, n: int, nb: int, tol: float = 1e-9, maxrank: int = 0, mode: str = "tlr",
                  prec: str = "fp64", want_grad: bool = False, seed: int = 0, strict_rank: bool = False,
-                 stream=None, single_stream: bool = False):
+                 stream=None, single_stream: bool = False, arena_bytes: int = 0):
         import torch
         self._lib = _lib.load()
         o = _lib.Opts()
@@ -65,6 +65,7 @@ class Handle:
         o.want_grad = 1 if want_grad else 0
         o.seed = int(seed)
         o.flags = (_lib.FLAG_STRICT_RANK if strict_rank else 0) | (_lib.FLAG_SINGLE_STREAM if single_stream else 0)
+        o.arena_bytes = int(arena_bytes)
         self.n, self.nb, self.mode = int(n), int(nb), mode
         self.nt = (self.n + self.nb - 1) // self.nb
         if stream is None:
@@ -151,6 +152,13 @@ class Handle:
         out = np.zeros(self.nt * self.nt, dtype=np.int32)
         st = self._lib.tlr_get_ranks(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self._check(st, "tlr_get_ranks")
+        return out.reshape(self.nt, self.nt)
+
+    def tangent_ranks(self) -> np.ndarray:
+        """Ranks of the tangent factor's tiles after loglik_grad (TLR)."""
+        out = np.zeros(self.nt * self.nt, dtype=np.int32)
+        st = self._lib.tlr_get_tangent_ranks(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self._check(st, "tlr_get_tangent_ranks")
         return out.reshape(self.nt, self.nt)
 
     def info(self) -> _lib.Info:

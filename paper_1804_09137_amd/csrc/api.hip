@@ -67,7 +67,6 @@ struct tlr_handle_s {
   double host_ms[4] = {0, 0, 0, 0};   // TLR_DEBUG: host time in the compressions' two waits and their callbacks
   bool multi = false;   // side and diagonal streams (TLR gradient handles without TLR_FLAG_SINGLE_STREAM)
   bool dense = false, grad = false, strict = false;
-  int64_t slot = 0;      // doubles per low-rank slot (nb * maxrank)
   int64_t vslot = 0;     // doubles per V~ staging block (nb * (maxrank + 1)): the
                          // truncating QR may produce maxrank + 1 columns before
                          // the tile is turned dense
@@ -92,16 +91,23 @@ struct tlr_handle_s {
   double* D = nullptr;    // TLR: diagonal tiles nt x (nb x nb)
   double* Dd = nullptr;   // TLR tangent diagonal tiles
   double* Dinv = nullptr; // both: inverses of the diagonal tiles (inside the arena for TLR)
-  // TLR off-diagonal tiles: L_ij = U V^T with U, V (ld nb) anywhere in one
-  // arena; family 0 is the factor, family 1 its tangent (gradient).  A
-  // low-rank tile uses its fixed slots; a tile whose rank would exceed
-  // maxrank is kept dense: U = the tile itself, V = Dinv_j (or the identity
+  // TLR off-diagonal tiles: L_ij = U V^T with U, V (ld nb) in one arena;
+  // family 0 is the factor, family 1 its tangent (gradient).  The arena
+  // holds the identity block, the inverses of the diagonal tiles, then the
+  // tile storage: each tile takes nb x k doubles for U and for V when its
+  // rank k is known (bump allocation, reset per factorisation), so the
+  // storage follows sum nb k_ij.  A tile whose rank would exceed maxrank is
+  // kept dense: U = the tile itself (nb x nb), V = Dinv_j (or the identity
   // for the compressed Sigma of tlr_compress), rank = tile width.
   double* arena = nullptr;
-  int64_t dinv_off = 0, ident_off = 0, dense_off = 0;
-  int64_t dense_cap = 0, dense_used = 0;
+  int64_t arena_len = 0;                 // doubles in the arena allocation
+  int64_t dinv_off = 0, ident_off = 0;
+  int64_t tile_off = 0, tile_cap = 0, tile_used = 0;   // tile storage: start, doubles, bump pointer
+  bool tile_auto = true;                 // opts.arena_bytes == 0: grow the storage when a factor needs more
+  bool tile_overflow = false;            // the last failure was the tile storage running out
+  int arena_grows = 0;
+  int splitk_count = 0;                  // split-K GEMM launches of the running factorisation
   struct Family {
-    int64_t u_base = 0, v_base = 0;      // arena offsets of the slot regions
     std::vector<int> rk;                 // nt*nt (i * nt + j)
     std::vector<int> r1;                 // range-finder ranks (sketch width prediction)
     std::vector<int> r1_prev, rk_prev;   // the previous factorisation's ranks, if hist
@@ -173,6 +179,12 @@ struct tlr_handle_s {
   int64_t gbuf_cap = 0;
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags
   int* qr_h = nullptr;
+  // FP32-product check (TLR_PREC_FP32_UPDATES handles): per diagonal tile j,
+  // chk[2j] = ||A_jj - D~_jj||_F^2 (the update that reached the tile) and
+  // chk[2j+1] = ||D_jj^{-1}||_F^2; chk_scr is one nb x nb scratch tile
+  double* chk_d = nullptr;
+  double* chk_h = nullptr;
+  double* chk_scr = nullptr;
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // per-kernel-class event timing (tlr_profile)
@@ -239,9 +251,6 @@ T* halloc(tlr_handle_s* h, int64_t count) {
 
 inline int tile_rows(const tlr_handle_s* h, int i) {
   return (i == h->nt - 1) ? (int)(h->n - (int64_t)i * h->nb) : h->nb;
-}
-inline int64_t slot_of(const tlr_handle_s* h, int i, int j) {  // i > j
-  return (int64_t)j * h->nt - (int64_t)j * (j + 1) / 2 + (i - j - 1);
 }
 inline double* dinv_tile(tlr_handle_s* h, int j) { return h->Dinv + (int64_t)j * h->nb * h->nb; }
 inline double* diag_tile(tlr_handle_s* h, int j) { return h->D + (int64_t)j * h->nb * h->nb; }
@@ -491,6 +500,7 @@ void gemm(tlr_handle_s* h, int64_t M, int64_t N, int nseg, const GemmSeg* segs, 
     for (int i = 0; i < nseg; ++i) K += segs[i].K;
     sk = choose_splitk(h, M, N, K);
   }
+  if (sk > 1) ++h->splitk_count;
   HIPCHK(launch_gemm(M, N, nseg, segs, C, ldc, ep, b, sk, sk > 1 ? h->skw : nullptr, h->s, tm, tn, tag));
 }
 
@@ -517,11 +527,8 @@ void family_reset(tlr_handle_s* h, Family& F, int kind) {
   std::fill(F.rk.begin(), F.rk.end(), 0);
   std::fill(F.r1.begin(), F.r1.end(), 0);
   std::fill(F.isdense.begin(), F.isdense.end(), 0);
-  for (int i = 0; i < h->nt; ++i)
-    for (int j = 0; j < i; ++j) {
-      F.uoff[tid_of(h, i, j)] = F.u_base + slot_of(h, i, j) * h->slot;
-      F.voff[tid_of(h, i, j)] = F.v_base + slot_of(h, i, j) * h->slot;
-    }
+  std::fill(F.uoff.begin(), F.uoff.end(), 0);
+  std::fill(F.voff.begin(), F.voff.end(), 0);
 }
 
 // device copies of the rank and offset tables (for the solves)
@@ -532,9 +539,46 @@ void family_upload(tlr_handle_s* h, Family& F) {
   HIPCHK(hipMemcpyAsync(F.voff_d, F.voff.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, h->s));
 }
 
-int64_t take_dense_block(tlr_handle_s* h) {
-  if (h->dense_used >= h->dense_cap) NOMEM("dense tile pool");
-  return h->dense_off + (h->dense_used++) * (int64_t)h->nb * h->nb;
+// (Re)allocate the TLR arena: identity block, inverses of the diagonal
+// tiles, then cap doubles of tile storage.  The previous arena (if any) is
+// freed first; its contents are not kept (a factorisation starts afresh).
+void arena_alloc(tlr_handle_s* h, int64_t cap) {
+  const int64_t nb = h->nb, nt = h->nt;
+  if (h->arena) {
+    sync(h);
+    (void)hipFree(h->arena);
+    h->bytes -= h->arena_len * (int64_t)sizeof(double);
+    h->arena = nullptr;
+    h->Dinv = nullptr;
+  }
+  h->ident_off = 0;
+  h->dinv_off = pad16(nb * nb);
+  h->tile_off = h->dinv_off + pad16(nt * nb * nb);
+  h->tile_cap = std::max<int64_t>(cap, 0) / kAlign * kAlign;
+  h->arena_len = h->tile_off + h->tile_cap;
+  void* p = nullptr;
+  if (hipMalloc(&p, (size_t)h->arena_len * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{TLR_ENOMEM};
+  }
+  h->arena = (double*)p;
+  h->bytes += h->arena_len * (int64_t)sizeof(double);
+  h->Dinv = h->arena + h->dinv_off;
+  h->tile_used = 0;
+  HIPCHK(launch_fill(h->arena + h->ident_off, nb, nb, nb, 0.0, h->s));
+  HIPCHK(launch_identity(h->arena + h->ident_off, nb, nb, h->s));
+}
+
+// nd doubles of tile storage (128-byte aligned); TLR_ENOMEM when the arena is full
+int64_t tile_take(tlr_handle_s* h, int64_t nd) {
+  const int64_t a = pad16(nd);
+  if (h->tile_used + a > h->tile_cap) {
+    h->tile_overflow = true;
+    NOMEM("tile storage (tlr_opts.arena_bytes)");
+  }
+  const int64_t off = h->tile_off + h->tile_used;
+  h->tile_used += a;
+  return off;
 }
 
 void throw_if_not_spd(tlr_handle_s* h) {
@@ -1082,13 +1126,13 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     F.r1[id] = t1[g];
     if (dense[g]) {
       F.rk[id] = ncols;
-      F.uoff[id] = take_dense_block(h);
+      F.uoff[id] = tile_take(h, (int64_t)nb * ncols);
       F.voff[id] = jb.dense_voff;
       ++ndense;
     } else {
       F.rk[id] = k2[g];
-      F.uoff[id] = F.u_base + slot_of(h, i, jb.col) * h->slot;
-      F.voff[id] = F.v_base + slot_of(h, i, jb.col) * h->slot;
+      F.uoff[id] = k2[g] > 0 ? tile_take(h, (int64_t)nb * k2[g]) : 0;
+      F.voff[id] = k2[g] > 0 ? tile_take(h, (int64_t)nb * k2[g]) : 0;
       maxk = std::max(maxk, k2[g]);
       if (k2[g] > 0) ++nlr;
     }
@@ -1699,12 +1743,58 @@ RankPred predict_ranks(const tlr_handle_s* h, const Family& F, int j, int T) {
 // only the primal columns <= j and the tangent columns < j), and their tiles
 // share the compression launches: half as many serial launch groups, twice
 // as many tiles per launch.
+// FP32-product check.  The rounding of the FP32 update products perturbs
+// Sigma by E; to first order log|Sigma| moves by tr(Sigma^{-1} E), and the
+// part of it that lands on diagonal tile j is bounded by
+// ||D_jj^{-1}||_F ||E_jj||_F, with D_jj = L_jj L_jj^T the tile's Schur
+// complement and ||E_jj||_F about u32 ||A_jj - D~_jj||_F (u32 = 2^-24, the
+// update being A_jj - D~_jj).  eta = u32 sum_j ||A_jj - D~_jj||_F ||D_jj^{-1}||_F
+// is the estimate compared with the log-likelihood's tolerance.  Measured on
+// CPU simulations of FP32-rounded updates over Matérn fields (n 1,600-6,400,
+// condition 1e1-1e6) it exceeded the actual log-likelihood change by 2x on the
+// worst-conditioned field and by up to 175x on well-conditioned ones.
+void fp32_check_update(tlr_handle_s* h, int j) {
+  const int nb = h->nb, nbj = tile_rows(h, j);
+  HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)j * nb, nbj, (int64_t)j * nb, nbj, h->chk_scr, nb, false,
+                             h->s));
+  HIPCHK(launch_sqdiff_acc(h->chk_scr, nb, diag_tile(h, j), nb, nbj, nbj, h->chk_d + 2 * j, h->s));
+}
+void fp32_check_inverse(tlr_handle_s* h, int j) {
+  const int nb = h->nb, nbj = tile_rows(h, j);
+  // D_jj^{-1} = L_jj^{-T} L_jj^{-1}
+  GemmSeg sg{};
+  sg.A = op_contigT(dinv_tile(h, j), nb, 0, 0);
+  sg.B = op_contigT(dinv_tile(h, j), nb, 0, 0);
+  sg.K = nbj;
+  gemm(h, nbj, nbj, 1, &sg, h->chk_scr, nb, epi_linear(1.0, 0.0));
+  HIPCHK(launch_sqdiff_acc(h->chk_scr, nb, nullptr, 0, nbj, nbj, h->chk_d + 2 * j + 1, h->s));
+}
+// After a log-likelihood ll from a factor with FP32 products: eta (above)
+// relative to |ll| goes to info.fp32_err_bound; true when eta exceeds half of
+// the 10 tol |ll| accuracy target, i.e. the factor must be computed again
+// with FP64 products.
+bool fp32_check_fails(tlr_handle_s* h, double ll) {
+  if (h->upd_tag != 2) {
+    h->info.fp32_err_bound = 0.0;
+    return false;
+  }
+  HIPCHK(hipMemcpyAsync(h->chk_h, h->chk_d, 2 * (size_t)h->nt * sizeof(double), hipMemcpyDeviceToHost, h->s_main));
+  sync(h);
+  double eta = 0.0;
+  for (int j = 0; j < h->nt; ++j) eta += std::sqrt(h->chk_h[2 * j]) * std::sqrt(h->chk_h[2 * j + 1]);
+  eta *= std::ldexp(1.0, -24);
+  h->info.fp32_err_bound = eta / std::max(std::fabs(ll), 1e-300);
+  return !(eta <= 5.0 * h->o.tol * std::fabs(ll));
+}
+
 void factor_tlr(tlr_handle_s* h, bool tangent) {
   const int nt = h->nt, nb = h->nb;
   reset_info(h);
+  if (h->upd_tag == 2) HIPCHK(launch_fill(h->chk_d, 2 * nt, 2 * nt, 1, 0.0, h->s));
   family_reset(h, h->fam[0], 1);
   family_reset(h, h->fam[1], 1);
-  h->dense_used = 0;
+  h->tile_used = 0;
+  h->tile_overflow = false;
   sync(h);
   meta_reset(h);
   h->im2_use = h->lm2_use = 0;   // the side stream's staging set (idle after the sync)
@@ -1726,7 +1816,9 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     const int nbj = tile_rows(h, j);
     const size_t e_d = prof_mark(h);
     HIPCHK(launch_copy_block(pbuf(j), h->n, diag_tile(h, j), nb, nbj, nbj, h->s));
+    if (h->upd_tag == 2) fp32_check_update(h, j);
     HIPCHK(tile_potrf_inv(diag_tile(h, j), nb, nbj, dinv_tile(h, j), nb, h->info_d, (int64_t)j * nb, h->tw, h->s));
+    if (h->upd_tag == 2) fp32_check_inverse(h, j);
     HIPCHK(launch_logdiag(diag_tile(h, j), nb, nbj, h->scal + j, h->s));
     prof_add(h, TLR_K_DIAG, e_d, 2.0 / 3.0 * nbj * (double)nbj * nbj, 16.0 * nbj * (double)nbj);
   };
@@ -2121,16 +2213,31 @@ tlr_status check_info(tlr_handle_s* h, int64_t* info) {
 // products, and the info counters record it.  The handle keeps FP64 products
 // from then on: its later calls (nearby theta of the same field) would most
 // likely fail the same way and pay for two factorisations.
+// Automatic tile storage (opts.arena_bytes == 0) that ran out: twice the
+// capacity, and the caller starts the pass again.
+void arena_grow(tlr_handle_s* h) {
+  h->s = h->s_main;   // an interrupted pass may have left a side stream current
+  h->tile_overflow = false;
+  ++h->arena_grows;
+  arena_alloc(h, 2 * h->tile_cap);
+}
+
 tlr_status factor_checked(tlr_handle_s* h, bool tangent, int64_t* info) {
   const bool f32 = h->o.prec == TLR_PREC_FP32_UPDATES && h->info.fp64_retries == 0;
   h->upd_tag = f32 ? 2 : 1;
   h->info.prec_used = f32 ? TLR_PREC_FP32_UPDATES : TLR_PREC_FP64;
   for (;;) {
     tlr_status st;
+    h->splitk_count = 0;
     try {
       if (h->dense) factor_dense(h, tangent); else factor_tlr(h, tangent);
       st = check_info(h, info);
+      h->info.splitk_launches = h->splitk_count;
     } catch (const Fail& f) {
+      if (f.st == TLR_ENOMEM && h->tile_overflow && h->tile_auto) {
+        arena_grow(h);
+        continue;
+      }
       if (f.st != TLR_ENOTSPD) throw;
       st = check_info(h, info);
     }
@@ -2158,6 +2265,10 @@ void rank_stats(tlr_handle_s* h) {
   h->info.rank_sum = sum;
   h->info.rank_max = mx;
   h->info.dense_tiles = nd;
+  h->info.tile_bytes_used = h->tile_used * (int64_t)sizeof(double);
+  h->info.tile_bytes_cap = h->tile_cap * (int64_t)sizeof(double);
+  h->info.arena_grows = h->arena_grows;
+  h->info.device_bytes = h->bytes;
 }
 
 template <class F>
@@ -2194,6 +2305,8 @@ void free_all(tlr_handle_s* h) {
     *e = nullptr;
   }
   for (void* p : h->dev_allocs) (void)hipFree(p);
+  if (h->arena) (void)hipFree(h->arena);
+  h->arena = nullptr;
   for (void* p : h->host_allocs) (void)hipHostFree(p);
   for (hipEvent_t& e : h->ev)
     if (e) (void)hipEventDestroy(e);
@@ -2229,6 +2342,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
   if (o->prec != TLR_PREC_FP64 && o->prec != TLR_PREC_FP32_UPDATES) return TLR_EINVAL;
   if (o->mode == TLR_MODE_TLR && !(o->tol > 0.0 && std::isfinite(o->tol))) return TLR_EINVAL;
   if (o->prec == TLR_PREC_FP32_UPDATES && o->mode != TLR_MODE_TLR) return TLR_EINVAL;
+  if (o->arena_bytes < 0) return TLR_EINVAL;
   tlr_handle_s* h = new (std::nothrow) tlr_handle_s();
   if (!h) return TLR_ENOMEM;
   tlr_status st = guarded(h, [&]() -> tlr_status {
@@ -2253,7 +2367,6 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     // this is (unless strict) kept dense
     h->smax = (int)std::min<int64_t>(kQrMaxCols, pad16(mr + mr / 2 + 48));
     h->debug = std::getenv("TLR_DEBUG") != nullptr;
-    h->slot = (int64_t)o->nb * mslot;
     h->vslot = (int64_t)o->nb * (mslot + 1);
     h->ntiles = (int64_t)h->nt * (h->nt - 1) / 2;
     const int64_t n = h->n, nb = h->nb, nt = h->nt;
@@ -2275,7 +2388,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->h_scal = halloc<double>(h, 4 * nt + 16);
     h->info_d = dalloc<unsigned long long>(h, 1);
     h->h_info = halloc<unsigned long long>(h, 1);
-    h->sk_cap = std::min<int64_t>(64ll << 20, 32 * std::max<int64_t>(n, 1024) * nb);
+    h->sk_cap = std::min<int64_t>(16ll << 20, 32 * std::max<int64_t>(n, 1024) * nb);
     h->skw = dalloc<double>(h, h->sk_cap);
     if (h->dense) {
       h->Lp = dalloc<double>(h, panels_size(n, nb));
@@ -2293,19 +2406,24 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->D = dalloc<double>(h, nt * nb * nb);
       if (h->grad) h->Dd = dalloc<double>(h, nt * nb * nb);
       h->lrtws = dalloc<double>(h, nt * (int64_t)kLrMaxRank);
-      // arena: [U0 | V0 | U1 | V1] slots, dense blocks, identity, Dinv tiles
+      // arena: identity, Dinv tiles, tile storage.  Explicit arena_bytes:
+      // that much tile storage, fixed.  Otherwise room for every tile of
+      // every family at rank max(12, maxrank / 16) plus one dense tile per
+      // tile column, grown (doubled) when a factorisation needs more.
       const int nfam = h->grad ? 2 : 1;
-      const int64_t nslots = std::max<int64_t>(h->ntiles, 1);
-      // dense-tile pool: every tile when that fits in 24 GB, else as many blocks
-      const int64_t pool_budget = (24ll << 30) / (8 * nb * nb);
-      h->dense_cap = std::max<int64_t>(16, std::min<int64_t>(h->ntiles * nfam, pool_budget));
-      int64_t cur = 0;
+      int64_t cap;
+      if (o->arena_bytes > 0) {
+        h->tile_auto = false;
+        cap = o->arena_bytes / (int64_t)sizeof(double);
+      } else {
+        const int64_t rg = std::max<int64_t>(12, mr / 16);
+        cap = nfam * (h->ntiles * 2 * nb * pad16(rg) + nt * nb * nb);
+        // TLR_ARENA_START (doubles) lowers the first automatic capacity, so
+        // that tests reach the doubling
+        if (const char* as = std::getenv("TLR_ARENA_START")) cap = std::min<int64_t>(cap, std::atoll(as));
+      }
       for (int f = 0; f < 2; ++f) {
         Family& F = h->fam[f];
-        if (f < nfam) {
-          F.u_base = cur; cur += nslots * h->slot;
-          F.v_base = cur; cur += nslots * h->slot;
-        }
         F.rk.assign((size_t)nt * nt, 0);
         F.r1.assign((size_t)nt * nt, 0);
         F.r1_prev.assign((size_t)nt * nt, 0);
@@ -2317,13 +2435,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         F.uoff_d = dalloc<int64_t>(h, nt * nt);
         F.voff_d = dalloc<int64_t>(h, nt * nt);
       }
-      h->dense_off = cur; cur += h->dense_cap * nb * nb;
-      h->ident_off = cur; cur += nb * nb;
-      h->dinv_off = cur; cur += nt * nb * nb;
-      h->arena = dalloc<double>(h, cur);
-      h->Dinv = h->arena + h->dinv_off;
-      HIPCHK(launch_fill(h->arena + h->ident_off, nb, nb, nb, 0.0, h->s));
-      HIPCHK(launch_identity(h->arena + h->ident_off, nb, nb, h->s));
+      arena_alloc(h, cap);
       if (h->grad) {
         h->ptmp_cap = nt * nb * nb;
         h->Ptmp = dalloc<double>(h, h->ptmp_cap);
@@ -2336,17 +2448,21 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       h->Bt = dalloc<double>(h, gc * nb * h->smax);
       h->Vtmp = dalloc<double>(h, gc * h->vslot);
       h->Zb = dalloc<double>(h, gc * h->smax * (mslot + 1));
-      // a row of tiles may hold dense tiles (width nb) in every slot
-      const int64_t rmax = nterms * nt * nb;
+      // the right factors of one row of tiles, side by side: up to rmax
+      // columns, the ranks of a row averaging up to maxrank / 2 (a dense
+      // tile counts nb); a row needing more fails with TLR_ENOMEM
+      const int64_t rmax = std::min<int64_t>(nterms * nt * nb, nterms * nt * std::max(mr / 2, 16) + 4 * nb);
       h->urow_cap = nb * rmax;
       h->Urow = dalloc<double>(h, h->urow_cap);
+      // W (rows below the diagonal x row rank sum) and the X = V^T V blocks
+      // are taken in chunks of tile rows that fit these capacities
       int64_t wworst = 0, xworst = 0;
       for (int64_t j = 0; j < nt; ++j) {
         wworst = std::max(wworst, (nt - j) * nb * nterms * j * nb);
         xworst = std::max(xworst, (nt - j) * nterms * j * nb * nb);
       }
-      h->w_cap = std::max<int64_t>(std::min<int64_t>(wworst, 512ll << 20), nb * rmax);
-      h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 256ll << 20), (int64_t)nterms * nt * nb * nb);
+      h->w_cap = std::max<int64_t>(std::min<int64_t>(wworst, 160ll << 20), nb * rmax);
+      h->x_cap = std::max<int64_t>(std::min<int64_t>(xworst, 64ll << 20), nb * rmax);
       h->Wb = dalloc<double>(h, h->w_cap);
       h->Xb = dalloc<double>(h, h->x_cap);
       if (h->multi) {
@@ -2405,6 +2521,11 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       }
       h->qr_d = dalloc<int>(h, 2 * gc);
       h->qr_h = halloc<int>(h, 2 * gc);
+      if (o->prec == TLR_PREC_FP32_UPDATES) {
+        h->chk_d = dalloc<double>(h, 2 * nt);
+        h->chk_h = halloc<double>(h, 2 * nt);
+        h->chk_scr = dalloc<double>(h, nb * nb);
+      }
       HIPCHK(launch_gaussian(h->omega, nb * h->smax, (uint32_t)o->seed, h->s));
     }
     for (hipEvent_t& e : h->ev) HIPCHK(hipEventCreate(&e));
@@ -2453,16 +2574,37 @@ tlr_status tlr_generate(tlr_handle_t h, const double* d_x, const double* d_y, co
   });
 }
 
+namespace {
+void compress_sigma(tlr_handle_s* h);
+}
+
 tlr_status tlr_compress(tlr_handle_t h) {
   if (!h) return TLR_EINVAL;
   if (h->dense) return TLR_ENOTIMPL;
   if (!h->bound) return TLR_ESTATE;
   return guarded(h, [&]() -> tlr_status {
+    for (;;) {
+      try {
+        compress_sigma(h);
+        return TLR_OK;
+      } catch (const Fail& f) {
+        if (!(f.st == TLR_ENOMEM && h->tile_overflow && h->tile_auto)) throw;
+        arena_grow(h);
+      }
+    }
+  });
+}
+
+namespace {
+// tlr_compress: every strictly-lower tile of Sigma compressed (no factorisation)
+void compress_sigma(tlr_handle_s* h) {
+  {
     prof_reset_pool(h);
     const int nt = h->nt, nb = h->nb;
     Family& F = h->fam[0];
     family_reset(h, F, 2);
-    h->dense_used = 0;
+    h->tile_used = 0;
+    h->tile_overflow = false;
     reset_info(h);
     sync(h);
     meta_reset(h);
@@ -2513,9 +2655,9 @@ tlr_status tlr_compress(tlr_handle_t h) {
     F.done_kind = 2;
     rank_stats(h);
     h->state = 1;
-    return TLR_OK;
-  });
+  }
 }
+}  // namespace
 
 tlr_status tlr_potrf(tlr_handle_t h, int64_t* info) {
   if (!h) return TLR_EINVAL;
@@ -2540,14 +2682,24 @@ tlr_status tlr_loglik(tlr_handle_t h, const double* d_z, double* ll, double* log
   if (!h || !d_z) return TLR_EINVAL;
   if (h->state < 2) return TLR_ESTATE;
   return guarded(h, [&]() -> tlr_status {
-    double ld = 0.0, q = 0.0;
-    HIPCHK(hipEventRecord(h->ev[2], h->s));
-    solve_forward(h, d_z, &ld, &q);
-    HIPCHK(hipEventRecord(h->ev[3], h->s));
-    sync(h);
-    h->info.t_solve_ms = elapsed(h->ev[2], h->ev[3]);
+    double ld = 0.0, q = 0.0, l = 0.0;
     const double n = (double)h->n;
-    if (ll) *ll = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * ld - 0.5 * q;
+    for (;;) {
+      HIPCHK(hipEventRecord(h->ev[2], h->s));
+      solve_forward(h, d_z, &ld, &q);
+      HIPCHK(hipEventRecord(h->ev[3], h->s));
+      sync(h);
+      h->info.t_solve_ms = elapsed(h->ev[2], h->ev[3]);
+      l = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * ld - 0.5 * q;
+      if (h->state != 2 || !fp32_check_fails(h, l)) break;
+      // the FP32 products cannot be shown to hold the tolerance: factor again in FP64
+      ++h->info.fp64_retries;
+      int64_t info = 0;
+      const tlr_status st = factor_checked(h, false, &info);
+      if (st != TLR_OK) return st;
+      if (!h->dense) rank_stats(h);
+    }
+    if (ll) *ll = l;
     if (logdet) *logdet = ld;
     if (quad) *quad = q;
     return TLR_OK;
@@ -2610,6 +2762,13 @@ tlr_status tlr_get_ranks(tlr_handle_t h, int32_t* host_ranks) {
   return TLR_OK;
 }
 
+tlr_status tlr_get_tangent_ranks(tlr_handle_t h, int32_t* host_ranks) {
+  if (!h || !host_ranks) return TLR_EINVAL;
+  if (!h->grad) return TLR_ESTATE;
+  for (size_t i = 0; i < (size_t)h->nt * h->nt; ++i) host_ranks[i] = h->dense ? 0 : h->fam[1].rk[i];
+  return TLR_OK;
+}
+
 tlr_status tlr_get_info(tlr_handle_t h, tlr_info* out) {
   if (!h || !out) return TLR_EINVAL;
   *out = h->info;
@@ -2663,22 +2822,30 @@ extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const d
   tlr_status st = tlr_generate(h, d_x, d_y, theta);
   if (st != TLR_OK) return st;
   return guarded(h, [&]() -> tlr_status {
-    prof_reset_pool(h);
-    h->state = 0;
-    HIPCHK(hipEventRecord(h->ev[0], h->s));
-    const tlr_status fst = factor_checked(h, true, info);
-    if (fst != TLR_OK) return fst;
-    HIPCHK(hipEventRecord(h->ev[1], h->s));
-    sync(h);
-    h->info.t_factor_ms = elapsed(h->ev[0], h->ev[1]);
-    if (!h->dense) rank_stats(h);
-    h->state = 3;
     double ld = 0.0, q = 0.0;
-    HIPCHK(hipEventRecord(h->ev[2], h->s));
-    const size_t e_s = prof_mark(h);
-    solve_forward(h, d_z, &ld, &q);
-    solve_backward(h);
-    prof_add(h, TLR_K_SOLVE, e_s, 0.0, 0.0);
+    const double n = (double)h->n;
+    for (;;) {
+      prof_reset_pool(h);
+      h->state = 0;
+      HIPCHK(hipEventRecord(h->ev[0], h->s));
+      const tlr_status fst = factor_checked(h, true, info);
+      if (fst != TLR_OK) return fst;
+      HIPCHK(hipEventRecord(h->ev[1], h->s));
+      sync(h);
+      h->info.t_factor_ms = elapsed(h->ev[0], h->ev[1]);
+      if (!h->dense) rank_stats(h);
+      h->state = 3;
+      HIPCHK(hipEventRecord(h->ev[2], h->s));
+      const size_t e_s = prof_mark(h);
+      solve_forward(h, d_z, &ld, &q);
+      if (!fp32_check_fails(h, -0.5 * n * std::log(2.0 * M_PI) - 0.5 * ld - 0.5 * q)) {
+        solve_backward(h);
+        prof_add(h, TLR_K_SOLVE, e_s, 0.0, 0.0);
+        break;
+      }
+      // the FP32 products cannot be shown to hold the tolerance: factor again in FP64
+      ++h->info.fp64_retries;
+    }
     HIPCHK(hipEventRecord(h->ev[3], h->s));
     const size_t e_q = prof_mark(h);
     // a^T dSigma/dbeta a over all pairs; partial sums in the split-K workspace
@@ -2694,7 +2861,6 @@ extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const d
     double trace = 0.0;
     for (int j = 0; j < h->nt; ++j) trace += h->h_scal[h->nt + j];
     const double qf = h->h_scal[2 * h->nt + 1];
-    const double n = (double)h->n;
     if (ll) *ll = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * ld - 0.5 * q;
     grad[0] = (q - n) / (2.0 * h->theta[0]);
     grad[1] = -0.5 * trace + 0.5 * qf;

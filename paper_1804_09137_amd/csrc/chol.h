@@ -16,6 +16,9 @@ hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t k, con
                          double beta, double* y, hipStream_t s);
 hipError_t launch_fill(double* A, int64_t lda, int64_t m, int64_t ncol, double value, hipStream_t s);
 hipError_t launch_identity(double* A, int64_t lda, int64_t m, hipStream_t s);
+// *acc += sum (A - B)^2 over the m x ncol block (B null: sum A^2); acc is device memory
+hipError_t launch_sqdiff_acc(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t m, int64_t ncol,
+                             double* acc, hipStream_t s);
 hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s);
 
 // Lower Cholesky of the m x m tile T (column-major, ld) in place, blocked

@@ -233,6 +233,34 @@ __global__ void __launch_bounds__(256) dot_kernel(const double* __restrict__ a, 
   if (threadIdx.x == 0) *out = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
+// *acc += sum of (A - B)^2 over an m x ncol block (B null: sum of A^2), both
+// column-major.  Grid-stride over the elements, one atomic add per workgroup.
+__global__ void __launch_bounds__(256) sqdiff_acc_kernel(const double* __restrict__ A, int64_t lda,
+                                                         const double* __restrict__ B, int64_t ldb, int64_t m,
+                                                         int64_t ncol, double* acc) {
+  __shared__ double part[4];
+  const int64_t tot = m * ncol;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t c = e / m, r = e - c * m;
+    double d = A[c * lda + r];
+    if (B) d -= B[c * ldb + r];
+    s += d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(acc, (part[0] + part[1]) + (part[2] + part[3]));
+}
+
+hipError_t launch_sqdiff_acc(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t m, int64_t ncol,
+                             double* acc, hipStream_t s) {
+  if (m <= 0 || ncol <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(128, (m * ncol + 255) / 256);
+  hipLaunchKernelGGL(sqdiff_acc_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, B, ldb, m, ncol, acc);
+  return hipGetLastError();
+}
+
 hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s) {
   hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(256), 0, s, a, b, m, out);
   return hipGetLastError();
