@@ -75,6 +75,13 @@ typedef enum {
                                  tlr_sample and tlr_get_tile see the FP32-product factor */
 } tlr_prec;
 
+typedef enum {
+  TLR_METRIC_EUCLID = 0,       /* ||s_a - s_b||_2 of planar coordinates (x, y) */
+  TLR_METRIC_GREAT_CIRCLE = 1  /* great-circle distance on a sphere, Eq. (gcd) (the haversine
+                                  formula): x = longitude, y = latitude, both in degrees;
+                                  d = 2 r asin(sqrt(hav(dlat) + cos lat_a cos lat_b hav(dlon))) */
+} tlr_metric;
+
 /* tlr_opts.flags */
 #define TLR_FLAG_STRICT_RANK 1  /* a tile needing rank > maxrank is an error (TLR_ERANK) instead of
                                    being kept dense */
@@ -99,7 +106,7 @@ typedef struct {
   int32_t want_grad;  /* non-zero: also allocate what tlr_loglik_grad needs */
   int32_t seed;       /* seed of the Gaussian sketch matrix used by TLR compression */
   int32_t flags;      /* TLR_FLAG_* */
-  int32_t reserved;   /* must be 0 */
+  int32_t metric;     /* tlr_metric: distance between locations (Section IV) */
   int64_t arena_bytes; /* TLR: device bytes for the storage of the off-diagonal tiles (U and V of
                           each low-rank tile at its rank, nb x nb for a dense one; the factor and,
                           with want_grad, its tangent).  > 0: exactly that much, allocated by
@@ -108,6 +115,8 @@ typedef struct {
                           max(16, maxrank / 8) plus two dense tiles per tile column, and doubled
                           (reallocated, the pass started again) whenever a pass needs more.
                           < 0: TLR_EINVAL.  Ignored in DENSE mode */
+  double sphere_radius; /* TLR_METRIC_GREAT_CIRCLE: radius of the sphere, in the unit of the
+                          distances (and of beta); 0 selects 6371 (the Earth's mean radius in km) */
 } tlr_opts;
 
 typedef struct {
@@ -195,6 +204,20 @@ tlr_status tlr_loglik(tlr_handle_t h, const double* d_z, double* ll, double* log
  * dSigma/dbeta entries.  Requires opts.want_grad.  info as in tlr_potrf. */
 tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
                            const double theta[3], double* ll, double grad[2], int64_t* info);
+
+/* Kriging prediction (Section III, Eq. (pred3)), after tlr_potrf of Sigma_22
+ * (the handle's bound locations s_1..s_n, theta and metric):
+ *   d_pred[i] = (Sigma_12 Sigma_22^{-1} z)_i,  i < m,
+ * with z = d_z (n observed values, caller's point order, zero mean) and
+ * Sigma_12[i, b] = C(d(snew_i, s_b); theta) for the m new locations
+ * (d_xnew[i], d_ynew[i]) (device, m each; any order).  Sigma_22^{-1} z is
+ * computed by the forward and backward solves over the (dense or TLR)
+ * factor; Sigma_12 is generated on the fly.  d_var (may be NULL): the
+ * conditional variances of Eq. (pred2), C(0) - Sigma_12 Sigma_22^{-1} Sigma_21
+ * on the diagonal, one forward solve per new location.  0 <= m <= 65535
+ * (else TLR_EINVAL); TLR_ESTATE before tlr_potrf.  Synchronises the stream. */
+tlr_status tlr_predict(tlr_handle_t h, const double* d_z, int64_t m, const double* d_xnew, const double* d_ynew,
+                       double* d_pred, double* d_var);
 
 /* After tlr_potrf: d_z = L d_eps (the factor of Sigma(theta) times a caller
  * vector), e.g. a synthetic measurement vector z ~ N(0, Sigma) from

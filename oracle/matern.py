@@ -43,26 +43,55 @@ def dmatern_dbeta(r, sigma2: float, beta: float, nu: float) -> np.ndarray:
     return out
 
 
-def distances(xa, ya, xb, yb) -> np.ndarray:
-    """Euclidean distance matrix r[a, b] = ||s_a - s_b|| (Section IV)."""
-    dx = np.subtract.outer(np.asarray(xa, float), np.asarray(xb, float))
-    dy = np.subtract.outer(np.asarray(ya, float), np.asarray(yb, float))
-    return np.sqrt(dx * dx + dy * dy)
+EARTH_RADIUS_KM = 6371.0
 
 
-def covariance(x, y, theta, rows=None, cols=None) -> np.ndarray:
-    """Sigma(theta)[rows, cols] with Sigma_ab = C(||s_a - s_b||; theta) (Section III)."""
+def distances(xa, ya, xb, yb, metric: str = "euclid", radius: float = EARTH_RADIUS_KM) -> np.ndarray:
+    """Distance matrix r[a, b] between locations (Section IV).
+
+    "euclid": ||s_a - s_b||_2.  "great_circle": Eq. (gcd), the haversine
+    formula, with x the longitude and y the latitude in degrees:
+    hav(d / r) = hav(phi_b - phi_a) + cos(phi_a) cos(phi_b) hav(lam_b - lam_a),
+    hav(t) = sin^2(t / 2), solved for d = 2 r arcsin(sqrt(hav(d / r))).
+    """
+    xa, ya, xb, yb = (np.asarray(v, float) for v in (xa, ya, xb, yb))
+    if metric == "euclid":
+        dx = np.subtract.outer(xa, xb)
+        dy = np.subtract.outer(ya, yb)
+        return np.sqrt(dx * dx + dy * dy)
+    if metric != "great_circle":
+        raise ValueError(metric)
+    phi_a, phi_b = np.radians(ya), np.radians(yb)
+    lam_a, lam_b = np.radians(xa), np.radians(xb)
+
+    def hav(t):
+        return np.sin(t / 2.0) ** 2
+
+    h = hav(np.subtract.outer(phi_b, phi_a).T) + np.outer(np.cos(phi_a), np.cos(phi_b)) * hav(
+        np.subtract.outer(lam_b, lam_a).T)
+    return 2.0 * radius * np.arcsin(np.sqrt(np.clip(h, 0.0, 1.0)))
+
+
+def covariance(x, y, theta, rows=None, cols=None, metric: str = "euclid",
+               radius: float = EARTH_RADIUS_KM) -> np.ndarray:
+    """Sigma(theta)[rows, cols] with Sigma_ab = C(d(s_a, s_b); theta) (Section III)."""
     x = np.asarray(x, float)
     y = np.asarray(y, float)
     ra = slice(None) if rows is None else rows
     cb = slice(None) if cols is None else cols
-    return matern(distances(x[ra], y[ra], x[cb], y[cb]), *theta)
+    return matern(distances(x[ra], y[ra], x[cb], y[cb], metric, radius), *theta)
 
 
-def covariance_dbeta(x, y, theta, rows=None, cols=None) -> np.ndarray:
+def covariance_dbeta(x, y, theta, rows=None, cols=None, metric: str = "euclid",
+                     radius: float = EARTH_RADIUS_KM) -> np.ndarray:
     """dSigma/dbeta[rows, cols], entry-wise dC/dbeta."""
     x = np.asarray(x, float)
     y = np.asarray(y, float)
     ra = slice(None) if rows is None else rows
     cb = slice(None) if cols is None else cols
-    return dmatern_dbeta(distances(x[ra], y[ra], x[cb], y[cb]), *theta)
+    return dmatern_dbeta(distances(x[ra], y[ra], x[cb], y[cb], metric, radius), *theta)
+
+
+def cross_covariance(xa, ya, xb, yb, theta, metric: str = "euclid", radius: float = EARTH_RADIUS_KM):
+    """C(d(a_i, b_j); theta) between two location sets (Sigma_12 of Section III)."""
+    return matern(distances(xa, ya, xb, yb, metric, radius), *theta)

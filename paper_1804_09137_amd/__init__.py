@@ -55,7 +55,8 @@ class Handle:
 
     def __init__(self, n: int, nb: int, tol: float = 1e-9, maxrank: int = 0, mode: str = "tlr",
                  prec: str = "fp64", want_grad: bool = False, seed: int = 0, strict_rank: bool = False,
-                 stream=None, single_stream: bool = False, arena_bytes: int = 0):
+                 stream=None, single_stream: bool = False, arena_bytes: int = 0, metric: str = "euclid",
+                 sphere_radius: float = 0.0):
         import torch
         self._lib = _lib.load()
         o = _lib.Opts()
@@ -66,6 +67,8 @@ class Handle:
         o.seed = int(seed)
         o.flags = (_lib.FLAG_STRICT_RANK if strict_rank else 0) | (_lib.FLAG_SINGLE_STREAM if single_stream else 0)
         o.arena_bytes = int(arena_bytes)
+        o.metric = {"euclid": 0, "great_circle": 1}[metric]
+        o.sphere_radius = float(sphere_radius)
         self.n, self.nb, self.mode = int(n), int(nb), mode
         self.nt = (self.n + self.nb - 1) // self.nb
         if stream is None:
@@ -127,6 +130,19 @@ class Handle:
         self._check(st, "tlr_loglik_grad", info.value)
         self._keep = (x, y)
         return ll.value, (g[0], g[1])
+
+    def predict(self, z, xnew, ynew, variance: bool = False):
+        """Kriging prediction at (xnew, ynew) from the observed z (after
+        potrf): Sigma_12 Sigma_22^{-1} z, and the conditional variances if
+        asked (Section III)."""
+        import torch
+        m = int(xnew.shape[0])
+        pred = torch.empty(m, dtype=torch.float64, device="cuda")
+        var = torch.empty(m, dtype=torch.float64, device="cuda") if variance else None
+        st = self._lib.tlr_predict(self._h, _ptr(z), m, _ptr(xnew), _ptr(ynew), _ptr(pred),
+                                   _ptr(var) if variance else ctypes.c_void_p())
+        self._check(st, "tlr_predict")
+        return (pred, var) if variance else pred
 
     def sample(self, eps):
         """z = L eps with the current factor (after potrf)."""

@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libtlrmle.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 HIP_SOURCES = ["matern.hip", "gemm.hip", "chol.hip", "tile_chol.hip", "compress.hip", "hqr.hip", "solve.hip",
-               "grad.hip", "api.hip"]
+               "grad.hip", "factor.hip", "api.hip",
+               "predict.hip"]
 CPP_SOURCES = ["morton.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -16,6 +16,11 @@ constexpr int kWave = 64;
 // ----------------------------------------------------------------------------
 enum MaternKind : int { kNuHalf = 0, kNuThreeHalves = 1, kNuFiveHalves = 2, kNuGeneral = 3 };
 
+// Distance between locations (Section IV): Euclidean in the plane, or the
+// great-circle distance of Eq. (gcd) (haversine formula) for (longitude,
+// latitude) in degrees on a sphere of radius `radius`.
+enum Metric : int { kMetricEuclid = 0, kMetricGreatCircle = 1 };
+
 constexpr int kTemmeTerms = 40;     // Temme series length cap (x <= 2 needs < 20)
 constexpr int kTrapBuckets = 9;     // trapezoid buckets in x (x > 2)
 constexpr int kTrapTerms = 32;      // nodes per bucket cap (needs <= 27)
@@ -41,6 +46,8 @@ struct MaternParams {
   double trap_h[kTrapBuckets];
   int trap_n[kTrapBuckets];
   const double* tab;    // device tables (kTabSize doubles), general nu only
+  int metric;           // Metric
+  double radius;        // kMetricGreatCircle: sphere radius (distance unit)
 };
 
 // Host: fill p for theta = (sigma2, beta, nu); writes the kTabSize-double table

@@ -124,7 +124,7 @@ __device__ inline void epi_store(const GemmEpi& ep, double* C, int64_t ldc, int6
     if (ep.beta != 0.0) o += ep.beta * (*c);
     *c = o;
   } else {
-    const double r = loc_dist(ep.x, ep.y, grow0 + m, ep.gcol0 + n);
+    const double r = loc_dist(ep.mp, ep.x, ep.y, grow0 + m, ep.gcol0 + n);
     double cv, dv;
     if (ep.kind == kEpiGenMinus) {
       matern_eval<false>(ep.mp, r, cv, dv);

@@ -48,9 +48,8 @@ __global__ void __launch_bounds__(256) pair_quad_kernel(MaternParams p, const do
     const int i = e % kPB, j = e / kPB;
     if (diag && i <= j) continue;
     if (r0 + i >= n || c0 + j >= n) continue;
-    const double dx = rx[i] - cx[j], dy = ry[i] - cy[j];
     double cv, dv;
-    matern_eval<true>(p, sqrt(dx * dx + dy * dy), cv, dv);
+    matern_eval<true>(p, point_dist(p, rx[i], ry[i], cx[j], cy[j]), cv, dv);
     s += ra[i] * ca[j] * dv;
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);

@@ -134,11 +134,27 @@ __device__ inline void matern_eval(const MaternParams& p, double r, double& c, d
   if (want_d) dc = p.norm * scale * u * knm * p.inv_beta;
 }
 
-__device__ inline double loc_dist(const double* __restrict__ x, const double* __restrict__ y,
-                                  int64_t a, int64_t b) {
-  const double dx = x[a] - x[b];
-  const double dy = y[a] - y[b];
+// Distance of two locations (Section IV).  Euclidean: sqrt(dx^2 + dy^2).
+// Great circle, Eq. (gcd): with phi the latitudes (y) and lambda the
+// longitudes (x) in radians, hav(d / r) = hav(phi_b - phi_a) +
+// cos(phi_a) cos(phi_b) hav(lambda_b - lambda_a), hav(t) = sin^2(t / 2), so
+// d = 2 r asin(sqrt(h)) (h clamped to 1 against rounding).
+__device__ inline double point_dist(const MaternParams& p, double xa, double ya, double xb, double yb) {
+  if (p.metric == kMetricGreatCircle) {
+    constexpr double kDeg = 3.14159265358979323846 / 180.0;
+    const double sp = sin(0.5 * kDeg * (yb - ya));
+    const double sl = sin(0.5 * kDeg * (xb - xa));
+    const double h = sp * sp + cos(kDeg * ya) * cos(kDeg * yb) * (sl * sl);
+    return 2.0 * p.radius * asin(sqrt(h < 1.0 ? h : 1.0));
+  }
+  const double dx = xa - xb;
+  const double dy = ya - yb;
   return sqrt(dx * dx + dy * dy);
+}
+
+__device__ inline double loc_dist(const MaternParams& p, const double* __restrict__ x,
+                                  const double* __restrict__ y, int64_t a, int64_t b) {
+  return point_dist(p, x[a], y[a], x[b], y[b]);
 }
 
 }  // namespace tlrk

@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) matern_block_kernel(MaternParams p, const
   const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t b = blockIdx.y;
   if (a >= m || b >= ncol) return;
-  const double r = loc_dist(x, y, r0 + a, c0 + b);
+  const double r = loc_dist(p, x, y, r0 + a, c0 + b);
   double c, dc;
   matern_eval<deriv>(p, r, c, dc);
   out[b * ld + a] = deriv ? dc : c;

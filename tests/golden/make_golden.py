@@ -17,6 +17,9 @@ theta_true and at the optimiser's start (0.5, 0.05, 0.5).
 
 n102400: the 320 x 320 grid, theta = (1, 0.1, 0.5): z = L eps, the
 log-determinant and q = z^T Sigma^{-1} z from the same factor.
+
+n40000_tlr EPS: the oracle's tile low-rank log-likelihood of the n40000
+configurations at threshold EPS (``tests/golden/n40000_tlr_EPS.json``).
 """
 from __future__ import annotations
 
@@ -103,10 +106,41 @@ def n102400(nb: int = 2048) -> dict:
                         "oracle_s": round(time.time() - t0, 1)}]}
 
 
+def n40000_tlr(eps: float) -> dict:
+    """The oracle's own tile low-rank log-likelihood (oracle/tlr.py: SVD
+    compression at eps, right-looking TLR Cholesky with QR + SVD
+    recompression, tile 560) at the six theta of n40000, on the same z: the
+    error of an exact-truncation TLR approximation at eps, against which the
+    GPU's TLR error is judged where it exceeds 10 eps (smooth, strongly
+    correlated fields)."""
+    from oracle import tlr as OT
+    m = 200
+    x, y = _field(m)
+    z = np.load(os.path.join(HERE, "n40000_z.npy"))
+    out = {"n": x.shape[0], "nb": 560, "eps": eps, "loglik": []}
+    for beta in (0.03, 0.1, 0.3):
+        for nu in (0.5, 1.0):
+            th = (1.0, beta, nu)
+            t0 = time.time()
+            r = OT.loglik(x, y, z, th, 560, eps)
+            rk = r["ranks_factor"]
+            low = rk[np.tril_indices(rk.shape[0], -1)]
+            rec = {"theta": list(th), "ll": r["ll"], "logdet": r["logdet"], "quad": r["quad"],
+                   "rank_mean": float(low.mean()), "rank_max": int(low.max()), "oracle_s": round(time.time() - t0, 1)}
+            out["loglik"].append(rec)
+            _log(f"tlr eps={eps} {th} {rec}")
+    return out
+
+
 if __name__ == "__main__":
     which = sys.argv[1]
-    res = {"n40000": n40000, "n102400": n102400}[which]()
-    res["generator"] = "tests/golden/make_golden.py " + which
+    if which == "n40000_tlr":
+        eps = float(sys.argv[2])
+        res = n40000_tlr(eps)
+        which = f"n40000_tlr_{sys.argv[2]}"
+    else:
+        res = {"n40000": n40000, "n102400": n102400}[which]()
+    res["generator"] = "tests/golden/make_golden.py " + " ".join(sys.argv[1:])
     with open(os.path.join(HERE, f"{which}.json"), "w") as f:
         json.dump(res, f, indent=1)
     _log("written")

@@ -45,6 +45,14 @@ def test_create_rejects_bad_options_without_gpu():
     assert lib.tlr_destroy(None) == m.TLR_OK
     assert lib.tlr_potrf(None, None) == m.TLR_EINVAL
     assert lib.tlr_loglik(None, None, None, None, None) == m.TLR_EINVAL
+    assert lib.tlr_predict(None, None, 0, None, None, None, None) == m.TLR_EINVAL
+    for kw in (dict(metric=2), dict(arena_bytes=-1), dict(sphere_radius=float("nan"))):
+        o = m.Opts()
+        o.n, o.nb, o.tol = 100, 64, 1e-9
+        for k, v in kw.items():
+            setattr(o, k, v)
+        assert lib.tlr_create(ctypes.byref(h), ctypes.byref(o), None) == m.TLR_EINVAL
+
 
 
 @pytest.mark.parametrize("m,seed", [(40, 0), (57, 3), (200, 0)])
