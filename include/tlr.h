@@ -280,6 +280,23 @@ tlr_status tlr_get_tile(tlr_handle_t h, int32_t i, int32_t j, double* d_out, int
 tlr_status tlr_covariance_block(tlr_handle_t h, int64_t r0, int64_t m, int64_t c0, int64_t k, int32_t deriv,
                                 double* d_out, int64_t ld);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): the dense log-likelihood of one small field
+ * in one call with no handle and no allocation, equal to tlr_create (DENSE)
+ * + tlr_generate + tlr_potrf + tlr_loglik.  n locations (1 <= n <= 2048,
+ * else TLR_EINVAL with a tlr_last_error text), Euclidean distance,
+ * theta = (sigma^2, beta, nu) on the host, d_x, d_y, d_z device vectors of
+ * length n; outputs ll, logdet, quad on the host (any may be NULL); info as
+ * tlr_potrf (TLR_ENOTSPD).  Work is issued on `stream` (a hipStream_t, NULL
+ * = null stream), which is synchronised before returning.  All
+ * intermediates live in a fixed device array of 68 MB per GPU that the
+ * library holds from its first use on that GPU until the process ends: calls
+ * that overlap on one GPU (several host threads or streams) race on it and
+ * must be serialised by the caller. */
+tlr_status tlr_dense_loglik_noalloc(int64_t n, const double* d_x, const double* d_y, const double* d_z,
+                                    const double theta[3], double* ll, double* logdet, double* quad, int64_t* info,
+                                    void* stream);
+
 /* Host helper: Morton (Z-order) permutation of n host points: each
  * coordinate is quantised to 16 bits over the points' bounding box, bits are
  * interleaved (x on even positions), keys are sorted stably.  perm[k] is the

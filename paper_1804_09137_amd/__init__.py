@@ -232,6 +232,24 @@ def loglik_grad_batched(handles, xs, ys, zs, thetas, nthreads: int = 4):
     return ll, gr
 
 
+def dense_loglik_noalloc(x, y, z, theta, stream=None):
+    """Dense l, log|Sigma| and z^T Sigma^{-1} z of one small field (n <= 2048)
+    with no handle and no device allocation (tlr_dense_loglik_noalloc)."""
+    import torch
+    lib = _lib.load()
+    n = int(x.shape[0])
+    ll, ld, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    info = ctypes.c_int64(0)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib.tlr_dense_loglik_noalloc(n, _ptr(x), _ptr(y), _ptr(z), _d3(theta), ctypes.byref(ll), ctypes.byref(ld),
+                                      ctypes.byref(q), ctypes.byref(info), ctypes.c_void_p(s.cuda_stream))
+    if st == _lib.TLR_ENOTSPD:
+        raise NotSPDError(info.value, "tlr_dense_loglik_noalloc")
+    if st != _lib.TLR_OK:
+        raise TLRError(st, "tlr_dense_loglik_noalloc")
+    return ll.value, ld.value, q.value
+
+
 def morton_order(x, y) -> np.ndarray:
     """Host Morton (Z-order) permutation of the points (x[i], y[i])."""
     lib = _lib.load()

@@ -61,7 +61,7 @@ KCLASSES = ["update", "lowrank", "compress", "diag", "solve", "gradq", "gen"]
 EXPORTS = ["tlr_create", "tlr_destroy", "tlr_generate", "tlr_compress", "tlr_potrf", "tlr_loglik",
            "tlr_loglik_grad", "tlr_get_ranks", "tlr_get_tangent_ranks", "tlr_get_info", "tlr_get_tile",
            "tlr_covariance_block", "tlr_morton_order", "tlr_last_error", "tlr_sample", "tlr_profile",
-           "tlr_get_kstats", "tlr_loglik_grad_batched", "tlr_predict"]
+           "tlr_get_kstats", "tlr_loglik_grad_batched", "tlr_predict", "tlr_dense_loglik_noalloc"]
 
 _lib = None
 
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlr_get_ranks": [P, ctypes.POINTER(ctypes.c_int32)],
         "tlr_get_tangent_ranks": [P, ctypes.POINTER(ctypes.c_int32)],
         "tlr_predict": [P, P, ctypes.c_int64, P, P, P, P],
+        "tlr_dense_loglik_noalloc": [I64, P, P, P, D3, D3, D3, D3, ctypes.POINTER(I64), P],
         "tlr_get_info": [P, ctypes.POINTER(Info)],
         "tlr_get_tile": [P, ctypes.c_int32, ctypes.c_int32, P, I64],
         "tlr_covariance_block": [P, I64, I64, I64, I64, ctypes.c_int32, P, I64],

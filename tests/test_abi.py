@@ -54,6 +54,17 @@ def test_create_rejects_bad_options_without_gpu():
         assert lib.tlr_create(ctypes.byref(h), ctypes.byref(o), None) == m.TLR_EINVAL
 
 
+def test_noalloc_rejects_sizes_without_gpu():
+    # argument checks come before any GPU call
+    m, lib = _lib()
+    D3 = ctypes.c_double * 3
+    fake = ctypes.c_void_p(16)
+    th = D3(1.0, 0.1, 0.5)
+    assert lib.tlr_dense_loglik_noalloc(100, None, fake, fake, th, None, None, None, None, None) == m.TLR_EINVAL
+    assert lib.tlr_dense_loglik_noalloc(0, fake, fake, fake, th, None, None, None, None, None) == m.TLR_EINVAL
+    assert lib.tlr_dense_loglik_noalloc(2049, fake, fake, fake, th, None, None, None, None, None) == m.TLR_EINVAL
+    assert b"exceeds the maximum 2048" in lib.tlr_last_error()
+
 
 @pytest.mark.parametrize("m,seed", [(40, 0), (57, 3), (200, 0)])
 def test_morton_matches_oracle(m, seed):
