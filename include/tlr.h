@@ -219,6 +219,18 @@ tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y,
 tlr_status tlr_predict(tlr_handle_t h, const double* d_z, int64_t m, const double* d_xnew, const double* d_ynew,
                        double* d_pred, double* d_var);
 
+/* tlr_loglik_grad with the smoothness free as well: grad = (dl/dsigma^2,
+ * dl/dbeta, dl/dnu), the nu term
+ *   -1/2 tr(Sigma^{-1} dSigma/dnu) + 1/2 a^T (dSigma/dnu) a
+ * with dC/dnu = C (log(u/2) - psi(nu) + (dK_nu/dnu)(u) / K_nu(u)), u = r/beta
+ * (psi the digamma function; dK_nu/dnu(x) = int_0^inf exp(-x cosh t) t sinh(nu t) dt,
+ * DLMF 10.32.9 differentiated in nu), propagated through the factorisation in
+ * tangent mode like the beta term.  The paper estimates all three parameters
+ * (Section VIII-D, Tables I-II).  Costs two tlr_loglik_grad passes (one
+ * tangent per parameter); l comes from the first.  Requires opts.want_grad. */
+tlr_status tlr_loglik_grad3(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
+                            const double theta[3], double* ll, double grad[3], int64_t* info);
+
 /* After tlr_potrf: d_z = L d_eps (the factor of Sigma(theta) times a caller
  * vector), e.g. a synthetic measurement vector z ~ N(0, Sigma) from
  * d_eps ~ N(0, I) (the data generator of Section VIII-D).  d_z must not alias
@@ -275,8 +287,9 @@ tlr_status tlr_get_info(tlr_handle_t h, tlr_info* out);
  * Diagonal tiles are lower triangular with zeros above. */
 tlr_status tlr_get_tile(tlr_handle_t h, int32_t i, int32_t j, double* d_out, int64_t ld);
 
-/* Write Sigma(theta)[r0:r0+m, c0:c0+k] (deriv = 0) or dSigma/dbeta (deriv =
- * 1) of the bound locations into d_out (column-major, ld >= m). */
+/* Write Sigma(theta)[r0:r0+m, c0:c0+k] (deriv = 0), dSigma/dbeta (deriv = 1)
+ * or dSigma/dnu (deriv = 2) of the bound locations into d_out (column-major,
+ * ld >= m).  Other deriv values: TLR_EINVAL. */
 tlr_status tlr_covariance_block(tlr_handle_t h, int64_t r0, int64_t m, int64_t c0, int64_t k, int32_t deriv,
                                 double* d_out, int64_t ld);
 

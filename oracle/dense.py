@@ -59,11 +59,11 @@ def loglik(x, y, z, theta) -> dict:
 
 
 def gradient(x, y, z, theta) -> dict:
-    """Score in (sigma2, beta) by the textbook formula; also returns l.
+    """Score in (sigma2, beta, nu) by the textbook formula; also returns l.
 
-    Returns {'ll', 'logdet', 'quad', 'dsigma2', 'dbeta', 'tr_beta', 'qf_beta'}
-    where tr_beta = tr(Sigma^{-1} dSigma/dbeta) and qf_beta = alpha^T
-    dSigma/dbeta alpha.
+    Returns {'ll', 'logdet', 'quad', 'dsigma2', 'dbeta', 'dnu', 'tr_beta',
+    'qf_beta', 'tr_nu', 'qf_nu'} where tr_beta = tr(Sigma^{-1} dSigma/dbeta)
+    and qf_beta = alpha^T dSigma/dbeta alpha (likewise for nu).
     """
     sigma2, beta, nu = (float(t) for t in theta)
     z = np.asarray(z, dtype=np.float64)
@@ -79,14 +79,18 @@ def gradient(x, y, z, theta) -> dict:
     alpha = Sinv @ z
     dS_s2 = _m.covariance(x, y, (1.0, beta, nu))
     dS_b = _m.covariance_dbeta(x, y, theta)
+    dS_n = _m.covariance_dnu(x, y, theta)
     tr_s2 = float(np.sum(Sinv * dS_s2))
     tr_b = float(np.sum(Sinv * dS_b))
+    tr_n = float(np.sum(Sinv * dS_n))
     qf_s2 = float(alpha @ (dS_s2 @ alpha))
     qf_b = float(alpha @ (dS_b @ alpha))
+    qf_n = float(alpha @ (dS_n @ alpha))
     return {"ll": ll, "logdet": logdet, "quad": quad,
             "dsigma2": -0.5 * tr_s2 + 0.5 * qf_s2,
             "dbeta": -0.5 * tr_b + 0.5 * qf_b,
-            "tr_beta": tr_b, "qf_beta": qf_b}
+            "dnu": -0.5 * tr_n + 0.5 * qf_n,
+            "tr_beta": tr_b, "qf_beta": qf_b, "tr_nu": tr_n, "qf_nu": qf_n}
 
 
 def sample_z(x, y, theta, eps) -> np.ndarray:

@@ -11,7 +11,7 @@ Gamma(nu) gives C(0) = theta1, used whenever r == 0 exactly.
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import gamma, kv
+from scipy.special import digamma, gamma, kv
 
 
 def matern(r, sigma2: float, beta: float, nu: float) -> np.ndarray:
@@ -40,6 +40,37 @@ def dmatern_dbeta(r, sigma2: float, beta: float, nu: float) -> np.ndarray:
     up = u[pos]
     out[pos] = (sigma2 / (2.0 ** (nu - 1.0) * gamma(nu)) * up ** (nu + 1.0)
                 * kv(nu - 1.0, up) / beta)
+    return out
+
+
+def dkv_dnu(nu: float, x) -> np.ndarray:
+    """dK_nu(x)/dnu, the derivative of scipy's K_nu in its order.
+
+    Central differences D(h) = (K_{nu+h} - K_{nu-h}) / (2h) at h and h/2,
+    combined by Richardson extrapolation, (4 D(h/2) - D(h)) / 3, whose error is
+    O(h^4) (h = 2e-3; scipy's K_nu itself is accurate to about 1e-14
+    relative, so the result to about 1e-10).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    h = 2e-3
+
+    def d(hh):
+        return (kv(nu + hh, x) - kv(nu - hh, x)) / (2.0 * hh)
+    return (4.0 * d(h / 2.0) - d(h)) / 3.0
+
+
+def dmatern_dnu(r, sigma2: float, beta: float, nu: float) -> np.ndarray:
+    """dC/dnu of Eq. (MaternCov): with u = r / beta,
+    dC/dnu = C (log(u / 2) - psi(nu)) + sigma2 2^{1-nu} / Gamma(nu) u^nu dK_nu/dnu(u)
+    (psi the digamma function); 0 at r = 0, where C = sigma2 for every nu."""
+    r = np.asarray(r, dtype=np.float64)
+    u = r / beta
+    out = np.zeros(u.shape)
+    pos = u > 0
+    up = u[pos]
+    norm = sigma2 / (2.0 ** (nu - 1.0) * gamma(nu))
+    c = norm * up ** nu * kv(nu, up)
+    out[pos] = c * (np.log(up / 2.0) - digamma(nu)) + norm * up ** nu * dkv_dnu(nu, up)
     return out
 
 
@@ -90,6 +121,16 @@ def covariance_dbeta(x, y, theta, rows=None, cols=None, metric: str = "euclid",
     ra = slice(None) if rows is None else rows
     cb = slice(None) if cols is None else cols
     return dmatern_dbeta(distances(x[ra], y[ra], x[cb], y[cb], metric, radius), *theta)
+
+
+def covariance_dnu(x, y, theta, rows=None, cols=None, metric: str = "euclid",
+                   radius: float = EARTH_RADIUS_KM) -> np.ndarray:
+    """dSigma/dnu[rows, cols], entry-wise dC/dnu."""
+    x = np.asarray(x, float)
+    y = np.asarray(y, float)
+    ra = slice(None) if rows is None else rows
+    cb = slice(None) if cols is None else cols
+    return dmatern_dnu(distances(x[ra], y[ra], x[cb], y[cb], metric, radius), *theta)
 
 
 def cross_covariance(xa, ya, xb, yb, theta, metric: str = "euclid", radius: float = EARTH_RADIUS_KM):

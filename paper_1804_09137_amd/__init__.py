@@ -144,6 +144,17 @@ class Handle:
         self._check(st, "tlr_predict")
         return (pred, var) if variance else pred
 
+    def loglik_grad3(self, x, y, z, theta):
+        """l and (dl/dsigma^2, dl/dbeta, dl/dnu) (tlr_loglik_grad3)."""
+        ll = ctypes.c_double()
+        g = (ctypes.c_double * 3)()
+        info = ctypes.c_int64(0)
+        st = self._lib.tlr_loglik_grad3(self._h, _ptr(x), _ptr(y), _ptr(z), _d3(theta), ctypes.byref(ll), g,
+                                        ctypes.byref(info))
+        self._check(st, "tlr_loglik_grad3", info.value)
+        self._keep = (x, y)
+        return ll.value, (g[0], g[1], g[2])
+
     def sample(self, eps):
         """z = L eps with the current factor (after potrf)."""
         import torch
@@ -191,10 +202,12 @@ class Handle:
         self._check(st, "tlr_get_tile")
         return out.t()
 
-    def covariance_block(self, r0: int, m: int, c0: int, k: int, deriv: bool = False):
+    def covariance_block(self, r0: int, m: int, c0: int, k: int, deriv=False):
+        """Sigma block (deriv False/0), dSigma/dbeta (True/1 or "beta") or dSigma/dnu (2 or "nu")."""
         import torch
         out = torch.empty((k, m), dtype=torch.float64, device="cuda")
-        st = self._lib.tlr_covariance_block(self._h, int(r0), int(m), int(c0), int(k), 1 if deriv else 0,
+        dv = {"beta": 1, "nu": 2}[deriv] if isinstance(deriv, str) else int(deriv)
+        st = self._lib.tlr_covariance_block(self._h, int(r0), int(m), int(c0), int(k), dv,
                                             _ptr(out), int(m))
         self._check(st, "tlr_covariance_block")
         return out.t()

@@ -61,7 +61,8 @@ KCLASSES = ["update", "lowrank", "compress", "diag", "solve", "gradq", "gen"]
 EXPORTS = ["tlr_create", "tlr_destroy", "tlr_generate", "tlr_compress", "tlr_potrf", "tlr_loglik",
            "tlr_loglik_grad", "tlr_get_ranks", "tlr_get_tangent_ranks", "tlr_get_info", "tlr_get_tile",
            "tlr_covariance_block", "tlr_morton_order", "tlr_last_error", "tlr_sample", "tlr_profile",
-           "tlr_get_kstats", "tlr_loglik_grad_batched", "tlr_predict", "tlr_dense_loglik_noalloc"]
+           "tlr_get_kstats", "tlr_loglik_grad_batched", "tlr_predict", "tlr_dense_loglik_noalloc",
+           "tlr_loglik_grad3"]
 
 _lib = None
 
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlr_potrf": [P, ctypes.POINTER(I64)],
         "tlr_loglik": [P, P, D3, D3, D3],
         "tlr_loglik_grad": [P, P, P, P, D3, D3, D3, ctypes.POINTER(I64)],
+        "tlr_loglik_grad3": [P, P, P, P, D3, D3, D3, ctypes.POINTER(I64)],
         "tlr_get_ranks": [P, ctypes.POINTER(ctypes.c_int32)],
         "tlr_get_tangent_ranks": [P, ctypes.POINTER(ctypes.c_int32)],
         "tlr_predict": [P, P, ctypes.c_int64, P, P, P, P],

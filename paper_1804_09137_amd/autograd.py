@@ -36,9 +36,11 @@ class TLRLogLik(torch.autograd.Function):
         return g * grad, None, None, None, None, None
 
 
-def fit(handle: Handle, x, y, z, theta0, nu: float, method: str = "L-BFGS-B", tol: float = 1e-6,
+def fit(handle: Handle, x, y, z, theta0, nu: float | None = None, method: str = "L-BFGS-B", tol: float = 1e-6,
         maxiter: int = 200) -> dict:
-    """Maximise l over (sigma^2, beta) > 0 from theta0 = (sigma^2, beta).
+    """Maximise l over (sigma^2, beta) > 0 from theta0 = (sigma^2, beta) at
+    fixed smoothness nu, or over (sigma^2, beta, nu) from a three-entry theta0
+    (nu None): the paper estimates all three (Section VIII-D).
 
     The search runs on log(theta) so that the bounds are implicit; the score
     maps through d l / d log(theta_i) = theta_i * d l / d theta_i.
@@ -51,14 +53,22 @@ def fit(handle: Handle, x, y, z, theta0, nu: float, method: str = "L-BFGS-B", to
     from scipy.optimize import minimize
 
     evals = {"n": 0}
+    free_nu = len(theta0) == 3
+    if free_nu == (nu is not None):
+        raise ValueError("give nu for a two-entry theta0, or a three-entry theta0 without nu")
+
+    def evaluate(th):
+        if free_nu:
+            return handle.loglik_grad3(x, y, z, tuple(float(t) for t in th))
+        return handle.loglik_grad(x, y, z, (float(th[0]), float(th[1]), float(nu)))
 
     def negll(phi):
         th = np.exp(phi)
-        ll, (gs, gb) = handle.loglik_grad(x, y, z, (float(th[0]), float(th[1]), float(nu)))
+        ll, g = evaluate(th)
         evals["n"] += 1
         if not math.isfinite(ll):
-            return 1e300, np.zeros(2)
-        return -ll, -np.array([gs * th[0], gb * th[1]])
+            return 1e300, np.zeros(len(phi))
+        return -ll, -np.array(g) * th
 
     phi0 = np.log(np.asarray(theta0, dtype=np.float64))
     if method == "L-BFGS-B":
@@ -70,6 +80,6 @@ def fit(handle: Handle, x, y, z, theta0, nu: float, method: str = "L-BFGS-B", to
     else:
         raise ValueError(f"unknown method {method!r}")
     th = np.exp(res.x)
-    ll, g = handle.loglik_grad(x, y, z, (float(th[0]), float(th[1]), float(nu)))
-    return {"theta": (float(th[0]), float(th[1])), "ll": ll, "grad": g, "evals": evals["n"] + 1,
+    ll, g = evaluate(th)
+    return {"theta": tuple(float(t) for t in th), "ll": ll, "grad": g, "evals": evals["n"] + 1,
             "converged": bool(res.success), "message": str(res.message)}

@@ -428,8 +428,11 @@ tlr_status tlr_covariance_block(tlr_handle_t h, int64_t r0, int64_t m, int64_t c
   if (!h || !d_out || m < 0 || k < 0 || r0 < 0 || c0 < 0 || r0 + m > h->n || c0 + k > h->n || ld < m)
     return TLR_EINVAL;
   if (!h->bound) return TLR_ESTATE;
+  if (deriv < 0 || deriv > 2) return TLR_EINVAL;
   return guarded(h, [&]() -> tlr_status {
-    HIPCHK(launch_matern_block(h->mp, h->x, h->y, r0, m, c0, k, d_out, ld, deriv != 0, h->s));
+    MaternParams p = h->mp;
+    p.dparam = deriv == 2 ? kDerivNu : kDerivBeta;
+    HIPCHK(launch_matern_block(p, h->x, h->y, r0, m, c0, k, d_out, ld, deriv != 0, h->s));
     sync(h);
     return TLR_OK;
   });
@@ -437,13 +440,19 @@ tlr_status tlr_covariance_block(tlr_handle_t h, int64_t r0, int64_t m, int64_t c
 
 }  // extern "C"
 
-extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
-                                      const double theta[3], double* ll, double grad[2], int64_t* info) {
+namespace {
+// l and the score of one theta parameter besides sigma^2: grad = (dl/dsigma^2,
+// dl/dtheta_d), theta_d = beta (dparam kDerivBeta) or nu (kDerivNu); the
+// tangent factorisation and the quadratic term both take their dSigma from
+// the Matérn generation with that derivative selected.
+tlr_status loglik_grad_impl(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
+                            const double theta[3], double* ll, double grad[2], int64_t* info, int dparam) {
   if (!h || !d_x || !d_y || !d_z || !theta || !grad) return TLR_EINVAL;
   if (!h->grad) return TLR_ESTATE;
   if (info) *info = 0;
   tlr_status st = tlr_generate(h, d_x, d_y, theta);
   if (st != TLR_OK) return st;
+  h->mp.dparam = dparam;
   return guarded(h, [&]() -> tlr_status {
     double ld = 0.0, q = 0.0;
     const double n = (double)h->n;
@@ -489,6 +498,29 @@ extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const d
     grad[1] = -0.5 * trace + 0.5 * qf;
     return TLR_OK;
   });
+}
+}  // namespace
+
+extern "C" tlr_status tlr_loglik_grad(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
+                                      const double theta[3], double* ll, double grad[2], int64_t* info) {
+  return loglik_grad_impl(h, d_x, d_y, d_z, theta, ll, grad, info, kDerivBeta);
+}
+
+extern "C" tlr_status tlr_loglik_grad3(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
+                                       const double theta[3], double* ll, double grad[3], int64_t* info) {
+  if (!grad) return TLR_EINVAL;
+  double g[2];
+  tlr_status st = loglik_grad_impl(h, d_x, d_y, d_z, theta, ll, g, info, kDerivBeta);
+  if (st != TLR_OK) return st;
+  grad[0] = g[0];
+  grad[1] = g[1];
+  // the same evaluation with the tangent in nu; l, log|Sigma| and q are kept
+  // from the first pass
+  st = loglik_grad_impl(h, d_x, d_y, d_z, theta, nullptr, g, info, kDerivNu);
+  h->mp.dparam = kDerivBeta;
+  if (st != TLR_OK) return st;
+  grad[2] = g[1];
+  return TLR_OK;
 }
 
 extern "C" tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, const double* const* d_x,

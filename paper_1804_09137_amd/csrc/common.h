@@ -28,9 +28,17 @@ constexpr int kTrapTerms = 32;      // nodes per bucket cap (needs <= 27)
 // Device-resident tables for general nu; laid out as doubles:
 //   temme[4][kTemmeTerms]: 1/(k-mu), 1/(k+mu), 1/(k^2-mu^2), 1/k  for k = 1..kTemmeTerms
 //   trap[kTrapBuckets][3][kTrapTerms]: cosh(t_k)-1, cosh(nu t_k), cosh((nu-1) t_k), t_k = k h_b
+//   dnu[3][kDnuNodes]: cosh(t_k) - 1, cosh(nu t_k), t_k sinh(nu t_k), t_k = k kDnuH
+//   (every nu: the derivative in nu)
+constexpr int kDnuNodes = 128;
+constexpr double kDnuH = 0.25;
 constexpr int kTabTemme = 0;
 constexpr int kTabTrap = 4 * kTemmeTerms;
-constexpr int kTabSize = kTabTrap + kTrapBuckets * 3 * kTrapTerms;
+constexpr int kTabDnu = kTabTrap + kTrapBuckets * 3 * kTrapTerms;
+constexpr int kTabSize = kTabDnu + 3 * kDnuNodes;
+
+// Which derivative matern_eval<true> returns: dC/dbeta or dC/dnu.
+enum MaternDeriv : int { kDerivBeta = 1, kDerivNu = 2 };
 
 struct MaternParams {
   double sigma2, beta, inv_beta, nu;
@@ -48,6 +56,8 @@ struct MaternParams {
   const double* tab;    // device tables (kTabSize doubles), general nu only
   int metric;           // Metric
   double radius;        // kMetricGreatCircle: sphere radius (distance unit)
+  int dparam;           // MaternDeriv: the parameter of the derivative (kDerivBeta by default)
+  double psi;           // digamma(nu), for dC/dnu
 };
 
 // Host: fill p for theta = (sigma2, beta, nu); writes the kTabSize-double table

@@ -508,7 +508,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   for (int g = 0; g < G; ++g) {
     const RankPred& pred = jobs[jof[g]].pred;
     const int t = tloc[g];
-    if (!h->strict && pred.k[t] > maxrank) {
+    // kept dense at once only when the same tile was dense in the previous
+    // factorisation: a prediction from the neighbouring tiles would carry a
+    // dense tile on to every later tile of its row
+    if (!h->strict && pred.hist && pred.k[t] > maxrank) {
       dense[g] = 1;
       t1[g] = pred.r1[t];
       continue;

@@ -79,12 +79,48 @@ __device__ inline void trap_pair(const MaternParams& p, double x, double& knu, d
   knum1 = p.trap_h[b] * sm;
 }
 
-// Matérn value C(r) and, if want_d, dC/dbeta.
+// S1 / S0 with S0 = sum_k w_k e^{-x (cosh t_k - 1)} cosh(nu t_k) and
+// S1 = sum_k e^{-x (cosh t_k - 1)} t_k sinh(nu t_k), t_k = k h, w_0 = 1/2:
+// the trapezoid rule on K_nu(x) = int_0^inf e^{-x cosh t} cosh(nu t) dt
+// (DLMF 10.32.9) and on its derivative in the order,
+// dK_nu/dnu(x) = int_0^inf e^{-x cosh t} t sinh(nu t) dt, with the common
+// factor e^{-x} dropped, so S1 / S0 = (dK_nu/dnu) / K_nu.  Both integrands
+// are even and analytic in the strip |Im t| < pi/2, so the trapezoid error
+// falls like exp(-pi^2 / h) (Trefethen & Weideman); the sum stops once
+// x (cosh t_k - 1) exceeds nu t_k + 40 (past the peak, terms below e^-40).
+__device__ inline double dnu_ratio(const MaternParams& p, double x) {
+  const double* cm1 = p.tab + kTabDnu;
+  const double* cnu = cm1 + kDnuNodes;
+  const double* tsn = cnu + kDnuNodes;
+  double s0 = 0.5, s1 = 0.0;
+  for (int k = 1; k < kDnuNodes; ++k) {
+    const double a = x * cm1[k];
+    if (a > 40.0 + p.nu * (k * kDnuH)) break;
+    const double e = exp(-a);
+    s0 += e * cnu[k];
+    s1 += e * tsn[k];
+  }
+  return s1 / s0;
+}
+
+// Matérn value C(r) and, if want_d, its derivative in the parameter p.dparam
+// selects: dC/dbeta, or
+//   dC/dnu = C (log(u / 2) - psi(nu)) + sigma2 2^{1-nu} / Gamma(nu) u^nu dK_nu/dnu(u)
+//          = C (log(u / 2) - psi(nu) + (dK_nu/dnu)(u) / K_nu(u)),
+// which is 0 at r = 0 (C(0) = sigma2 for every nu) and is taken as 0 below
+// u = 1e-10 (its limit; the trapezoid's nodes end there).
 template <bool want_d>
 __device__ inline void matern_eval(const MaternParams& p, double r, double& c, double& dc) {
   if (r == 0.0) {  // limit u^nu K_nu(u) -> 2^(nu-1) Gamma(nu)
     c = p.sigma2;
     dc = 0.0;
+    return;
+  }
+  if (want_d && p.dparam == kDerivNu) {
+    double unused;
+    matern_eval<false>(p, r, c, unused);
+    const double u = r * p.inv_beta;
+    dc = (u < 1e-10) ? 0.0 : c * (log(0.5 * u) - p.psi + dnu_ratio(p, u));
     return;
   }
   const double u = r * p.inv_beta;

@@ -45,6 +45,21 @@ const double kRGamma[26] = {
 const double kTrapEdge[kTrapBuckets] = {3.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0, 256.0, 1e300};
 const double kTrapH[kTrapBuckets] = {0.2, 0.21, 0.19, 0.15, 0.105, 0.075, 0.053, 0.037, 0.022};
 const double kTrapLo[kTrapBuckets] = {2.0, 3.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0, 256.0};
+
+// digamma(x), x > 0: the recurrence psi(x) = psi(x + 1) - 1/x up to x >= 10,
+// then the asymptotic series psi(x) ~ ln x - 1/(2x) - sum_k B_2k / (2k x^2k)
+// (Abramowitz & Stegun 6.3.5 and 6.3.18), seven terms: error below 1e-16.
+double digamma(double x) {
+  double acc = 0.0;
+  while (x < 10.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  const double r = 1.0 / (x * x);
+  const double s = r * (1.0 / 12 - r * (1.0 / 120 - r * (1.0 / 252 - r * (1.0 / 240 - r * (1.0 / 132 -
+                   r * (691.0 / 32760 - r * (1.0 / 12)))))));
+  return acc + std::log(x) - 0.5 / x - s;
+}
 }  // namespace
 
 bool matern_setup(double sigma2, double beta, double nu, MaternParams* p, double* tab) {
@@ -61,6 +76,15 @@ bool matern_setup(double sigma2, double beta, double nu, MaternParams* p, double
   else if (nu == 2.5) p->kind = kNuFiveHalves;
   else p->kind = kNuGeneral;
   for (int i = 0; i < kTabSize; ++i) tab[i] = 0.0;
+  p->dparam = kDerivBeta;
+  p->psi = digamma(nu);
+  for (int k = 0; k < kDnuNodes; ++k) {   // nodes of dnu_ratio (every nu)
+    const double t = k * kDnuH;
+    const double sh = std::sinh(0.5 * t);
+    tab[kTabDnu + k] = 2.0 * sh * sh;   // cosh t - 1 without cancellation
+    tab[kTabDnu + kDnuNodes + k] = std::cosh(nu * t);
+    tab[kTabDnu + 2 * kDnuNodes + k] = t * std::sinh(nu * t);
+  }
   if (p->kind != kNuGeneral) return true;
 
   double mu;

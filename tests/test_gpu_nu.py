@@ -1,0 +1,109 @@
+"""The smoothness nu as a free parameter (the paper estimates all three
+Matérn parameters, Section VIII-D): dSigma/dnu on the device against the
+oracle (oracle/matern.py dmatern_dnu: C (log(u/2) - psi(nu)) plus the order
+derivative of K_nu by Richardson-extrapolated differences of scipy's K_nu,
+accurate to ~1e-10), the nu term of the score through the C-ABI
+(tlr_loglik_grad3) against the oracle's dense score, a central difference,
+and a three-parameter L-BFGS fit against the same fit on the oracle.
+
+Tolerances: entries 2e-9 sigma^2 (the oracle's accuracy); dense score terms
+1e-8 of their scale; TLR 100 eps of it; fitted parameters 1e-4 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import dense as D
+from oracle import matern as M
+
+from gpu_util import field, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.5, 0.8, 1.0, 1.5, 2.2, 2.5])
+def test_dsigma_dnu_block(nu):
+    import paper_1804_09137_amd as P
+    n = 600
+    th = (1.2, 0.08, nu)
+    x, y, _ = field(n, 0, with_z=False)
+    h = P.Handle(n, 128, tol=1e-9)
+    xd, yd = to_dev(x, y)
+    h.generate(xd, yd, th)
+    got = h.covariance_block(0, n, 0, n, deriv="nu").cpu().numpy()
+    want = M.covariance_dnu(x, y, th)
+    err = np.abs(got - want).max()
+    log(f"nu={nu}: max |dC/dnu - oracle| = {err:.2e} (max |dC/dnu| {np.abs(want).max():.3f})")
+    assert err <= 2e-9 * th[0]
+    assert np.all(np.diag(got) == 0.0)
+    # the beta derivative is unchanged by the nu machinery
+    gb = h.covariance_block(0, 200, 0, 200, deriv=True).cpu().numpy()
+    np.testing.assert_allclose(gb, M.covariance_dbeta(x, y, th, slice(0, 200), slice(0, 200)), rtol=5e-13,
+                               atol=1e-300)
+
+
+@pytest.mark.parametrize("mode,eps,nu", [("dense", 0.0, 0.5), ("dense", 0.0, 1.3), ("tlr", 1e-9, 0.8),
+                                         ("tlr", 1e-9, 1.5)])
+def test_score_nu_matches_oracle(mode, eps, nu):
+    import paper_1804_09137_amd as P
+    n, nb = 1500, 256
+    th = (1.0, 0.1, nu)
+    x, y, z = field(n, 9, th)
+    ref = D.gradient(x, y, z, th)
+    h = P.Handle(n, nb, mode=mode, tol=max(eps, 1e-9), maxrank=128, want_grad=True)
+    xd, yd, zd = to_dev(x, y, z)
+    ll, g = h.loglik_grad3(xd, yd, zd, th)
+    ll2, g2 = h.loglik_grad(xd, yd, zd, th)
+    sb = 0.5 * (abs(ref["tr_beta"]) + abs(ref["qf_beta"]))
+    sn = 0.5 * (abs(ref["tr_nu"]) + abs(ref["qf_nu"]))
+    log(f"{mode} nu={nu}: dnu {g[2]:.10g} vs {ref['dnu']:.10g} (scale {sn:.3e}); dbeta {g[1]:.10g} vs "
+        f"{ref['dbeta']:.10g}")
+    tol = 1e-8 if mode == "dense" else 100 * eps
+    assert abs(g[2] - ref["dnu"]) <= tol * sn
+    assert abs(g[1] - ref["dbeta"]) <= tol * sb
+    assert abs(ll - ref["ll"]) <= (1e-9 if mode == "dense" else 10 * eps) * abs(ref["ll"])
+    # the two-parameter call is unchanged
+    assert abs(g2[1] - g[1]) <= 1e-12 * sb + (0 if mode == "dense" else 10 * eps * sb)
+
+
+def test_score_nu_central_difference():
+    import paper_1804_09137_amd as P
+    n, nb = 1200, 256
+    th = (1.0, 0.1, 1.1)
+    x, y, z = field(n, 10, th)
+    xd, yd, zd = to_dev(x, y, z)
+    d = P.Handle(n, nb, mode="dense", want_grad=True)
+    hn = 1e-5
+    v = []
+    for nu in (th[2] + hn, th[2] - hn):
+        d.generate(xd, yd, (th[0], th[1], nu))
+        d.potrf()
+        v.append(d.loglik(zd)[0])
+    fd = (v[0] - v[1]) / (2 * hn)
+    _, g = d.loglik_grad3(xd, yd, zd, th)
+    log(f"central difference {fd:.8g}, score {g[2]:.8g}")
+    assert abs(fd - g[2]) <= 1e-6 * max(1.0, abs(g[2])) + 1e-12 * abs(v[0]) / hn
+
+
+@pytest.mark.parametrize("mode", ["dense", "tlr"])
+def test_three_parameter_fit_matches_oracle(mode):
+    import paper_1804_09137_amd as P
+    from paper_1804_09137_amd.autograd import fit
+    from scipy.optimize import minimize
+    n, nb = 700, 128
+    x, y, z = field(n, 11, (1.0, 0.1, 0.9))
+
+    def f(phi):
+        th = np.exp(phi)
+        r = D.gradient(x, y, z, tuple(th))
+        return -r["ll"], -np.array([r["dsigma2"], r["dbeta"], r["dnu"]]) * th
+    ref = np.exp(minimize(f, np.log([0.5, 0.05, 0.5]), jac=True, method="L-BFGS-B",
+                          options={"ftol": 1e-15, "gtol": 1e-9}).x)
+    h = P.Handle(n, nb, mode=mode, tol=1e-10, maxrank=nb, want_grad=True)
+    xd, yd, zd = to_dev(x, y, z)
+    # the TLR likelihood moves in steps where ranks change with theta (its
+    # score is the TLR approximation of the exact one), so its fit stops at
+    # the 1e-6 gradient tolerance of the MLE configuration; the dense one at 1e-9
+    r = fit(h, xd, yd, zd, (0.5, 0.05, 0.5), tol=1e-9 if mode == "dense" else 1e-6)
+    log(f"{mode}: theta {r['theta']} vs oracle {tuple(ref)} in {r['evals']} evals; score {r['grad']}")
+    assert r["converged"]
+    np.testing.assert_allclose(r["theta"], ref, rtol=1e-4)
