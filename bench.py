@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--beta", type=float, default=0.1)
     ap.add_argument("--nu", type=float, default=0.5)
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose nb and maxrank with the autotuner (paper_1804_09137_amd/tune.py) before timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=8000)
     ap.add_argument("--z-white", action="store_true",
@@ -322,6 +324,12 @@ def main():
         del hz
         torch.cuda.empty_cache()
 
+    if args.tune:
+        from paper_1804_09137_amd.tune import tune
+        tr = tune(xd, yd, zd, th, args.eps, log=log,
+                  cands=[(nb, mr) for nb in (640, 800, 1024) for mr in (nb // 4, nb // 3)])
+        args.nb, args.maxrank = tr["nb"], tr["maxrank"]
+        out["tuning"] = {f"{k[0]}/{k[1]}": v for k, v in tr["ms"].items()}
     log(f"[bench] TLR handle n={n} nb={args.nb} eps={args.eps} maxrank={args.maxrank}")
     ht = P.Handle(n, args.nb, tol=args.eps, maxrank=args.maxrank, want_grad=True, prec=args.prec)
     # cold call: a fresh handle, no rank history (first-touch costs included)
