@@ -58,10 +58,11 @@ def cpu_baseline(n_target: int, theta, n_sample: int) -> dict:
         x, y = x[p], y[p]
         z = D.sample_z(x, y, theta, synth.standard_normal(ns, 1))
         ts = []
-        for _ in range(3):
+        for r in range(3):
             t0 = time.perf_counter()
             D.gradient(x, y, z, theta)
             ts.append(time.perf_counter() - t0)
+            log(f"[bench] CPU oracle n={ns} run {r + 1}/3: {ts[-1]:.2f} s")
         meds[ns] = statistics.median(ts)
     n1, n2 = sorted(meds)
     # t = a n^2 + b n^3 through (n1, t1), (n2, t2)

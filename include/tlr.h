@@ -83,6 +83,13 @@ typedef enum {
 } tlr_metric;
 
 /* tlr_opts.flags */
+#define TLR_FLAG_ACA 4          /* tlr_compress compresses each tile by adaptive cross approximation with
+                                   partial pivoting, fused with its generation (only the rows and columns
+                                   it visits are generated; Section V lists ACA among the methods), and
+                                   stops after two consecutive terms with ||u|| ||v|| <= tol / 10.  Its
+                                   error is estimated by those terms, not bounded as the default
+                                   randomized range finder's is; ranks come out a little higher than
+                                   the SVD's */
 #define TLR_FLAG_STRICT_RANK 1  /* a tile needing rank > maxrank is an error (TLR_ERANK) instead of
                                    being kept dense */
 #define TLR_FLAG_SINGLE_STREAM 2 /* TLR with want_grad: issue everything on the caller's stream.  By

@@ -56,7 +56,7 @@ class Handle:
     def __init__(self, n: int, nb: int, tol: float = 1e-9, maxrank: int = 0, mode: str = "tlr",
                  prec: str = "fp64", want_grad: bool = False, seed: int = 0, strict_rank: bool = False,
                  stream=None, single_stream: bool = False, arena_bytes: int = 0, metric: str = "euclid",
-                 sphere_radius: float = 0.0):
+                 sphere_radius: float = 0.0, aca: bool = False):
         import torch
         self._lib = _lib.load()
         o = _lib.Opts()
@@ -65,7 +65,8 @@ class Handle:
         o.prec = {"fp64": _lib.PREC_FP64, "fp32_updates": _lib.PREC_FP32_UPDATES}[prec]
         o.want_grad = 1 if want_grad else 0
         o.seed = int(seed)
-        o.flags = (_lib.FLAG_STRICT_RANK if strict_rank else 0) | (_lib.FLAG_SINGLE_STREAM if single_stream else 0)
+        o.flags = ((_lib.FLAG_STRICT_RANK if strict_rank else 0) | (_lib.FLAG_SINGLE_STREAM if single_stream else 0)
+                   | (_lib.FLAG_ACA if aca else 0))
         o.arena_bytes = int(arena_bytes)
         o.metric = {"euclid": 0, "great_circle": 1}[metric]
         o.sphere_radius = float(sphere_radius)

@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 
 HIP_SOURCES = ["matern.hip", "gemm.hip", "chol.hip", "tile_chol.hip", "compress.hip", "hqr.hip", "solve.hip",
                "grad.hip", "factor.hip", "api.hip",
-               "predict.hip", "noalloc.hip"]
+               "predict.hip", "noalloc.hip", "aca.hip"]
 CPP_SOURCES = ["morton.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

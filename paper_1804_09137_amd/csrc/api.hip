@@ -209,6 +209,8 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
       }
       h->qr_d = dalloc<int>(h, 2 * gc);
       h->qr_h = halloc<int>(h, 2 * gc);
+      h->aca_d = dalloc<AcaTask>(h, gc);
+      h->aca_h = halloc<AcaTask>(h, gc);
       if (o->prec == TLR_PREC_FP32_UPDATES) {
         h->chk_d = dalloc<double>(h, 2 * nt);
         h->chk_h = halloc<double>(h, 2 * nt);
@@ -271,7 +273,7 @@ tlr_status tlr_compress(tlr_handle_t h) {
   return guarded(h, [&]() -> tlr_status {
     for (;;) {
       try {
-        compress_sigma(h);
+        if (h->o.flags & TLR_FLAG_ACA) compress_sigma_aca(h); else compress_sigma(h);
         return TLR_OK;
       } catch (const Fail& f) {
         if (!(f.st == TLR_ENOMEM && h->tile_overflow && h->tile_auto)) throw;

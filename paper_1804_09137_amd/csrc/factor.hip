@@ -2150,4 +2150,115 @@ void compress_sigma(tlr_handle_s* h) {
     h->state = 1;
   }
 }
+
+// tlr_compress with TLR_FLAG_ACA: every strictly-lower tile of Sigma by
+// adaptive cross approximation fused with its generation (aca.hip), column
+// by column; U and V go to the tile storage at the rank ACA stopped at.  The
+// stop is two consecutive terms with ||u|| ||v|| <= tol / 10.  A tile that
+// needs more than maxrank steps is generated densely (V = identity), or is a
+// TLR_ERANK failure with TLR_FLAG_STRICT_RANK.
+void compress_sigma_aca(tlr_handle_s* h) {
+  prof_reset_pool(h);
+  const int nt = h->nt, nb = h->nb;
+  Family& F = h->fam[0];
+  family_reset(h, F, 2);
+  h->tile_used = 0;
+  h->tile_overflow = false;
+  reset_info(h);
+  sync(h);
+  meta_reset(h);
+  h->state = 0;
+  const int kmax = h->maxrank;
+  const double tau = 0.1 * h->o.tol;
+  double cflops = 0.0;
+  for (int j = 0; j < nt; ++j) {
+    const int nbj = tile_rows(h, j);
+    HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)j * nb, nbj, (int64_t)j * nb, nbj, diag_tile(h, j), nb,
+                               false, h->s));
+    const int T = nt - j - 1;
+    if (T <= 0) continue;
+    const size_t e_c = prof_mark(h);
+    for (int t = 0; t < T; ++t) {
+      AcaTask& a = h->aca_h[t];
+      a.r0 = (int64_t)(j + 1 + t) * nb;
+      a.c0 = (int64_t)j * nb;
+      a.m = tile_rows(h, j + 1 + t);
+      a.n = nbj;
+      a.U = h->Ybuf + (int64_t)t * nb * h->smax;
+      a.V = h->Q1 + (int64_t)t * nb * h->smax;
+      a.ld = nb;
+      a.rank = h->qr_d + t;
+    }
+    HIPCHK(hipMemcpyAsync(h->aca_d, h->aca_h, T * sizeof(AcaTask), hipMemcpyHostToDevice, h->s));
+    HIPCHK(launch_aca(h->mp, h->x, h->y, h->aca_d, T, kmax, tau, h->s));
+    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, T * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    HIPCHK(hipStreamSynchronize(h->s));
+    meta_reset(h);
+    int nlr = 0;
+    for (int t = 0; t < T; ++t) {
+      const int i = j + 1 + t;
+      const size_t id = tid_of(h, i, j);
+      const int k = h->qr_h[t];
+      const int m = tile_rows(h, i);
+      cflops += 2.0 * k * (double)k * (m + nbj);
+      if (k > kmax) {
+        if (h->strict) {
+          h->bad_i = i;
+          h->bad_j = j;
+          throw Fail{TLR_ERANK};
+        }
+        F.isdense[id] = 1;
+        F.rk[id] = nbj;
+        F.uoff[id] = tile_take(h, (int64_t)nb * nbj);
+        F.voff[id] = h->ident_off;
+        HIPCHK(launch_matern_block(h->mp, h->x, h->y, (int64_t)i * nb, m, (int64_t)j * nb, nbj,
+                                   h->arena + F.uoff[id], nb, false, h->s));
+      } else {
+        F.rk[id] = k;
+        F.uoff[id] = k > 0 ? tile_take(h, (int64_t)nb * k) : 0;
+        F.voff[id] = k > 0 ? tile_take(h, (int64_t)nb * k) : 0;
+        if (k > 0) ++nlr;
+      }
+    }
+    if (nlr > 0) {
+      // U (m x k) and V (nbj x k) from the ACA scratch to the tile storage
+      meta_reserve(h, 4 * (int64_t)nlr, 4 * (int64_t)nlr);
+      int *m_d, *k_d;
+      int* m_h = im_take(h, 2 * nlr, &m_d);
+      int* k_h = im_take(h, 2 * nlr, &k_d);
+      int64_t *so_d, *do_d;
+      int64_t* so_h = lm_take(h, 2 * nlr, &so_d);
+      int64_t* do_h = lm_take(h, 2 * nlr, &do_d);
+      int q = 0;
+      int64_t maxe = 0;
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        if (F.isdense[id] || F.rk[id] <= 0) continue;
+        const int k = F.rk[id];
+        m_h[q] = tile_rows(h, j + 1 + t); k_h[q] = k;
+        m_h[nlr + q] = nbj; k_h[nlr + q] = k;
+        so_h[q] = so_h[nlr + q] = (int64_t)t * nb * h->smax;   // same block of the U and the V scratch
+        do_h[q] = F.uoff[id];
+        do_h[nlr + q] = F.voff[id];
+        maxe = std::max<int64_t>(maxe, (int64_t)nb * k);
+        ++q;
+      }
+      im_push(h, m_h, m_d, 2 * (int64_t)nlr);
+      im_push(h, k_h, k_d, 2 * (int64_t)nlr);
+      lm_push(h, so_h, so_d, 2 * (int64_t)nlr);
+      lm_push(h, do_h, do_d, 2 * (int64_t)nlr);
+      HIPCHK(launch_batched_copy(h->Ybuf, nb, so_d, h->arena, nb, do_d, m_d, k_d, maxe, nlr, h->s));
+      HIPCHK(launch_batched_copy(h->Q1, nb, so_d + nlr, h->arena, nb, do_d + nlr, m_d + nlr, k_d + nlr, maxe, nlr,
+                                 h->s));
+    }
+    prof_add(h, TLR_K_COMPRESS, e_c, 0.0, 0.0);
+  }
+  family_upload(h, F);
+  sync(h);
+  F.done_kind = 2;
+  rank_stats(h);
+  h->state = 1;
+  (void)cflops;
+}
+
 }  // namespace tlri

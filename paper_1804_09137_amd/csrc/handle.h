@@ -10,6 +10,7 @@
 #include "compress.h"
 #include "solve.h"
 #include "grad.h"
+#include "aca.h"
 #include <algorithm>
 #include <chrono>
 #include <functional>
@@ -175,6 +176,8 @@ struct tlr_handle_s {
   double* lrtws = nullptr;  // nt x kLrMaxRank: the low-rank apply's t = B^T v per tile
   double* gbuf = nullptr;   // -(W_i^T Q1_i) of a folded column's tiles, gbuf_cap doubles
   int64_t gbuf_cap = 0;
+  AcaTask* aca_d = nullptr;  // gcap ACA task records (tlr_compress with TLR_FLAG_ACA)
+  AcaTask* aca_h = nullptr;
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags
   int* qr_h = nullptr;
   // FP32-product check (TLR_PREC_FP32_UPDATES handles): per diagonal tile j,
@@ -263,6 +266,7 @@ bool fp32_check_fails(tlr_handle_s* h, double ll);
 void solve_forward(tlr_handle_s* h, const double* z, double* logdet, double* quad);
 void solve_backward(tlr_handle_s* h);
 void compress_sigma(tlr_handle_s* h);
+void compress_sigma_aca(tlr_handle_s* h);
 void arena_alloc(tlr_handle_s* h, int64_t cap);
 void arena_grow(tlr_handle_s* h);
 void family_reset(tlr_handle_s* h, Family& F, int kind);
