@@ -86,7 +86,8 @@ typedef enum {
 #define TLR_FLAG_ACA 4          /* tlr_compress compresses each tile by adaptive cross approximation with
                                    partial pivoting, fused with its generation (only the rows and columns
                                    it visits are generated; Section V lists ACA among the methods), and
-                                   stops after two consecutive terms with ||u|| ||v|| <= tol / 10.  Its
+                                   stops after two consecutive terms with ||u|| ||v|| <= tol / 10 (both
+                                   dropped).  Its
                                    error is estimated by those terms, not bounded as the default
                                    randomized range finder's is; ranks come out a little higher than
                                    the SVD's */
@@ -146,6 +147,11 @@ typedef struct {
   int32_t arena_grows;        /* TLR, arena_bytes = 0: times the tile storage was doubled */
   int32_t splitk_launches;    /* GEMM launches of the last factorisation that split their K range
                                  over several workgroups (long inner dimension, few output tiles) */
+  int32_t qr_tiles_reg;       /* TLR: tiles of the last factorisation whose truncation (pivoted QR of
+                                 the t1 x t1 factor) ran in registers (t1 <= 192), */
+  int32_t qr_tiles_lds;       /*   in registers plus LDS (192 < t1 <= 224), */
+  int32_t qr_tiles_global;    /*   in global memory (t1 > 224) */
+  int32_t reserved_info;      /* 0 */
   double fp32_err_bound;      /* TLR_PREC_FP32_UPDATES: estimated |l_FP32 - l_FP64| / |l| of the last
                                  log-likelihood computed from a factor with FP32 products (see
                                  TLR_PREC_FP32_UPDATES); 0 when the factor used FP64 products */

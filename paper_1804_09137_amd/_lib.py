@@ -49,6 +49,8 @@ class Info(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("t_grad_ms", ctypes.c_double),
                 ("tile_bytes_used", ctypes.c_int64), ("tile_bytes_cap", ctypes.c_int64),
                 ("arena_grows", ctypes.c_int32), ("splitk_launches", ctypes.c_int32),
+                ("qr_tiles_reg", ctypes.c_int32), ("qr_tiles_lds", ctypes.c_int32),
+                ("qr_tiles_global", ctypes.c_int32), ("reserved_info", ctypes.c_int32),
                 ("fp32_err_bound", ctypes.c_double)]
 
 

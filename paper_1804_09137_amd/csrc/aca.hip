@@ -9,9 +9,10 @@
 //   column   u_k = A[:, j*] - sum_{l<k} U[:, l] V[j*, l]
 //   next row i* = argmax |u_k,i| over unused rows
 // so that A ~ U V^T.  The stop is absolute (the threshold of Section V is):
-// two consecutive terms with ||u_k|| ||v_k|| <= tau, a zero residual on every
-// row tried, or k = kmax (then *rank = kmax + 1: the tile needs more).  One
-// 256-thread workgroup per tile; the current row and column live in LDS.
+// two consecutive terms with ||u_k|| ||v_k|| <= tau (both then dropped), a
+// zero residual on every row tried, or k = kmax (then *rank = kmax + 1: the
+// tile needs more).  One 256-thread workgroup per tile; the current row and
+// column live in LDS.
 #include "kernels.h"
 #include "matern.h"
 #include "aca.h"
@@ -155,7 +156,9 @@ __global__ void __launch_bounds__(kAcaThreads) aca_kernel(MaternParams p, const 
     if (nxt >= m || dummy < 0.0) break;   // every row used
     ist = nxt;
   }
-  if (tid == 0) *t.rank = (k >= kmax && small < 2) ? kmax + 1 : k;
+  // the trailing terms below tau are dropped (at most two, each of spectral
+  // norm ||u|| ||v|| <= tau)
+  if (tid == 0) *t.rank = (k >= kmax && small < 2) ? kmax + 1 : k - small;
 }
 
 hipError_t launch_aca(const MaternParams& p, const double* x, const double* y, const AcaTask* d_tasks, int count,

@@ -116,6 +116,8 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         F.uoff.assign((size_t)nt * nt, 0);
         F.voff.assign((size_t)nt * nt, 0);
         F.isdense.assign((size_t)nt * nt, 0);
+        F.dense_meas.assign((size_t)nt * nt, 0);
+        F.dense_meas_prev.assign((size_t)nt * nt, 0);
         F.rk_d = dalloc<int>(h, nt * nt);
         F.uoff_d = dalloc<int64_t>(h, nt * nt);
         F.voff_d = dalloc<int64_t>(h, nt * nt);
@@ -319,6 +321,7 @@ tlr_status tlr_loglik(tlr_handle_t h, const double* d_z, double* ll, double* log
       if (h->state != 2 || !fp32_check_fails(h, l)) break;
       // the FP32 products cannot be shown to hold the tolerance: factor again in FP64
       ++h->info.fp64_retries;
+      drop_history(h);
       int64_t info = 0;
       const tlr_status st = factor_checked(h, false, &info);
       if (st != TLR_OK) return st;
@@ -479,6 +482,7 @@ tlr_status loglik_grad_impl(tlr_handle_t h, const double* d_x, const double* d_y
       }
       // the FP32 products cannot be shown to hold the tolerance: factor again in FP64
       ++h->info.fp64_retries;
+      drop_history(h);
     }
     HIPCHK(hipEventRecord(h->ev[3], h->s));
     const size_t e_q = prof_mark(h);

@@ -301,16 +301,25 @@ void family_reset(tlr_handle_s* h, Family& F, int kind) {
   if (F.done_kind == kind) {
     F.r1_prev.swap(F.r1);
     F.rk_prev = F.rk;
+    F.dense_meas_prev.swap(F.dense_meas);
     F.hist = true;
   } else {
     F.hist = false;
   }
+  std::fill(F.dense_meas.begin(), F.dense_meas.end(), 0);
   F.done_kind = 0;
   std::fill(F.rk.begin(), F.rk.end(), 0);
   std::fill(F.r1.begin(), F.r1.end(), 0);
   std::fill(F.isdense.begin(), F.isdense.end(), 0);
   std::fill(F.uoff.begin(), F.uoff.end(), 0);
   std::fill(F.voff.begin(), F.voff.end(), 0);
+}
+
+// The next pass predicts from neighbouring tiles only (used when a factor is
+// computed again with FP64 products: the FP32 pass's ranks carry its rounding).
+void drop_history(tlr_handle_s* h) {
+  h->fam[0].done_kind = 0;
+  h->fam[1].done_kind = 0;
 }
 
 // device copies of the rank and offset tables (for the solves)
@@ -372,6 +381,7 @@ void throw_if_not_spd(tlr_handle_s* h) {
 struct RankPred {
   std::vector<int> k, r1;
   bool hist = false;   // from the same tiles of the previous factorisation (else from neighbours)
+  std::vector<char> meas;   // with history: the tile was found dense by its measured rank last time
 };
 
 // ---------------------------------------------------------------------------
@@ -502,17 +512,20 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     h->bad_j = jobs[jof[g]].col;
     throw Fail{TLR_ERANK};
   };
-  std::vector<char> dense(G, 0);
+  std::vector<char> dense(G, 0), early(G, 0);
   std::vector<int> sz(G), t1(G, 0), todo;
   int rounds = 0;
   for (int g = 0; g < G; ++g) {
     const RankPred& pred = jobs[jof[g]].pred;
     const int t = tloc[g];
-    // kept dense at once only when the same tile was dense in the previous
-    // factorisation: a prediction from the neighbouring tiles would carry a
-    // dense tile on to every later tile of its row
-    if (!h->strict && pred.hist && pred.k[t] > maxrank) {
+    // kept dense at once only when the same tile was found dense by its
+    // measured rank in the previous factorisation: a prediction from the
+    // neighbouring tiles would carry a dense tile on to every later tile of
+    // its row, and a tile kept dense at once is measured again next time (theta
+    // moves, and its rank may come back under maxrank)
+    if (!h->strict && pred.hist && pred.k[t] > maxrank && pred.meas[t]) {
       dense[g] = 1;
+      early[g] = 1;
       t1[g] = pred.r1[t];
       continue;
     }
@@ -726,6 +739,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     for (int q = 0; q < L; ++q) {
       const int g = lr[q];
       const bool small = t1[g] <= kRegQrBig;
+      ++h->qr_class[t1[g] <= kRegQrMax ? 0 : (small ? 1 : 2)];
       QrcpTask& tk = h->tk_h[small ? qs++ : qb++];
       tk = QrcpTask{};
       tk.m = t1[g];
@@ -908,6 +922,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     const int i = jb.i_first + tloc[g];
     const size_t id = tid_of(h, i, jb.col);
     F.isdense[id] = dense[g];
+    F.dense_meas[id] = dense[g] && !early[g];
     F.r1[id] = t1[g];
     if (dense[g]) {
       F.rk[id] = ncols;
@@ -1504,12 +1519,14 @@ RankPred predict_ranks(const tlr_handle_s* h, const Family& F, int j, int T) {
   RankPred p;
   p.k.resize(T);
   p.r1.resize(T);
+  p.meas.assign(T, 0);
   p.hist = F.hist;
   for (int t = 0; t < T; ++t) {
     const int i = j + 1 + t;
     if (F.hist) {
       p.k[t] = F.rk_prev[tid_of(h, i, j)];
       p.r1[t] = F.r1_prev[tid_of(h, i, j)];
+      p.meas[t] = F.dense_meas_prev[tid_of(h, i, j)];
     } else if (j > 0) {
       p.k[t] = std::max(F.rk[tid_of(h, i - 1, j - 1)], F.rk[tid_of(h, i, j - 1)]);
       p.r1[t] = std::max(F.r1[tid_of(h, i - 1, j - 1)], F.r1[tid_of(h, i, j - 1)]);
@@ -1578,6 +1595,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   family_reset(h, h->fam[1], 1);
   h->tile_used = 0;
   h->tile_overflow = false;
+  h->qr_class[0] = h->qr_class[1] = h->qr_class[2] = 0;
   sync(h);
   meta_reset(h);
   h->im2_use = h->lm2_use = 0;   // the side stream's staging set (idle after the sync)
@@ -2025,6 +2043,7 @@ tlr_status factor_checked(tlr_handle_s* h, bool tangent, int64_t* info) {
       st = check_info(h, info);
     }
     if (st != TLR_ENOTSPD || h->upd_tag != 2) return st;
+    drop_history(h);
     h->upd_tag = 1;
     h->info.prec_used = TLR_PREC_FP64;
     ++h->info.fp64_retries;
@@ -2051,6 +2070,9 @@ void rank_stats(tlr_handle_s* h) {
   h->info.tile_bytes_used = h->tile_used * (int64_t)sizeof(double);
   h->info.tile_bytes_cap = h->tile_cap * (int64_t)sizeof(double);
   h->info.arena_grows = h->arena_grows;
+  h->info.qr_tiles_reg = h->qr_class[0];
+  h->info.qr_tiles_lds = h->qr_class[1];
+  h->info.qr_tiles_global = h->qr_class[2];
   h->info.device_bytes = h->bytes;
 }
 

@@ -106,6 +106,7 @@ struct tlr_handle_s {
   bool tile_overflow = false;            // the last failure was the tile storage running out
   int arena_grows = 0;
   int splitk_count = 0;                  // split-K GEMM launches of the running factorisation
+  int qr_class[3] = {0, 0, 0};           // truncation QRs by size class (registers, + LDS, global)
   struct Family {
     std::vector<int> rk;                 // nt*nt (i * nt + j)
     std::vector<int> r1;                 // range-finder ranks (sketch width prediction)
@@ -114,6 +115,7 @@ struct tlr_handle_s {
     int done_kind = 0;                   // what the last finished pass computed: 1 factor, 2 compression of Sigma
     std::vector<int64_t> uoff, voff;     // arena offsets of U_ij, V_ij
     std::vector<char> isdense;
+    std::vector<char> dense_meas, dense_meas_prev;   // dense by a measured rank (not decided early), this / last pass
     int* rk_d = nullptr;
     int64_t* uoff_d = nullptr;
     int64_t* voff_d = nullptr;
@@ -270,6 +272,7 @@ void compress_sigma_aca(tlr_handle_s* h);
 void arena_alloc(tlr_handle_s* h, int64_t cap);
 void arena_grow(tlr_handle_s* h);
 void family_reset(tlr_handle_s* h, Family& F, int kind);
+void drop_history(tlr_handle_s* h);
 void family_upload(tlr_handle_s* h, Family& F);
 int lr_kmax(const tlr_handle_s* h, int j, bool col);
 double* panel(tlr_handle_s* h, double* base, int j);

@@ -333,29 +333,51 @@ def test_ill_conditioned_field_no_worse_than_oracle_tlr():
     assert e_gpu <= max(10 * eps, 2.0 * e_or)
 
 
-def test_pivoted_qr_size_classes(monkeypatch, capfd):
+def test_pivoted_qr_size_classes():
     # n = 6400 in tiles of 800 at eps = 1e-7: the primal tiles next to the
     # diagonal have range ranks t1 just above 192 (pivoted QR in registers
     # plus LDS), the tangent ones above 224 (pivoted QR in global memory), the
-    # rest below 192 (all in registers).  The library's per-column debug lines
-    # show which classes ran; the results match the oracle and the dense path.
-    import re
+    # rest below 192 (all in registers).  The library counts the tiles of each
+    # class; the results match the oracle and the dense path.
     import paper_1804_09137_amd as P
     n, nb, eps = 6400, 800, 1e-7
     th = (1.0, 0.1, 0.5)
     x, y, z = field(n, 0, th)
     ref = D.loglik(x, y, z, th)
     xd, yd, zd = to_dev(x, y, z)
-    monkeypatch.setenv("TLR_DEBUG", "1")
     h = _handle(n, nb, tol=eps, maxrank=nb // 2, want_grad=True)
-    monkeypatch.delenv("TLR_DEBUG")
     ll, g = h.loglik_grad(xd, yd, zd, th)
-    err = capfd.readouterr().err
-    t1 = [int(v) for v in re.findall(r"t1<=(\d+)", err)]
-    log(f"columns {len(t1)}, largest t1 per column {sorted(t1)}")
-    assert any(v <= 192 for v in t1) and any(192 < v <= 224 for v in t1) and any(v > 224 for v in t1)
+    i = h.info()
+    log(f"truncation QRs: registers {i.qr_tiles_reg}, registers + LDS {i.qr_tiles_lds}, global {i.qr_tiles_global}")
+    assert i.qr_tiles_reg > 0 and i.qr_tiles_lds > 0 and i.qr_tiles_global > 0
     hd = _handle(n, 320, mode="dense", want_grad=True)
     lld, gd = hd.loglik_grad(xd, yd, zd, th)
     log(f"ll rel {abs(ll - ref['ll']) / abs(ref['ll']):.2e}, grad {g} vs dense {gd}")
     assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
     assert abs(g[0] - gd[0]) <= 1e-5 * abs(gd[0]) and abs(g[1] - gd[1]) <= 1e-5 * abs(gd[1])
+
+
+@pytest.mark.parametrize("aca", [False, True])
+def test_compress_exact_rank_tiles(aca):
+    # the first 128 locations are 5 distinct points repeated, so every tile
+    # (i, 0) below the diagonal has exactly 5 distinct columns: rank 5 up to
+    # rounding.  The compressor (randomized range finder + pivoted QR, or ACA)
+    # must find rank 5 and reproduce the tile; Sigma itself is singular, which
+    # tlr_compress (no factorisation) does not mind.
+    import synth
+    n, nb, eps = 512, 128, 1e-9
+    th = (1.0, 0.2, 1.0)
+    x, y = synth.jittered_subset(n, 5)
+    x[:nb] = np.tile(x[:5], nb // 5 + 1)[:nb]
+    y[:nb] = np.tile(y[:5], nb // 5 + 1)[:nb]
+    h = _handle(n, nb, tol=eps, maxrank=100, aca=aca)
+    xd, yd = to_dev(x, y)
+    h.generate(xd, yd, th)
+    h.compress()
+    R = h.ranks()
+    log(f"aca={aca}: ranks of tile column 0: {R[1:, 0].tolist()}")
+    for i in range(1, n // nb):
+        assert R[i, 0] == 5, (i, R[i, 0])
+        A = M.covariance(x, y, th, slice(i * nb, (i + 1) * nb), slice(0, nb))
+        T = h.tile(i, 0).cpu().numpy()
+        assert np.linalg.norm(A - T, 2) <= eps
