@@ -91,6 +91,12 @@ typedef enum {
                                    error is estimated by those terms, not bounded as the default
                                    randomized range finder's is; ranks come out a little higher than
                                    the SVD's */
+#define TLR_FLAG_PIVOTED_TRUNC 8 /* truncate each tile's projection by column-pivoted QR of its t1 x t1 R
+                                   factor (rank: the first step whose unreduced block has Frobenius
+                                   norm <= 0.8 tol).  By default the unpivoted R is truncated directly
+                                   (rank: the smallest k with ||R[k:, k:]||_F <= 0.8 tol): the basis
+                                   from the QR of the random sketch already comes ordered by energy,
+                                   and the ranks are the same or one or two higher */
 #define TLR_FLAG_STRICT_RANK 1  /* a tile needing rank > maxrank is an error (TLR_ERANK) instead of
                                    being kept dense */
 #define TLR_FLAG_SINGLE_STREAM 2 /* TLR with want_grad: issue everything on the caller's stream.  By

@@ -56,7 +56,7 @@ class Handle:
     def __init__(self, n: int, nb: int, tol: float = 1e-9, maxrank: int = 0, mode: str = "tlr",
                  prec: str = "fp64", want_grad: bool = False, seed: int = 0, strict_rank: bool = False,
                  stream=None, single_stream: bool = False, arena_bytes: int = 0, metric: str = "euclid",
-                 sphere_radius: float = 0.0, aca: bool = False):
+                 sphere_radius: float = 0.0, aca: bool = False, pivoted_trunc: bool = False):
         import torch
         self._lib = _lib.load()
         o = _lib.Opts()
@@ -66,7 +66,7 @@ class Handle:
         o.want_grad = 1 if want_grad else 0
         o.seed = int(seed)
         o.flags = ((_lib.FLAG_STRICT_RANK if strict_rank else 0) | (_lib.FLAG_SINGLE_STREAM if single_stream else 0)
-                   | (_lib.FLAG_ACA if aca else 0))
+                   | (_lib.FLAG_ACA if aca else 0) | (_lib.FLAG_PIVOTED_TRUNC if pivoted_trunc else 0))
         o.arena_bytes = int(arena_bytes)
         o.metric = {"euclid": 0, "great_circle": 1}[metric]
         o.sphere_radius = float(sphere_radius)

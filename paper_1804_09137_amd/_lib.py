@@ -28,6 +28,7 @@ PREC_FP32_UPDATES = 1
 FLAG_STRICT_RANK = 1
 FLAG_SINGLE_STREAM = 2
 FLAG_ACA = 4
+FLAG_PIVOTED_TRUNC = 8
 
 _NAMES = {0: "TLR_OK", 1: "TLR_ENOTSPD", -1: "TLR_EINVAL", -2: "TLR_ENOMEM", -3: "TLR_EHIP",
           -4: "TLR_ERANK", -5: "TLR_ENOTIMPL", -6: "TLR_ESTATE"}

@@ -44,6 +44,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     mr = std::min(mr, kQrMaxCols - 96);
     h->maxrank = mr;
     h->strict = (o->flags & TLR_FLAG_STRICT_RANK) != 0;
+    h->pivoted_trunc = (o->flags & TLR_FLAG_PIVOTED_TRUNC) != 0;
     // TLR gradient handles run the tangent chain and the diagonal steps on
     // streams of their own unless asked for one stream
     h->multi = h->grad && !h->dense && !(o->flags & TLR_FLAG_SINGLE_STREAM);
@@ -72,7 +73,9 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
     h->scal = dalloc<double>(h, 4 * nt + 16);
     h->h_scal = halloc<double>(h, 4 * nt + 16);
     h->info_d = dalloc<unsigned long long>(h, 1);
-    h->h_info = halloc<unsigned long long>(h, 1);
+    h->h_info = halloc_coherent<unsigned long long>(h, 1, &h->h_info_d);
+    h->pub_seq_h = halloc_coherent<unsigned>(h, 1, &h->pub_seq_d);
+    *h->pub_seq_h = 0;
     h->sk_cap = std::min<int64_t>(16ll << 20, 32 * std::max<int64_t>(n, 1024) * nb);
     h->skw = dalloc<double>(h, h->sk_cap);
     if (h->dense) {
@@ -210,7 +213,7 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         h->gbuf = dalloc<double>(h, h->gbuf_cap);
       }
       h->qr_d = dalloc<int>(h, 2 * gc);
-      h->qr_h = halloc<int>(h, 2 * gc);
+      h->qr_h = halloc_coherent<int>(h, 2 * gc, &h->qr_hd);
       h->aca_d = dalloc<AcaTask>(h, gc);
       h->aca_h = halloc<AcaTask>(h, gc);
       if (o->prec == TLR_PREC_FP32_UPDATES) {

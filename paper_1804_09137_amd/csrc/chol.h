@@ -20,6 +20,10 @@ hipError_t launch_identity(double* A, int64_t lda, int64_t m, hipStream_t s);
 hipError_t launch_sqdiff_acc(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t m, int64_t ncol,
                              double* acc, hipStream_t s);
 hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s);
+// n ints src -> dst and (w_src non-null) one word w_src -> w_dst, then *flag =
+// seq (system-scope release); dst, w_dst and flag are fine-grained host memory
+hipError_t launch_publish(const int* src, int n, int* dst, const unsigned long long* w_src, unsigned long long* w_dst,
+                          unsigned* flag, unsigned seq, hipStream_t s);
 
 // Lower Cholesky of the m x m tile T (column-major, ld) in place, blocked
 // left-looking with 64-wide blocks; writes the inverse factor to Inv (ldi) and

@@ -266,6 +266,26 @@ hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, 
   return hipGetLastError();
 }
 
+// Copy n ints (and optionally one 64-bit word) into fine-grained host memory,
+// then store seq to *flag with release semantics at system scope: a host that
+// reads *flag == seq (acquire) then sees the copied values.  One workgroup.
+__global__ void __launch_bounds__(256) publish_kernel(const int* __restrict__ src, int n, int* dst,
+                                                      const unsigned long long* __restrict__ w_src,
+                                                      unsigned long long* w_dst, unsigned* flag, unsigned seq) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
+  if (threadIdx.x == 0 && w_src) *w_dst = *w_src;
+  __threadfence_system();   // each thread's stores complete at system scope before the flag
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_publish(const int* src, int n, int* dst, const unsigned long long* w_src, unsigned long long* w_dst,
+                          unsigned* flag, unsigned seq, hipStream_t s) {
+  if (n < 0 || (n > 0 && (!src || !dst)) || !flag || (w_src && !w_dst)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(256), 0, s, src, n, dst, w_src, w_dst, flag, seq);
+  return hipGetLastError();
+}
+
 }  // namespace tlrk
 
 namespace tlrk {

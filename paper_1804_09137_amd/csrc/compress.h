@@ -53,6 +53,14 @@ struct HqrTask {
   int xrows;        // apply (identity == 0): rows >= xrows of X are cleared first
   int identity;     // apply: X starts as [I_kx; 0]
   const double* tau;   // wy_build: the s reflector scalars
+  // factor, trunc != 0 (with tol > 0): rank = the smallest k with
+  // ||R[k:, k:]||_F <= tol instead of the range rank, flag = 0, and the rows
+  // of R written out transposed: Z[c + r ldz] = R[r, c] for c >= r, 0 for
+  // c < r, over r < min(min(m, s), zcap) and c < s.
+  int trunc;
+  int zcap;
+  double* Z;
+  int64_t ldz;
 };
 
 hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s, int max_m = kQrMaxRows);

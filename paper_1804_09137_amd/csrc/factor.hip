@@ -109,19 +109,37 @@ struct DiagStream {
   ~DiagStream() { h->s = h->s_main; }
 };
 
-// The compression's host waits for the rank read-backs.  A handle with the
-// look-ahead streams polls the stream (the wait is on its critical path, and
-// a blocking wait adds the wake-up latency to every step); single-stream
-// handles, which run many to a process, block.
+// The compression's rank read-backs: a kernel copies the ranks (and with
+// info the SPD word) into fine-grained host memory and then stores a new
+// sequence number there (system-scope release).
+void rank_publish(tlr_handle_s* h, int n, bool info) {
+  const unsigned seq = ++h->pub_seq;
+  HIPCHK(launch_publish(h->qr_d, n, h->qr_hd, info ? h->info_d : nullptr, h->h_info_d, h->pub_seq_d, seq, h->s));
+}
+
+// The host waits for the last publish.  A handle with the look-ahead streams
+// spins on the sequence number (the wait is on its critical path; the
+// completion status of the stream itself reaches the host up to milliseconds
+// late while three queues retire short kernels), checking the stream for
+// errors now and then; single-stream handles, which run many to a process,
+// block.
 void rank_wait(tlr_handle_s* h) {
   if (!h->multi) {
     HIPCHK(hipStreamSynchronize(h->s));
     return;
   }
-  for (;;) {
-    const hipError_t e = hipStreamQuery(h->s);
-    if (e == hipSuccess) return;
-    if (e != hipErrorNotReady) HIPCHK(e);
+  const unsigned want = h->pub_seq;
+  for (uint64_t it = 1;; ++it) {
+    if (__atomic_load_n(h->pub_seq_h, __ATOMIC_ACQUIRE) == want) return;
+    if ((it & 4095) == 0) {
+      const hipError_t e = hipStreamQuery(h->s);
+      if (e == hipSuccess) {
+        // the stream is idle, so the publish kernel has run
+        if (__atomic_load_n(h->pub_seq_h, __ATOMIC_ACQUIRE) == want) return;
+        HIPCHK(hipErrorLaunchFailure);
+      }
+      if (e != hipErrorNotReady) HIPCHK(e);
+    }
   }
 }
 
@@ -453,6 +471,8 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   // of the discarded block) <= tol in the spectral norm
   const double tol_range = 0.1 * tol;
   const double tol_trunc = 0.8 * tol;
+  const bool piv = h->pivoted_trunc;
+  std::chrono::steady_clock::time_point t_after_wait{};
   HqrTask* hq_fy = h->hq_h;            // factor Y (synchronised per round)
   HqrTask* hq_ay = h->hq_h + gc;       // Q1 = Q_y [I; 0]
   HqrTask* hq_fb = h->hq_h + 2 * gc;   // factor B^T
@@ -647,8 +667,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       });
     }
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
-    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, 2 * (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
-    HIPCHK(hipMemcpyAsync(h->h_info, h->info_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->s));
+    rank_publish(h, 2 * gc, true);
     auto h0 = std::chrono::steady_clock::now();
     if (during && during[0]) {   // the host would otherwise wait here
       during[0]();
@@ -725,18 +744,28 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.m = ncols;
       tk.s = t1[g];
       tk.T = h->Tw + (int64_t)g * h->tw_stride;
+      if (!piv) {
+        // the truncation rank and Z = R_b[:k, :]^T come with the factor
+        tk.tol = tol_trunc;
+        tk.trunc = 1;
+        tk.rank = h->qr_d + g;
+        tk.flag = h->qr_d + gc + g;
+        tk.Z = h->Zb + (int64_t)g * h->smax * (maxrank + 1);
+        tk.ldz = h->smax;
+        tk.zcap = maxrank + 1;
+      }
       cflops += 2.0 * ncols * t1[g] * t1[g];
     }
-    // truncation by pivoted QR of R_b (t1 x t1): Z = Pi R_r[:k, :]^T.  Small
-    // factors stay on chip (reflectors into the Y workspace, which Q1 no
-    // longer needs; Q_r is formed afterwards); larger ones are copied out and
-    // pivoted in place, Q_r into Vtmp.
+    // TLR_FLAG_PIVOTED_TRUNC: truncation by pivoted QR of R_b (t1 x t1): Z =
+    // Pi R_r[:k, :]^T.  Small factors stay on chip (reflectors into the Y
+    // workspace, which Q1 no longer needs; Q_r is formed afterwards); larger
+    // ones are copied out and pivoted in place, Q_r into Vtmp.
     std::vector<int> big;
     int nsmall = 0;
-    for (int q = 0; q < L; ++q)
+    for (int q = 0; q < L && piv; ++q)
       if (t1[lr[q]] <= kRegQrBig) ++nsmall;
     int qs = 0, qb = nsmall;
-    for (int q = 0; q < L; ++q) {
+    for (int q = 0; q < L && piv; ++q) {
       const int g = lr[q];
       const bool small = t1[g] <= kRegQrBig;
       ++h->qr_class[t1[g] <= kRegQrMax ? 0 : (small ? 1 : 2)];
@@ -769,7 +798,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     }
     // regions 1 and 2 (Q1, B^T) in one upload, then the truncation tasks
     HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, (gc + L) * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
-    HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
+    if (piv) HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
     const int nbg = (int)big.size();
     // A folded job's tiles lead lr (job 0 holds the lowest slots).  Their
     // projection is C^T Q1 - U (W^T Q1): G = -(W^T Q1) first, then a second
@@ -886,10 +915,12 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       if (L > nf) gemm(h, ncols, maxn, 1, sg, h->Bt, nb, epi_linear(1.0, 0.0), &btr, false, 128, 32, m_h + nf, n_h + nf);
     }
     HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
-    if (nbg > 0) HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
-    HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
-    HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
-    HIPCHK(hipMemcpyAsync(h->qr_h, h->qr_d, (size_t)gc * sizeof(int), hipMemcpyDeviceToHost, h->s));
+    if (piv) {
+      if (nbg > 0) HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
+      HIPCHK(launch_qrcp_reg(h->tk_d, nsmall, h->s));
+      HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
+    }
+    rank_publish(h, gc, false);
     auto h0 = std::chrono::steady_clock::now();
     if (during && during[1]) {
       during[1]();
@@ -901,6 +932,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       const auto h2 = std::chrono::steady_clock::now();
       h->host_ms[2] += std::chrono::duration<double, std::milli>(h1 - h0).count();
       h->host_ms[3] += std::chrono::duration<double, std::milli>(h2 - h1).count();
+      t_after_wait = h2;
     }
     meta_reset(h);
     for (int q = 0; q < L; ++q) {
@@ -965,7 +997,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     // workspace) and scalars
     int nq = 0, max_k = 0;
     for (int g = 0; g < G; ++g) {
-      if (dense[g] || k2[g] == 0 || t1[g] > kRegQrBig) continue;
+      if (!piv || dense[g] || k2[g] == 0 || t1[g] > kRegQrBig) continue;
       HqrTask& tw = hq_wr[nq];
       tw = HqrTask{};
       tw.A = h->Ybuf + (int64_t)g * nb * h->smax;
@@ -1000,10 +1032,16 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       tk.ldx = nb;
       tk.kx = k2[g];
       tk.xrows = t1[g];
+      tk.identity = piv ? 0 : 1;   // [Q_r; 0] (pivoted) or [I_k; 0]
     }
     // regions 3 (V~), 4 and 5 (Q_r) in one upload, before the launches
+    const auto u0 = std::chrono::steady_clock::now();
     HIPCHK(hipMemcpyAsync(h->hq_d + 3 * gc, hq_ab, (nq > 0 ? 2 * (size_t)gc + nq : (size_t)nlr) * sizeof(HqrTask),
                           hipMemcpyHostToDevice, h->s));
+    if (h->debug && t_after_wait.time_since_epoch().count() != 0) {
+      h->host_ms[4] += std::chrono::duration<double, std::milli>(u0 - t_after_wait).count();
+      h->host_ms[5] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - u0).count();
+    }
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, nlr, &m_d);
     int* n_h = im_take(h, nlr, &n_d);
@@ -1041,6 +1079,8 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     sg.B = op_contigT(h->Zb, h->smax, 0, 0);
     sg.K = h->smax;
     gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+    if (h->debug)
+      h->host_ms[6] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - u0).count();
   }
   // dense tiles: copy the tile into its block
   if (ndense > 0) {
@@ -1882,6 +1922,15 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         rest_wait();
         HIPCHK(hipEventRecord(h->ev_join, h->s));
       }
+      // the diagonal step of primal column j + 1 on its own stream, behind the
+      // tangent's rows there: only the triangular solves after the
+      // compression need it, and issued here it runs beside the compression
+      if (j + 1 < nt) {
+        DiagStream ds(h);
+        HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
+        primal_diag(j + 1);
+        HIPCHK(hipEventRecord(h->ev_diag, h->s));
+      }
       // each column is sketched as soon as it is complete: the primal one on
       // the main stream, the tangent one on the side stream after its chain
       std::vector<ColumnJob> jobs;
@@ -1892,31 +1941,23 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       jobs.push_back(tangent_job(j));
       jobs.back().wait = h->ev_join;
       jobs.back().sketch_stream = h->s_side;
-      // The compressions of step j are issued first.  The host issues the pre
+      // The compressions of step j are issued first; the host issues the pre
       // parts of step j + 1 (side stream) in its first wait, for the range
-      // ranks, and the diagonal step of primal column j + 1 (its own stream;
-      // only the triangular solves after the compression need it) in its
-      // second wait, for the truncation ranks.
-      finish(
-          jobs, j + 1 < nt,
-          [&]() {
-            if (j + 1 < nt) pre(j + 1);
-          },
-          [&]() {
-            if (j + 1 >= nt) return;
-            DiagStream ds(h);
-            HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
-            primal_diag(j + 1);
-            HIPCHK(hipEventRecord(h->ev_diag, h->s));
-          });
+      // ranks.
+      finish(jobs, j + 1 < nt, [&]() {
+        if (j + 1 < nt) pre(j + 1);
+      });
       HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
     }
   }
   family_upload(h, P);
   sync(h);
   if (h->debug) {
-    std::fprintf(stderr, "[tlr] host ms: issue in wait 1 %.1f, wait 1 %.1f, issue in wait 2 %.1f, wait 2 %.1f\n",
-                 h->host_ms[0], h->host_ms[1], h->host_ms[2], h->host_ms[3]);
+    std::fprintf(stderr,
+                 "[tlr] host ms: issue in wait 1 %.1f, wait 1 %.1f, issue in wait 2 %.1f, wait 2 %.1f, "
+                 "wait 2 to upload %.1f, upload %.1f, upload to last launch %.1f\n",
+                 h->host_ms[0], h->host_ms[1], h->host_ms[2], h->host_ms[3], h->host_ms[4], h->host_ms[5],
+                 h->host_ms[6]);
     for (double& v : h->host_ms) v = 0.0;
   }
   P.done_kind = 1;

@@ -63,7 +63,9 @@ struct tlr_handle_s {
   int gcap = 0;         // tile slots of the compression scratch
   int upd_tag = 1;      // column-update kernels of the running factorisation: 1 FP64, 2 FP32 products
   bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
-  double host_ms[4] = {0, 0, 0, 0};   // TLR_DEBUG: host time in the compressions' two waits and their callbacks
+  double host_ms[7] = {0, 0, 0, 0, 0, 0, 0};   // TLR_DEBUG: host time in the compressions' two waits and their
+                                               // callbacks, then after the second wait: bookkeeping, upload, launches
+  bool pivoted_trunc = false;   // TLR_FLAG_PIVOTED_TRUNC
   bool multi = false;   // side and diagonal streams (TLR gradient handles without TLR_FLAG_SINGLE_STREAM)
   bool dense = false, grad = false, strict = false;
   int64_t vslot = 0;     // doubles per V~ staging block (nb * (maxrank + 1)): the
@@ -181,7 +183,12 @@ struct tlr_handle_s {
   AcaTask* aca_d = nullptr;  // gcap ACA task records (tlr_compress with TLR_FLAG_ACA)
   AcaTask* aca_h = nullptr;
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags
-  int* qr_h = nullptr;
+  int* qr_h = nullptr;  // fine-grained host copy (rank_publish), device address qr_hd
+  int* qr_hd = nullptr;
+  unsigned long long* h_info_d = nullptr;   // device address of h_info (fine-grained)
+  unsigned* pub_seq_h = nullptr;            // last publish sequence number written by the device
+  unsigned* pub_seq_d = nullptr;
+  unsigned pub_seq = 0;                     // last one issued
   // FP32-product check (TLR_PREC_FP32_UPDATES handles): per diagonal tile j,
   // chk[2j] = ||A_jj - D~_jj||_F^2 (the update that reached the tile) and
   // chk[2j+1] = ||D_jj^{-1}||_F^2; chk_scr is one nb x nb scratch tile
@@ -234,15 +241,28 @@ T* dalloc(tlr_handle_s* h, int64_t count) {
 }
 
 template <class T>
-T* halloc(tlr_handle_s* h, int64_t count) {
+T* halloc(tlr_handle_s* h, int64_t count, unsigned flags = hipHostMallocDefault) {
   if (count <= 0) count = 1;
   void* p = nullptr;
-  if (hipHostMalloc(&p, (size_t)count * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&p, (size_t)count * sizeof(T), flags) != hipSuccess) {
     (void)hipGetLastError();
     throw Fail{TLR_ENOMEM};
   }
   h->host_allocs.push_back(p);
   return (T*)p;
+}
+// Fine-grained (coherent) host memory that kernels write and the host polls;
+// *dev receives the device address of the same bytes.
+template <class T>
+T* halloc_coherent(tlr_handle_s* h, int64_t count, T** dev) {
+  T* p = halloc<T>(h, count, hipHostMallocCoherent | hipHostMallocMapped);
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{TLR_ENOMEM};
+  }
+  *dev = (T*)d;
+  return p;
 }
 
 extern thread_local char g_last_error[256];

@@ -311,7 +311,82 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
     __syncthreads();
   }
 
-  if (tk.tol > 0.0) {
+  if (tk.tol > 0.0 && tk.trunc) {
+    // Truncation rank from the unpivoted R: dropping rows k.. of R leaves an
+    // error of ||R[k:, k:]||_F = sqrt(sum_{r >= k} ||R[r, r:]||^2).  One pass
+    // over the upper triangle (wave w: columns w, w + 8, ..; lane: rows
+    // lane + 64 i) gives the per-row partial sums and writes Z; the panel
+    // LDS, no longer needed, holds the partials of the 8 waves.
+    constexpr int RI = kQrMaxCols / 64;
+    constexpr int CB = 4;   // columns per batch of loads
+    double part[RI];
+#pragma unroll
+    for (int i = 0; i < RI; ++i) part[i] = 0.0;
+    const int zr = tk.Z ? (nref < tk.zcap ? nref : tk.zcap) : 0;
+    gdouble* Z = gptr(tk.Z);
+    for (int cb = w; cb < s; cb += NW * CB) {
+      double v[CB][RI];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int c = cb + NW * u;
+        const gdouble* ac = A + (int64_t)c * lda;
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+          const int r = lane + 64 * i;
+          v[u][i] = (64 * i < nref && c < s && r <= c && r < nref) ? ac[r] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int c = cb + NW * u;
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+          const int r = lane + 64 * i;
+          part[i] += v[u][i] * v[u][i];
+          if (64 * i < zr && c < s && r < zr) Z[(int64_t)r * tk.ldz + c] = v[u][i];
+        }
+      }
+    }
+    double* rs = P;   // [NW][kQrMaxCols]
+#pragma unroll
+    for (int i = 0; i < RI; ++i) rs[w * kQrMaxCols + lane + 64 * i] = part[i];
+    __syncthreads();
+    if (w == 0) {
+      // lane l scans rows 8l .. 8l + 7: suffix sums within the lane, then
+      // over the lanes above it
+      constexpr int RL = kQrMaxCols / 64;
+      double f[RL];
+#pragma unroll
+      for (int j = 0; j < RL; ++j) {
+        const int r = RL * lane + j;
+        double acc = 0.0;
+#pragma unroll
+        for (int v2 = 0; v2 < NW; ++v2) acc += rs[v2 * kQrMaxCols + r];
+        f[j] = r < nref ? acc : 0.0;
+      }
+#pragma unroll
+      for (int j = RL - 2; j >= 0; --j) f[j] += f[j + 1];
+      double suf = f[0];   // inclusive suffix over lanes >= lane
+      for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_down(suf, off, 64);
+        if (lane + off < 64) suf += o;
+      }
+      const double above = suf - f[0];
+      const double tol2 = tk.tol * tk.tol;
+      int k = 0;
+#pragma unroll
+      for (int j = 0; j < RL; ++j)
+        if (RL * lane + j < nref && f[j] + above > tol2) k = RL * lane + j + 1;
+      for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(k, off, 64);
+        k = o > k ? o : k;
+      }
+      if (lane == 0) {
+        if (tk.rank) *tk.rank = k;
+        if (tk.flag) *tk.flag = 0;
+      }
+    }
+  } else if (tk.tol > 0.0) {
     if (tid == 0) sh_t1 = 0;
     __syncthreads();
     const double tol2 = tk.tol * tk.tol;

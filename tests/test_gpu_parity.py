@@ -140,13 +140,15 @@ def test_tlr_tiny_threshold_equals_dense():
     assert abs(ll - ref) <= 1e-11 * abs(ref)
 
 
-def test_tlr_compress_meets_threshold():
+@pytest.mark.parametrize("pivoted", [False, True])
+def test_tlr_compress_meets_threshold(pivoted):
     # tlr_compress of Sigma itself: every tile within eps in the spectral
-    # norm; ranks compared with the oracle's SVD ranks.
+    # norm; ranks compared with the oracle's SVD ranks.  Both truncations:
+    # unpivoted R (default) and column-pivoted QR of R.
     n, nb, eps = 1600, 320, 1e-7
     th = (1.0, 0.1, 0.5)
     x, y, _ = field(n, 0, th, with_z=False)
-    h = _handle(n, nb, tol=eps, maxrank=200, strict_rank=True)
+    h = _handle(n, nb, tol=eps, maxrank=200, strict_rank=True, pivoted_trunc=pivoted)
     xd, yd = to_dev(x, y)
     h.generate(xd, yd, th)
     h.compress()
@@ -163,9 +165,9 @@ def test_tlr_compress_meets_threshold():
             over.append(R[i, j] - k_svd)
             assert err <= eps, (i, j, err)
             assert R[i, j] >= k_svd - 1
-    log(f"compress rank excess over SVD: {over}")
-    # the pivoted-QR truncation bounds the Frobenius norm of the discarded
-    # block, which is >= its spectral norm: a few more columns than the SVD
+    log(f"pivoted={pivoted}: compress rank excess over SVD: {over}")
+    # the truncation bounds the Frobenius norm of the discarded block, which
+    # is >= its spectral norm: a few more columns than the SVD
     assert max(over) <= 8
 
 
@@ -333,35 +335,50 @@ def test_ill_conditioned_field_no_worse_than_oracle_tlr():
     assert e_gpu <= max(10 * eps, 2.0 * e_or)
 
 
-def test_pivoted_qr_size_classes():
-    # n = 6400 in tiles of 800 at eps = 1e-7: the primal tiles next to the
-    # diagonal have range ranks t1 just above 192 (pivoted QR in registers
-    # plus LDS), the tangent ones above 224 (pivoted QR in global memory), the
-    # rest below 192 (all in registers).  The library counts the tiles of each
-    # class; the results match the oracle and the dense path.
+def test_pivoted_qr_size_classes_and_unpivoted_ranks():
+    # n = 6400 in tiles of 800 at eps = 1e-7.  With TLR_FLAG_PIVOTED_TRUNC the
+    # primal tiles next to the diagonal have range ranks t1 just above 192
+    # (pivoted QR in registers plus LDS), the tangent ones above 224 (pivoted
+    # QR in global memory), the rest below 192 (all in registers); the library
+    # counts the tiles of each class.  The default unpivoted truncation runs
+    # no pivoted QR and gives each tile the same rank or up to two more.  Both
+    # match the oracle and the dense path.
     import paper_1804_09137_amd as P
     n, nb, eps = 6400, 800, 1e-7
     th = (1.0, 0.1, 0.5)
     x, y, z = field(n, 0, th)
     ref = D.loglik(x, y, z, th)
     xd, yd, zd = to_dev(x, y, z)
-    h = _handle(n, nb, tol=eps, maxrank=nb // 2, want_grad=True)
-    ll, g = h.loglik_grad(xd, yd, zd, th)
-    i = h.info()
-    log(f"truncation QRs: registers {i.qr_tiles_reg}, registers + LDS {i.qr_tiles_lds}, global {i.qr_tiles_global}")
-    assert i.qr_tiles_reg > 0 and i.qr_tiles_lds > 0 and i.qr_tiles_global > 0
     hd = _handle(n, 320, mode="dense", want_grad=True)
     lld, gd = hd.loglik_grad(xd, yd, zd, th)
-    log(f"ll rel {abs(ll - ref['ll']) / abs(ref['ll']):.2e}, grad {g} vs dense {gd}")
-    assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
-    assert abs(g[0] - gd[0]) <= 1e-5 * abs(gd[0]) and abs(g[1] - gd[1]) <= 1e-5 * abs(gd[1])
+    ranks = {}
+    for piv in (True, False):
+        h = _handle(n, nb, tol=eps, maxrank=nb // 2, want_grad=True, pivoted_trunc=piv)
+        ll, g = h.loglik_grad(xd, yd, zd, th)
+        i = h.info()
+        log(f"pivoted={piv}: truncation QRs: registers {i.qr_tiles_reg}, registers + LDS {i.qr_tiles_lds}, "
+            f"global {i.qr_tiles_global}; rank sum {i.rank_sum}")
+        if piv:
+            assert i.qr_tiles_reg > 0 and i.qr_tiles_lds > 0 and i.qr_tiles_global > 0
+        else:
+            assert i.qr_tiles_reg == 0 and i.qr_tiles_lds == 0 and i.qr_tiles_global == 0
+        ranks[piv] = (h.ranks().copy(), h.tangent_ranks().copy())
+        log(f"ll rel {abs(ll - ref['ll']) / abs(ref['ll']):.2e}, grad {g} vs dense {gd}")
+        assert abs(ll - ref["ll"]) <= 10 * eps * abs(ref["ll"])
+        assert abs(g[0] - gd[0]) <= 1e-5 * abs(gd[0]) and abs(g[1] - gd[1]) <= 1e-5 * abs(gd[1])
+        h.close()
+    for f in range(2):
+        d = ranks[False][f].astype(int) - ranks[True][f].astype(int)
+        low = np.tril_indices(d.shape[0], -1)
+        log(f"factor {f}: unpivoted - pivoted rank: min {d[low].min()}, max {d[low].max()}")
+        assert d[low].min() >= -2 and d[low].max() <= 2
 
 
-@pytest.mark.parametrize("aca", [False, True])
-def test_compress_exact_rank_tiles(aca):
+@pytest.mark.parametrize("mode", ["unpivoted", "pivoted", "aca"])
+def test_compress_exact_rank_tiles(mode):
     # the first 128 locations are 5 distinct points repeated, so every tile
     # (i, 0) below the diagonal has exactly 5 distinct columns: rank 5 up to
-    # rounding.  The compressor (randomized range finder + pivoted QR, or ACA)
+    # rounding.  The compressor (randomized range finder + QR truncation, or ACA)
     # must find rank 5 and reproduce the tile; Sigma itself is singular, which
     # tlr_compress (no factorisation) does not mind.
     import synth
@@ -370,12 +387,12 @@ def test_compress_exact_rank_tiles(aca):
     x, y = synth.jittered_subset(n, 5)
     x[:nb] = np.tile(x[:5], nb // 5 + 1)[:nb]
     y[:nb] = np.tile(y[:5], nb // 5 + 1)[:nb]
-    h = _handle(n, nb, tol=eps, maxrank=100, aca=aca)
+    h = _handle(n, nb, tol=eps, maxrank=100, aca=mode == "aca", pivoted_trunc=mode == "pivoted")
     xd, yd = to_dev(x, y)
     h.generate(xd, yd, th)
     h.compress()
     R = h.ranks()
-    log(f"aca={aca}: ranks of tile column 0: {R[1:, 0].tolist()}")
+    log(f"{mode}: ranks of tile column 0: {R[1:, 0].tolist()}")
     for i in range(1, n // nb):
         assert R[i, 0] == 5, (i, R[i, 0])
         A = M.covariance(x, y, th, slice(i * nb, (i + 1) * nb), slice(0, nb))
