@@ -70,7 +70,11 @@ hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
 // at least every task's kx (columns beyond the split it covers are left
 // untouched).
 constexpr int kApplyCols = 16;
-hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx);
+// With d_items, one workgroup per (task, chunk) pair listed there (2 ints
+// each, nitems pairs; the order is the dispatch order) instead of the full
+// count x chunks grid.
+hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx,
+                            const int* d_items = nullptr, int nitems = 0);
 // The compact-WY factors T (per 16 reflectors, the layout hqr_factor writes)
 // of s Householder vectors stored as hqr_factor stores them (A, lda, m rows,
 // unit diagonal implied) with scalars tau; max_s >= every task's min(m, s).

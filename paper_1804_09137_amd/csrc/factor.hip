@@ -17,6 +17,7 @@
 // once.
 #include "handle.h"
 
+#include <array>
 #include <atomic>
 #include <system_error>
 #include <thread>
@@ -143,6 +144,49 @@ void rank_wait(tlr_handle_s* h) {
   }
 }
 
+// TLR_DEBUG timing marks of the look-ahead schedule: event id of step
+// dbg_step on stream st (the report after the factorisation gives each mark's
+// mean time after the previous step's end).
+constexpr int kDbgMarks = 21;
+void dbg_mark(tlr_handle_s* h, int id, hipStream_t st) {
+  if (!h->debug || h->dbg_step < 0 || h->dbg_step >= h->nt) return;
+  const size_t need = (size_t)h->nt * kDbgMarks;
+  if (h->dbg_ev.size() < need) {
+    const size_t old = h->dbg_ev.size();
+    h->dbg_ev.resize(need, nullptr);
+    for (size_t i = old; i < need; ++i) HIPCHK(hipEventCreate(&h->dbg_ev[i]));
+  }
+  HIPCHK(hipEventRecord(h->dbg_ev[(size_t)h->dbg_step * kDbgMarks + id], st));
+}
+void dbg_report(tlr_handle_s* h) {
+  if (!h->debug || h->dbg_ev.empty()) return;
+  static const char* names[kDbgMarks] = {"main: step start (pre waited)", "main: last term done", "side: tangent tail start",
+                                         "side: tangent tail done (join)", "main: factor Y launched",
+                                         "main: range ranks published", "main: factor B^T launched",
+                                         "main: truncation ranks published", "main: compression done",
+                                         "main: diagonal step waited", "main: step end", "diag: diagonal step done",
+                                         "side: next pre issued part done", "side: tangent sketch done",
+                                         "side: tangent last term done", "side: diagonal tangent done",
+                                         "side: rest rows waited", "main: range tasks uploaded",
+                                         "main: Q1 formed", "main: truncation tasks uploaded", "main: V formed"};
+  double sum[kDbgMarks] = {0};
+  int cnt = 0;
+  for (int j = 2; j + 3 < h->nt; ++j, ++cnt) {
+    hipEvent_t ref = h->dbg_ev[(size_t)(j - 1) * kDbgMarks + 10];
+    for (int id = 0; id < kDbgMarks; ++id) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ref, h->dbg_ev[(size_t)j * kDbgMarks + id]) != hipSuccess) {
+        (void)hipGetLastError();
+        ms = 0.f;
+      }
+      sum[id] += ms;
+    }
+  }
+  if (cnt == 0) return;
+  std::fprintf(stderr, "[tlr] step marks (ms after the previous step's end, mean of %d steps):\n", cnt);
+  for (int id = 0; id < kDbgMarks; ++id) std::fprintf(stderr, "[tlr]   %6.3f  %s\n", sum[id] / cnt, names[id]);
+}
+
 // Make room for a group of metadata takes: when the staging buffers would
 // overflow, wait for the stream that owns them (every queued copy has then
 // been consumed) and recycle them.  Called before a group, never inside one.
@@ -151,6 +195,39 @@ void meta_reserve(tlr_handle_s* h, int64_t ints, int64_t longs) {
   HIPCHK(hipStreamSynchronize(h->s));
   meta_reset(h);
   if (ints > h->im_cap || longs > h->lm_cap) NOMEM("metadata of one launch group");
+}
+
+// Chunks (16 columns of X) of an apply launch's tasks.
+int64_t apply_chunks(const HqrTask* t, int count) {
+  int64_t n = 0;
+  for (int q = 0; q < count; ++q) n += (t[q].kx + kApplyCols - 1) / kApplyCols;
+  return n;
+}
+
+// Work-ordered (task, chunk) list of an apply launch, staged for upload: one
+// pair per chunk of X that has columns, the chunks applying the most panels
+// first (with X = [I; 0] a chunk needs only the panels up to its columns), so
+// that the workgroup that sets the launch time is dispatched first.
+const int* apply_items(tlr_handle_s* h, const HqrTask* t, int count, int* n) {
+  std::vector<std::array<int, 3>> it;   // panels, task, chunk
+  for (int q = 0; q < count; ++q) {
+    const int np = (std::min(t[q].m, t[q].s) + 15) / 16;
+    const int nch = (t[q].kx + kApplyCols - 1) / kApplyCols;
+    for (int c = 0; c < nch; ++c) it.push_back({t[q].identity ? std::min(np, c * kApplyCols / 16 + 1) : np, q, c});
+  }
+  std::stable_sort(it.begin(), it.end(), [](const std::array<int, 3>& a, const std::array<int, 3>& b) {
+    return a[0] > b[0];
+  });
+  *n = (int)it.size();
+  if (it.empty()) return nullptr;
+  int* d;
+  int* p = im_take(h, 2 * (int64_t)it.size(), &d);
+  for (size_t e = 0; e < it.size(); ++e) {
+    p[2 * e] = it[e][1];
+    p[2 * e + 1] = it[e][2];
+  }
+  im_push(h, p, d, 2 * (int64_t)it.size());
+  return d;
 }
 
 // ---- per-kernel-class timing: an event pair around each launch group ----
@@ -572,11 +649,18 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   }
   bool waited = false;   // the jobs' wait events are on the stream
   while (!todo.empty()) {
+    // job order, and by sketch width within a job (the sketch launches one
+    // tile width per run of equal-class widths)
+    std::stable_sort(todo.begin(), todo.end(),
+                     [&](int a, int b) { return jof[a] != jof[b] ? jof[a] < jof[b] : sz[a] < sz[b]; });
     const int cnt = (int)todo.size();
     // the factor's task list is uploaded before the sketch (no upload
     // between the two launches)
+    // the factor's tasks widest first (the widest tile sets the launch time)
+    std::vector<int> fy(todo);
+    std::stable_sort(fy.begin(), fy.end(), [&](int a, int b) { return sz[a] > sz[b]; });
     for (int q = 0; q < cnt; ++q) {
-      const int g = todo[q];
+      const int g = fy[q];
       HqrTask& tk = hq_fy[q];
       tk = HqrTask{};
       tk.A = h->Ybuf + (int64_t)g * nb * h->smax;
@@ -630,10 +714,27 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         sg[1].K = jb.fold.K;
         cflops += 2.0 * maxm * sw * (double)jb.fold.K * sn;
       }
-      GemmBatch bt{};
-      bt.count = sn; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d; bt.a_off1 = a1_d;
-      gemm(h, maxm, sw, fo ? 2 : 1, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, sw <= 64 ? 64 : 128,
-           m_h, n_h);
+      // the items come sorted by width within the job: one launch per tile
+      // width (32, 64 or 128 columns), so a narrow sketch does not fill a wide
+      // tile with padding
+      auto wcls = [](int w) { return w <= 32 ? 32 : (w <= 64 ? 64 : 128); };
+      for (int q0 = 0; q0 < sn;) {
+        const int cls = wcls(n_h[q0]);
+        int q1 = q0 + 1, subm = m_h[q0], subw = n_h[q0];
+        while (q1 < sn && wcls(n_h[q1]) == cls) {
+          subm = std::max(subm, m_h[q1]);
+          subw = std::max(subw, n_h[q1]);
+          ++q1;
+        }
+        GemmBatch bt{};
+        bt.count = q1 - q0; bt.m_of = m_d + q0; bt.n_of = n_d + q0; bt.a_off = a_d + q0; bt.c_off = c_d + q0;
+        bt.a_off1 = a1_d ? a1_d + q0 : nullptr;
+        gemm(h, subm, subw, fo ? 2 : 1, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, cls, m_h + q0,
+             n_h + q0);
+        q0 = q1;
+      }
+      (void)maxm;
+      (void)sw;
       h->s = own;
     };
     // todo is in job order: [b, e) ranges of one job each
@@ -654,6 +755,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         if (jobs[k].sketch_stream) {
           if (e0 > b0) sketch(b0, e0, jobs[k].sketch_stream, jobs[k]);
           HIPCHK(hipEventRecord(jobs[k].wait, jobs[k].sketch_stream));
+          dbg_mark(h, 13, jobs[k].sketch_stream);
           HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
         } else {
           if (jobs[k].wait) HIPCHK(hipStreamWaitEvent(h->s, jobs[k].wait, 0));
@@ -666,8 +768,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         if (e0 > b0) sketch(b0, e0, nullptr, jobs[k]);
       });
     }
+    if (rounds == 0) dbg_mark(h, 4, h->s);
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     rank_publish(h, 2 * gc, true);
+    if (rounds == 0) dbg_mark(h, 5, h->s);
     auto h0 = std::chrono::steady_clock::now();
     if (during && during[0]) {   // the host would otherwise wait here
       during[0]();
@@ -734,9 +838,11 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       max_kx = std::max(max_kx, tk.kx);
       cflops += 2.0 * tk.m * t1[g] * t1[g];
     }
-    // B^T = Q_b R_b
+    // B^T = Q_b R_b, widest first
+    std::vector<int> fb(lr);
+    std::stable_sort(fb.begin(), fb.end(), [&](int a, int b) { return t1[a] > t1[b]; });
     for (int q = 0; q < L; ++q) {
-      const int g = lr[q];
+      const int g = fb[q];
       HqrTask& tk = hq_fb[q];
       tk = HqrTask{};
       tk.A = h->Bt + (int64_t)g * nb * h->smax;
@@ -798,6 +904,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     }
     // regions 1 and 2 (Q1, B^T) in one upload, then the truncation tasks
     HIPCHK(hipMemcpyAsync(h->hq_d + gc, hq_ay, (gc + L) * sizeof(HqrTask), hipMemcpyHostToDevice, h->s));
+    dbg_mark(h, 17, h->s);
     if (piv) HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
     const int nbg = (int)big.size();
     // A folded job's tiles lead lr (job 0 holds the lowest slots).  Their
@@ -815,7 +922,9 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         nf = 0;
       }
     }
-    meta_reserve(h, 3 * (int64_t)L + nbg + 3 * (int64_t)nf, 3 * (int64_t)L + 2 * (int64_t)nbg + 4 * (int64_t)nf);
+    const int64_t ay_chunks = apply_chunks(hq_ay, L);
+    meta_reserve(h, 3 * (int64_t)L + nbg + 3 * (int64_t)nf + 2 * ay_chunks,
+                 3 * (int64_t)L + 2 * (int64_t)nbg + 4 * (int64_t)nf);
     // projection Bt_g = C_g^T Q1_g (ncols x t1)
     int *m_d, *n_d, *k_d;
     int* m_h = im_take(h, L, &m_d);
@@ -895,7 +1004,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     btr.a_off = a_d + nf; btr.b_off = b_d + nf; btr.c_off = c_d + nf;
     if (nf > 0) flat_tiles(h, btf, 128, 32, m_h, n_h);
     if (L > nf) flat_tiles(h, btr, 128, 32, m_h + nf, n_h + nf);
-    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx));
+    int n_ay = 0;
+    const int* ay_items = apply_items(h, hq_ay, L, &n_ay);
+    HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx, ay_items, n_ay));
+    dbg_mark(h, 18, h->s);
     {
       GemmSeg sg[2] = {};
       sg[0].A = op_contigT(h->colbase, ld, 0, 0);
@@ -914,6 +1026,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       }
       if (L > nf) gemm(h, ncols, maxn, 1, sg, h->Bt, nb, epi_linear(1.0, 0.0), &btr, false, 128, 32, m_h + nf, n_h + nf);
     }
+    dbg_mark(h, 6, h->s);
     HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
     if (piv) {
       if (nbg > 0) HIPCHK(launch_copy_upper(h->Bt, nb, so_d, h->Ybuf, nb, do_d, nn_d, big_m, nbg, h->s));
@@ -921,6 +1034,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       HIPCHK(launch_qrcp(h->tk_d + nsmall, L - nsmall, h->s, big_m));
     }
     rank_publish(h, gc, false);
+    dbg_mark(h, 7, h->s);
     auto h0 = std::chrono::steady_clock::now();
     if (during && during[1]) {
       during[1]();
@@ -991,7 +1105,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     fold_apply(gs);
   }
   // 6. V~ = Q_b [Q_r; 0] and U_g = Q1_g Z_g (m_g x k_g) for the low-rank tiles
-  meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
+  int64_t k_chunks = 0;   // 16-column chunks of the V~ (and Q_r) applications
+  for (int g = 0; g < G; ++g)
+    if (!dense[g] && k2[g] > 0) k_chunks += (k2[g] + kApplyCols - 1) / kApplyCols;
+  meta_reserve(h, 3 * (int64_t)nlr + 2 * (int64_t)ndense + 4 * k_chunks, 3 * (int64_t)nlr + 2 * (int64_t)ndense);
   if (nlr > 0) {
     // Q_r of the tiles pivoted on chip, from their reflectors (in the Y
     // workspace) and scalars
@@ -1038,6 +1155,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     const auto u0 = std::chrono::steady_clock::now();
     HIPCHK(hipMemcpyAsync(h->hq_d + 3 * gc, hq_ab, (nq > 0 ? 2 * (size_t)gc + nq : (size_t)nlr) * sizeof(HqrTask),
                           hipMemcpyHostToDevice, h->s));
+    dbg_mark(h, 19, h->s);
     if (h->debug && t_after_wait.time_since_epoch().count() != 0) {
       h->host_ms[4] += std::chrono::duration<double, std::milli>(u0 - t_after_wait).count();
       h->host_ms[5] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - u0).count();
@@ -1069,11 +1187,15 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     GemmBatch bt{};
     bt.count = nlr; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
     flat_tiles(h, bt, 128, 32, m_h, n_h);
+    int n_qr = 0, n_ab = 0;
+    const int* qr_items = nq > 0 ? apply_items(h, hq_qr, nq, &n_qr) : nullptr;
+    const int* ab_items = apply_items(h, hq_ab, nlr, &n_ab);
     if (nq > 0) {
       HIPCHK(launch_wy_build(h->hq_d + 4 * gc, nq, h->s, max_k));
-      HIPCHK(launch_hqr_apply(h->hq_d + 5 * gc, nq, h->s, max_k));
+      HIPCHK(launch_hqr_apply(h->hq_d + 5 * gc, nq, h->s, max_k, qr_items, n_qr));
     }
-    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s, max_kx));
+    HIPCHK(launch_hqr_apply(h->hq_d + 3 * gc, nlr, h->s, max_kx, ab_items, n_ab));
+    dbg_mark(h, 20, h->s);
     GemmSeg sg{};
     sg.A = op_contig(h->Q1, nb, 0, 0);
     sg.B = op_contigT(h->Zb, h->smax, 0, 0);
@@ -1106,6 +1228,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
                                h->s));
   }
   prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
+  dbg_mark(h, 8, h->s);
 }
 
 // V(i, col) = Dinv_col * V~_i for the low-rank tiles below the diagonal
@@ -1688,6 +1811,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     const size_t e_td = prof_mark(h);
     tangent_diag(h, j, cold, h->n, diag_tile(h, j), nb, ddj, nb);
     prof_add(h, TLR_K_DIAG, e_td, 6.0 * nbj * (double)nbj * nbj, 32.0 * nbj * (double)nbj);
+    dbg_mark(h, 15, h->s);
     const int T = nt - j - 1;
     if (T <= 0) return;
     int kmax = 0, cnt = 0;
@@ -1761,6 +1885,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       GemmBatch cb{};
       cb.count = cnt; cb.m_of = m_d; cb.n_of = n_d; cb.k_of = k_d; cb.a_off = a_d; cb.b_off = b_d; cb.c_off = c_d;
       rest_wait();
+      dbg_mark(h, 16, h->s);
       HIPCHK(launch_thin_gemm(h->arena, nb, pcat, nb, cold, h->n, cb, mmax, kmax, nbj, h->s, -1.0, 1.0, true));
     } else if (cnt > 0) {
       meta_reserve(h, 6 * (int64_t)cnt, 6 * (int64_t)cnt);
@@ -1845,6 +1970,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     for (auto& f : during)
       if (f) f();
     if (wait_diag) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_diag, 0));
+    dbg_mark(h, 9, h->s_main);
     for (const ColumnJob& jb : jobs)
       if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
   };
@@ -1885,6 +2011,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       if (j + 1 < nt) primal_update(j + 1, 0, j, true);
       tangent_update(j, 0, j - 1, true);
       HIPCHK(hipEventRecord(h->ev_pre, h->s));
+      dbg_mark(h, 12, h->s);
     };
     primal_update(0, 0, 0, true);
     primal_diag(0);
@@ -1901,6 +2028,8 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     for (int j = 0; j < nt; ++j) {
       // main: the rest of primal column j + 1 waits for its pre part
       HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_pre, 0));
+      h->dbg_step = j;
+      dbg_mark(h, 0, h->s_main);
       // Issued first: the primal column's rest and then its sketch are the
       // longer chain to the next compression; the host issues launches about
       // as fast as the GPU runs these short kernels.
@@ -1910,17 +2039,21 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       if (j + 1 < nt) {
         primal_update(j + 1, j, j + 1, false, &pfold);
         HIPCHK(hipEventRecord(h->ev_post, h->s_main));
+        dbg_mark(h, 1, h->s_main);
       }
       {
         // side: the rest of tangent column j, after step j - 1's compressions
         SideStream ss(h);
         HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
+        dbg_mark(h, 2, h->s);
         // the tangent's rows below its diagonal tile on the diagonal-step stream
         // (idle here), beside the tangent of the diagonal step
         tangent_update(j, j - 1, j, false, h->s_diag);
+        dbg_mark(h, 14, h->s);
         tangent_rest(j);
         rest_wait();
         HIPCHK(hipEventRecord(h->ev_join, h->s));
+        dbg_mark(h, 3, h->s);
       }
       // the diagonal step of primal column j + 1 on its own stream, behind the
       // tangent's rows there: only the triangular solves after the
@@ -1930,6 +2063,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         HIPCHK(hipStreamWaitEvent(h->s, h->ev_post, 0));
         primal_diag(j + 1);
         HIPCHK(hipEventRecord(h->ev_diag, h->s));
+        dbg_mark(h, 11, h->s);
       }
       // each column is sketched as soon as it is complete: the primal one on
       // the main stream, the tangent one on the side stream after its chain
@@ -1948,6 +2082,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         if (j + 1 < nt) pre(j + 1);
       });
       HIPCHK(hipEventRecord(h->ev_fin, h->s_main));
+      dbg_mark(h, 10, h->s_main);
     }
   }
   family_upload(h, P);
@@ -1959,7 +2094,9 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
                  h->host_ms[0], h->host_ms[1], h->host_ms[2], h->host_ms[3], h->host_ms[4], h->host_ms[5],
                  h->host_ms[6]);
     for (double& v : h->host_ms) v = 0.0;
+    dbg_report(h);
   }
+  h->dbg_step = -1;
   P.done_kind = 1;
   if (tangent) G.done_kind = 1;
 }
@@ -2139,6 +2276,9 @@ void free_all(tlr_handle_s* h) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t& e : h->evpool) (void)hipEventDestroy(e);
   h->evpool.clear();
+  for (hipEvent_t& e : h->dbg_ev)
+    if (e) (void)hipEventDestroy(e);
+  h->dbg_ev.clear();
   h->dev_allocs.clear();
   h->host_allocs.clear();
 }

@@ -63,6 +63,8 @@ struct tlr_handle_s {
   int gcap = 0;         // tile slots of the compression scratch
   int upd_tag = 1;      // column-update kernels of the running factorisation: 1 FP64, 2 FP32 products
   bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
+  std::vector<hipEvent_t> dbg_ev;   // TLR_DEBUG: per-step timing marks of the three streams
+  int dbg_step = -1;
   double host_ms[7] = {0, 0, 0, 0, 0, 0, 0};   // TLR_DEBUG: host time in the compressions' two waits and their
                                                // callbacks, then after the second wait: bookkeeping, upload, launches
   bool pivoted_trunc = false;   // TLR_FLAG_PIVOTED_TRUNC

@@ -422,14 +422,18 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
 // Workgroup (task, y) applies Q to columns [y * kApplyCols, (y + 1) *
 // kApplyCols) of X: the columns are independent, so a wide X (the largest
 // tile of a column sets the launch time) is spread over several CUs.
-__global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict__ tasks) {
-  const HqrTask tk = tasks[blockIdx.x];
+__global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict__ tasks,
+                                                       const int* __restrict__ items) {
+  // items (optional): workgroup b takes task items[2b], column chunk items[2b + 1]
+  const int ti = items ? items[2 * blockIdx.x] : (int)blockIdx.x;
+  const int cy = items ? items[2 * blockIdx.x + 1] : (int)blockIdx.y;
+  const HqrTask tk = tasks[ti];
   __shared__ double P[PB * LDP];
   __shared__ double red[NW * RS];
   __shared__ double Wf[256], Wp[256], Ts[256];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int m = tk.m, s = tk.s;
-  const int x0 = blockIdx.y * kApplyCols;
+  const int x0 = cy * kApplyCols;
   const int kx = tk.kx < x0 + kApplyCols ? tk.kx : x0 + kApplyCols;   // this workgroup: columns [x0, kx)
   if (m <= 0 || kx <= x0) return;
   gdouble* X = gptr(tk.X);
@@ -863,10 +867,17 @@ hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx) {
+hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, int max_kx, const int* d_items,
+                            int nitems) {
+  if (d_items) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)nitems), dim3(NT), 0, s, d_tasks, d_items);
+    return hipGetLastError();
+  }
   if (count <= 0) return hipSuccess;
   const int chunks = max_kx > kApplyCols ? (max_kx + kApplyCols - 1) / kApplyCols : 1;
-  hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)count, (unsigned)chunks), dim3(NT), 0, s, d_tasks);
+  hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)count, (unsigned)chunks), dim3(NT), 0, s, d_tasks,
+                     (const int*)nullptr);
   return hipGetLastError();
 }
 
