@@ -429,7 +429,7 @@ def main():
         "hbm_GBps": wk["compress"]["bytes"] / t_c / 1e9, "hbm_frac": wk["compress"]["bytes"] / t_c / 1e9 / PEAK_HBM,
         "algorithmic_flops_per_eval": wk["compress"]["flops"], "algorithmic_bytes_per_eval": wk["compress"]["bytes"],
         "executed_flops_per_eval": kc["flops"], "ms_per_eval": kc["ms"], "launch_groups": kc["launches"],
-        "kernel": "compression chain (sketch GEMM, blocked Householder QR, pivoted QR, Q applications)"}
+        "kernel": "compression chain (sketch GEMM, blocked Householder QR, projection, truncation of R, Q applications)"}
     out["work_model"] = wk
     t_eval = 1e-3 * out["ms_per_step"]
     out["work_model_rates"] = {"algorithmic_tflops_per_eval_time": wk["total"]["flops"] / t_eval / 1e12,

@@ -250,10 +250,6 @@ tlr_status tlr_predict(tlr_handle_t h, const double* d_z, int64_t m, const doubl
 tlr_status tlr_loglik_grad3(tlr_handle_t h, const double* d_x, const double* d_y, const double* d_z,
                             const double theta[3], double* ll, double grad[3], int64_t* info);
 
-/* After tlr_potrf: d_z = L d_eps (the factor of Sigma(theta) times a caller
- * vector), e.g. a synthetic measurement vector z ~ N(0, Sigma) from
- * d_eps ~ N(0, I) (the data generator of Section VIII-D).  d_z must not alias
- * d_eps. */
 /* Log-likelihood and score of several independent fields at once (one handle
  * per field, each built with want_grad; the handles must be distinct and
  * should run on distinct streams, or their work serialises).  Field f is
@@ -273,6 +269,10 @@ tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_t* hs, cons
                                    const double* const* d_y, const double* const* d_z, const double* theta,
                                    double* ll, double* grad, int64_t* info, int32_t* status, int32_t nthreads);
 
+/* After tlr_potrf: d_z = L d_eps (the factor of Sigma(theta) times a caller
+ * vector), e.g. a synthetic measurement vector z ~ N(0, Sigma) from
+ * d_eps ~ N(0, I) (the data generator of Section VIII-D).  d_z must not alias
+ * d_eps. */
 tlr_status tlr_sample(tlr_handle_t h, const double* d_eps, double* d_z);
 
 /* enable = 1: bracket every launch group with hipEvents on the stream it

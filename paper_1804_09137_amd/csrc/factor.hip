@@ -1227,7 +1227,12 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     HIPCHK(launch_batched_copy(h->colbase, ld, so_d, h->arena, nb, do_d, m_d, k_d, (int64_t)nb * ncols, ndense,
                                h->s));
   }
-  prof_add(h, TLR_K_COMPRESS, e_c, cflops, 0.0);
+  // algorithmic bytes: each tile read by the sketch and by the projection, and
+  // its factors written (U and V at its rank, a dense tile once)
+  double cbytes = 0.0;
+  for (int g = 0; g < G; ++g)
+    cbytes += 8.0 * (2.0 * rows[g] * ncols + (dense[g] ? (double)rows[g] * ncols : (double)(rows[g] + ncols) * k2[g]));
+  prof_add(h, TLR_K_COMPRESS, e_c, cflops, cbytes);
   dbg_mark(h, 8, h->s);
 }
 
