@@ -158,6 +158,13 @@ void dbg_mark(tlr_handle_s* h, int id, hipStream_t st) {
   }
   HIPCHK(hipEventRecord(h->dbg_ev[(size_t)h->dbg_step * kDbgMarks + id], st));
 }
+// host time since the previous host mark, into slot id (slot 0 restarts the clock)
+void dbg_host(tlr_handle_s* h, int id) {
+  if (!h->debug || h->dbg_step < 0) return;
+  const auto now = std::chrono::steady_clock::now();
+  if (id > 0) h->dbg_host[id] += std::chrono::duration<double, std::milli>(now - h->dbg_host_last).count();
+  h->dbg_host_last = now;
+}
 void dbg_report(tlr_handle_s* h) {
   if (!h->debug || h->dbg_ev.empty()) return;
   static const char* names[kDbgMarks] = {"main: step start (pre waited)", "main: last term done", "side: tangent tail start",
@@ -183,6 +190,13 @@ void dbg_report(tlr_handle_s* h) {
     }
   }
   if (cnt == 0) return;
+  static const char* hn[8] = {"", "truncation ranks seen -> compression issued", "-> diagonal wait issued",
+                              "-> triangular solves issued", "-> next step's first wait issued",
+                              "-> tangent chain issued", "-> diagonal step issued", "-> factor Y launched"};
+  std::fprintf(stderr, "[tlr] host ms per step (mean over %d steps):", h->nt);
+  for (int id = 1; id < 8; ++id) std::fprintf(stderr, " %s %.3f;", hn[id], h->dbg_host[id] / h->nt);
+  std::fprintf(stderr, "\n");
+  for (double& v : h->dbg_host) v = 0.0;
   std::fprintf(stderr, "[tlr] step marks (ms after the previous step's end, mean of %d steps):\n", cnt);
   for (int id = 0; id < kDbgMarks; ++id) std::fprintf(stderr, "[tlr]   %6.3f  %s\n", sum[id] / cnt, names[id]);
 }
@@ -192,6 +206,10 @@ void dbg_report(tlr_handle_s* h) {
 // been consumed) and recycle them.  Called before a group, never inside one.
 void meta_reserve(tlr_handle_s* h, int64_t ints, int64_t longs) {
   if (h->im_use + ints <= h->im_cap && h->lm_use + longs <= h->lm_cap) return;
+  if (h->debug) {
+    ++h->dbg_meta_syncs;
+    if (h->s == h->s_main) ++h->dbg_meta_syncs_main;
+  }
   HIPCHK(hipStreamSynchronize(h->s));
   meta_reset(h);
   if (ints > h->im_cap || longs > h->lm_cap) NOMEM("metadata of one launch group");
@@ -768,7 +786,10 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         if (e0 > b0) sketch(b0, e0, nullptr, jobs[k]);
       });
     }
-    if (rounds == 0) dbg_mark(h, 4, h->s);
+    if (rounds == 0) {
+      dbg_mark(h, 4, h->s);
+      dbg_host(h, 7);
+    }
     HIPCHK(launch_hqr_factor(h->hq_d, cnt, h->s));
     rank_publish(h, 2 * gc, true);
     if (rounds == 0) dbg_mark(h, 5, h->s);
@@ -1042,6 +1063,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     }
     auto h1 = std::chrono::steady_clock::now();
     rank_wait(h);
+    dbg_host(h, 0);
     if (h->debug) {
       const auto h2 = std::chrono::steady_clock::now();
       h->host_ms[2] += std::chrono::duration<double, std::milli>(h1 - h0).count();
@@ -1234,6 +1256,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     cbytes += 8.0 * (2.0 * rows[g] * ncols + (dense[g] ? (double)rows[g] * ncols : (double)(rows[g] + ncols) * k2[g]));
   prof_add(h, TLR_K_COMPRESS, e_c, cflops, cbytes);
   dbg_mark(h, 8, h->s);
+  dbg_host(h, 1);
 }
 
 // V(i, col) = Dinv_col * V~_i for the low-rank tiles below the diagonal
@@ -1976,8 +1999,10 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       if (f) f();
     if (wait_diag) HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_diag, 0));
     dbg_mark(h, 9, h->s_main);
+    dbg_host(h, 2);
     for (const ColumnJob& jb : jobs)
       if (jb.T > 0) lowrank_trsm(h, jb.col, jb.i_first, jb.T, h->Vtmp + (int64_t)jb.g0 * h->vslot, *jb.F);
+    dbg_host(h, 3);
   };
 
   if (!side) {
@@ -2035,6 +2060,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       HIPCHK(hipStreamWaitEvent(h->s_main, h->ev_pre, 0));
       h->dbg_step = j;
       dbg_mark(h, 0, h->s_main);
+      dbg_host(h, 4);
       // Issued first: the primal column's rest and then its sketch are the
       // longer chain to the next compression; the host issues launches about
       // as fast as the GPU runs these short kernels.
@@ -2059,6 +2085,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         rest_wait();
         HIPCHK(hipEventRecord(h->ev_join, h->s));
         dbg_mark(h, 3, h->s);
+        dbg_host(h, 5);
       }
       // the diagonal step of primal column j + 1 on its own stream, behind the
       // tangent's rows there: only the triangular solves after the
@@ -2069,6 +2096,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         primal_diag(j + 1);
         HIPCHK(hipEventRecord(h->ev_diag, h->s));
         dbg_mark(h, 11, h->s);
+        dbg_host(h, 6);
       }
       // each column is sketched as soon as it is complete: the primal one on
       // the main stream, the tangent one on the side stream after its chain
@@ -2095,9 +2123,10 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   if (h->debug) {
     std::fprintf(stderr,
                  "[tlr] host ms: issue in wait 1 %.1f, wait 1 %.1f, issue in wait 2 %.1f, wait 2 %.1f, "
-                 "wait 2 to upload %.1f, upload %.1f, upload to last launch %.1f\n",
+                 "wait 2 to upload %.1f, upload %.1f, upload to last launch %.1f; staging syncs %d (main %d)\n",
                  h->host_ms[0], h->host_ms[1], h->host_ms[2], h->host_ms[3], h->host_ms[4], h->host_ms[5],
-                 h->host_ms[6]);
+                 h->host_ms[6], h->dbg_meta_syncs, h->dbg_meta_syncs_main);
+    h->dbg_meta_syncs = h->dbg_meta_syncs_main = 0;
     for (double& v : h->host_ms) v = 0.0;
     dbg_report(h);
   }

@@ -65,6 +65,9 @@ struct tlr_handle_s {
   bool debug = false;   // TLR_DEBUG set: per-column compression statistics on stderr
   std::vector<hipEvent_t> dbg_ev;   // TLR_DEBUG: per-step timing marks of the three streams
   int dbg_step = -1;
+  int dbg_meta_syncs = 0, dbg_meta_syncs_main = 0;   // TLR_DEBUG: staging-buffer synchronisations
+  double dbg_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};       // TLR_DEBUG: host time between issue points of a step
+  std::chrono::steady_clock::time_point dbg_host_last{};
   double host_ms[7] = {0, 0, 0, 0, 0, 0, 0};   // TLR_DEBUG: host time in the compressions' two waits and their
                                                // callbacks, then after the second wait: bookkeeping, upload, launches
   bool pivoted_trunc = false;   // TLR_FLAG_PIVOTED_TRUNC
