@@ -211,6 +211,13 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         // fallback that applies the folded term to the tiles instead
         if (const char* fb = std::getenv("TLR_FOLD_GBUF")) h->gbuf_cap = std::min<int64_t>(h->gbuf_cap, std::atoll(fb));
         h->gbuf = dalloc<double>(h, h->gbuf_cap);
+        h->wf_ld = nt * nb;
+        h->wf_pcols = h->maxrank;
+        h->wf_tcols = 3 * h->maxrank;
+        h->wf_cap = h->wf_ld * (h->wf_pcols + h->wf_tcols);
+        h->Wf = dalloc<double>(h, h->wf_cap);
+        h->zst2_cols = 2 * h->maxrank + kFoldRsumMax;
+        h->zst2 = dalloc<double>(h, h->smax * (int64_t)h->zst2_cols);
       }
       h->qr_d = dalloc<int>(h, 2 * gc);
       h->qr_h = halloc_coherent<int>(h, 2 * gc, &h->qr_hd);

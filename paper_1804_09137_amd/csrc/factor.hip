@@ -517,12 +517,30 @@ struct RankPred {
 // compression: those tiles still owe C_i -= W_i U^T (W: the update's left
 // factor, rows from the diagonal tile on, leading dimension ldw; U: the row
 // factor, nb x K).  The compression applies it inside its sketch and
-// projection products instead of rewriting the whole column.
+// projection products instead of rewriting the whole column.  A tangent
+// column also owes, per tile t, its correction C_t -= Uc_t P_t^T (Uc_t the
+// primal tile's left factor in the arena, P_t = dL_jj V~_t); W then holds
+// Uc_t beside the term's own columns, in columns K .. K + cr[t] of the tile's
+// rows, so that one product with W^T gives both parts of the projection.
 struct FoldOut {
+  // in (optional): where the update builds W (wld rows apart, wcols columns
+  // available) and U_row
+  double* wdst = nullptr;
+  int64_t wld = 0;
+  int wcols = 0;
+  double* udst = nullptr;
+  int extra = 0;                // columns of W kept after the term's own for the correction
+  // out: K > 0 when the column is folded
   const double* W = nullptr;
   int64_t ldw = 0;
   const double* U = nullptr;
   int K = 0;
+  const double* zs = nullptr;   // -(Omega^T U) (and -(Omega^T Pc) after it): ld smax; null: computed here
+  bool corr = false;            // the per-tile correction
+  std::vector<int64_t> cu;      // Uc_t: arena offset
+  std::vector<int> cr;          // Uc_t: columns (0: no correction for the tile)
+  std::vector<int64_t> cp;      // P_t: first column in Pc (its Omega products: column K + cp in zs)
+  const double* Pc = nullptr;   // nb x (sum cr), ld nb
 };
 
 struct ColumnJob {
@@ -585,42 +603,57 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       rows[g] = tile_rows(h, jobs[k].i_first + t);
       srow[g] = (jobs[k].src - h->colbase) + (int64_t)t * nb;
     }
-  // the pending term of the folded job, applied to tiles gs of it:
-  // C_g -= W_g U^T (W_g: rows (1 + t) nb.. of W for tile t)
-  std::vector<char> fold_done(G, 0);   // tile g has taken the pending term
-  auto fold_apply = [&](const std::vector<int>& gs_in) {
-    const FoldOut& fo = jobs[0].fold;
+  // the pending terms of folded job k, applied to its tiles gs:
+  // C_g -= W_g U^T (W_g: rows (1 + t) nb.. of W for tile t) and the
+  // correction C_g -= Uc_t P_t^T
+  std::vector<char> fold_done(G, 0);   // tile g has taken the pending terms
+  auto fold_apply = [&](int k, const std::vector<int>& gs_in) {
+    const FoldOut& fo = jobs[k].fold;
     std::vector<int> gs;
     for (int g : gs_in)
-      if (!fold_done[g]) {
+      if (!fold_done[g] && jof[g] == k) {
         fold_done[g] = 1;
         gs.push_back(g);
       }
     const int cntf = (int)gs.size();
     if (cntf == 0 || fo.K <= 0) return;
-    meta_reserve(h, cntf, 2 * (int64_t)cntf);
+    meta_reserve(h, 2 * (int64_t)cntf, 4 * (int64_t)cntf);
     int* fm_d;
     int* fm_h = im_take(h, cntf, &fm_d);
-    int64_t *fa_d, *fc_d;
+    int* fk_d;
+    int* fk_h = im_take(h, cntf, &fk_d);
+    int64_t *fa_d, *fc_d, *fa1_d, *fb1_d;
     int64_t* fa_h = lm_take(h, cntf, &fa_d);
     int64_t* fc_h = lm_take(h, cntf, &fc_d);
-    int maxm = 1;
+    int64_t* fa1_h = lm_take(h, cntf, &fa1_d);
+    int64_t* fb1_h = lm_take(h, cntf, &fb1_d);
+    int maxm = 1, kc = 0;
     for (int q = 0; q < cntf; ++q) {
-      const int g = gs[q];
+      const int g = gs[q], t = tloc[g];
       fm_h[q] = rows[g];
-      fa_h[q] = (int64_t)(1 + tloc[g]) * nb;
+      fa_h[q] = (int64_t)(1 + t) * nb;
       fc_h[q] = srow[g];
+      fk_h[q] = fo.corr ? fo.cr[t] : 0;
+      fa1_h[q] = fo.corr ? fo.cu[t] : 0;
+      fb1_h[q] = fo.corr ? fo.cp[t] * nb : 0;
+      kc = std::max(kc, fk_h[q]);
       maxm = std::max(maxm, rows[g]);
     }
-    im_push(h, fm_h, fm_d, cntf);
-    lm_push(h, fa_h, fa_d, 2 * (int64_t)cntf);
-    GemmSeg fs{};
-    fs.A = op_contig(fo.W, fo.ldw, 0, 0);
-    fs.B = op_contig(fo.U, nb, 0, 0);
-    fs.K = fo.K;
+    im_push(h, fm_h, fm_d, 2 * (int64_t)cntf);
+    lm_push(h, fa_h, fa_d, 4 * (int64_t)cntf);
+    GemmSeg fs[2] = {};
+    fs[0].A = op_contig(fo.W, fo.ldw, 0, 0);
+    fs[0].B = op_contig(fo.U, nb, 0, 0);
+    fs[0].K = fo.K;
     GemmBatch fb{};
     fb.count = cntf; fb.m_of = fm_d; fb.a_off = fa_d; fb.c_off = fc_d;
-    gemm(h, maxm, ncols, 1, &fs, h->colbase, ld, epi_linear(-1.0, 1.0), &fb);
+    if (fo.corr && kc > 0) {
+      fs[1].A = op_contig(h->arena, nb, 0, 0);
+      fs[1].B = op_contig(fo.Pc, nb, 0, 0);
+      fs[1].K = kc;
+      fb.a_off1 = fa1_d; fb.b_off1 = fb1_d; fb.k_of1 = fk_d;
+    }
+    gemm(h, maxm, ncols, (fo.corr && kc > 0) ? 2 : 1, fs, h->colbase, ld, epi_linear(-1.0, 1.0), &fb);
   };
   auto fail_rank = [&](int g) {
     h->bad_i = jobs[jof[g]].i_first + tloc[g];
@@ -654,16 +687,19 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   }
   // 1-2. sketch and range rank; a tile with fewer than 8 samples beyond its
   // rank estimate is sketched again, alone, 1.3 times as wide
-  // a folded job: Zs = -(Omega^T U) (smax x K), the sketch of its pending term
-  for (const ColumnJob& jb : jobs) {
-    if (jb.fold.K <= 0) continue;
-    if (jb.fold.K > h->maxrank || &jb != &jobs[0]) throw Fail{TLR_EINVAL};   // one folded job, listed first
+  // a folded job without them: Zs = -(Omega^T U) (smax x K), the sketch of
+  // its pending term (one such job at a time: it takes the zst buffer)
+  int nzs = 0;
+  for (ColumnJob& jb : jobs) {
+    if (jb.fold.K <= 0 || jb.fold.zs) continue;
+    if (jb.fold.K > h->maxrank || jb.fold.corr || nzs++ > 0) throw Fail{TLR_EINVAL};
     GemmSeg zs{};
     zs.A = op_contigT(h->omega, nb, 0, 0);
     zs.B = op_contigT(jb.fold.U, nb, 0, 0);
     zs.K = ncols;
     gemm(h, h->smax, jb.fold.K, 1, &zs, h->zst, h->smax, epi_linear(-1.0, 0.0));
     cflops += 2.0 * h->smax * (double)jb.fold.K * ncols;
+    jb.fold.zs = h->zst;
   }
   bool waited = false;   // the jobs' wait events are on the stream
   while (!todo.empty()) {
@@ -697,40 +733,59 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     // early is sketched while another is still being finished elsewhere.
     auto sketch = [&](int sb, int se, hipStream_t on, const ColumnJob& jb) {
       const int sn = se - sb;
-      const bool fo = jb.fold.K > 0;
-      meta_reserve(h, 2 * (int64_t)sn, (fo ? 3 : 2) * (int64_t)sn);   // on the compression stream, which owns the set
+      const FoldOut& fold = jb.fold;
+      const bool fo = fold.K > 0, co = fo && fold.corr;
+      const int nsg = co ? 3 : (fo ? 2 : 1);
+      // on the compression stream, which owns the set
+      meta_reserve(h, (co ? 3 : 2) * (int64_t)sn, (co ? 5 : (fo ? 3 : 2)) * (int64_t)sn);
       hipStream_t own = h->s;
       h->s = on ? on : own;
-      int *m_d, *n_d;
+      int *m_d, *n_d, *k2_d = nullptr;
       int* m_h = im_take(h, sn, &m_d);
       int* n_h = im_take(h, sn, &n_d);
-      int64_t *a_d, *c_d, *a1_d = nullptr;
+      int* k2_h = co ? im_take(h, sn, &k2_d) : nullptr;
+      int64_t *a_d, *c_d, *a1_d = nullptr, *a2_d = nullptr, *b2_d = nullptr;
       int64_t* a_h = lm_take(h, sn, &a_d);
       int64_t* c_h = lm_take(h, sn, &c_d);
       int64_t* a1_h = fo ? lm_take(h, sn, &a1_d) : nullptr;
-      int maxm = 1, sw = 0;
+      int64_t* a2_h = co ? lm_take(h, sn, &a2_d) : nullptr;
+      int64_t* b2_h = co ? lm_take(h, sn, &b2_d) : nullptr;
+      int maxm = 1, sw = 0, kc = 0;
       for (int q = 0; q < sn; ++q) {
-        const int g = todo[sb + q];
+        const int g = todo[sb + q], t = tloc[g];
         m_h[q] = rows[g];
         n_h[q] = sz[g];
         a_h[q] = srow[g];
         c_h[q] = (int64_t)g * nb * h->smax;
-        if (fo) a1_h[q] = (int64_t)(1 + tloc[g]) * nb;   // rows of W for this tile
+        if (fo) a1_h[q] = (int64_t)(1 + t) * nb;   // rows of W for this tile
+        if (co) {
+          k2_h[q] = fold.cr[t];
+          a2_h[q] = fold.cu[t];
+          b2_h[q] = (fold.K + fold.cp[t]) * h->smax;
+          kc = std::max(kc, fold.cr[t]);
+        }
         maxm = std::max(maxm, m_h[q]);
         sw = std::max(sw, sz[g]);
       }
-      im_push(h, m_h, m_d, 2 * (int64_t)sn);
-      lm_push(h, a_h, a_d, (fo ? 3 : 2) * (int64_t)sn);
-      // Y = C Omega, and with a fold + W (-(Omega^T U))^T = (C - W U^T) Omega
-      GemmSeg sg[2] = {};
+      im_push(h, m_h, m_d, (co ? 3 : 2) * (int64_t)sn);
+      lm_push(h, a_h, a_d, (co ? 5 : (fo ? 3 : 2)) * (int64_t)sn);
+      // Y = C Omega, and with a fold + W (-(Omega^T U))^T = (C - W U^T) Omega,
+      // with the correction also + Uc_t (-(Omega^T P_t))^T
+      GemmSeg sg[3] = {};
       sg[0].A = op_contig(h->colbase, ld, 0, 0);
       sg[0].B = op_contigT(h->omega, nb, 0, 0);
       sg[0].K = ncols;
       if (fo) {
-        sg[1].A = op_contig(jb.fold.W, jb.fold.ldw, 0, 0);
-        sg[1].B = op_contig(h->zst, h->smax, 0, 0);
-        sg[1].K = jb.fold.K;
-        cflops += 2.0 * maxm * sw * (double)jb.fold.K * sn;
+        sg[1].A = op_contig(fold.W, fold.ldw, 0, 0);
+        sg[1].B = op_contig(fold.zs, h->smax, 0, 0);
+        sg[1].K = fold.K;
+        cflops += 2.0 * maxm * sw * (double)fold.K * sn;
+      }
+      if (co) {
+        sg[2].A = op_contig(h->arena, nb, 0, 0);
+        sg[2].B = op_contig(fold.zs, h->smax, 0, 0);
+        sg[2].K = std::max(kc, 1);
+        cflops += 2.0 * maxm * sw * (double)kc * sn;
       }
       // the items come sorted by width within the job: one launch per tile
       // width (32, 64 or 128 columns), so a narrow sketch does not fill a wide
@@ -747,8 +802,12 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         GemmBatch bt{};
         bt.count = q1 - q0; bt.m_of = m_d + q0; bt.n_of = n_d + q0; bt.a_off = a_d + q0; bt.c_off = c_d + q0;
         bt.a_off1 = a1_d ? a1_d + q0 : nullptr;
-        gemm(h, subm, subw, fo ? 2 : 1, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, cls, m_h + q0,
-             n_h + q0);
+        if (co) {
+          bt.k_of2 = k2_d + q0;
+          bt.a_off2 = a2_d + q0;
+          bt.b_off2 = b2_d + q0;
+        }
+        gemm(h, subm, subw, nsg, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, cls, m_h + q0, n_h + q0);
         q0 = q1;
       }
       (void)maxm;
@@ -928,47 +987,78 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     dbg_mark(h, 17, h->s);
     if (piv) HIPCHK(hipMemcpyAsync(h->tk_d, h->tk_h, L * sizeof(QrcpTask), hipMemcpyHostToDevice, h->s));
     const int nbg = (int)big.size();
-    // A folded job's tiles lead lr (job 0 holds the lowest slots).  Their
-    // projection is C^T Q1 - U (W^T Q1): G = -(W^T Q1) first, then a second
-    // segment U G.  Should G not fit its buffer, the pending term is applied
-    // to those tiles instead.
-    int nf = 0;
-    const FoldOut fo = jobs[0].fold;
-    if (fo.K > 0) {
-      while (nf < L && jof[lr[nf]] == 0) ++nf;
+    // Folded jobs' projections: C^T Q1 + U G (+ P_t H_t with the correction),
+    // with [G; H] = -(W^T Q1) over the W rows of the tile (W holds Uc_t after
+    // the term's own columns), one launch for the folded tiles of all jobs
+    // (their W share one buffer and leading dimension), then one projection
+    // launch per folded job.  Should [G; H] not fit its buffer, the pending
+    // terms are applied to those tiles instead.
+    struct FoldRange {
+      int k, b, e;   // job, its tiles lr[b, e)
+    };
+    std::vector<FoldRange> fr;
+    for (int q = 0; q < L;) {
+      const int k = jof[lr[q]];
+      int e = q;
+      while (e < L && jof[lr[e]] == k) ++e;
+      if (jobs[k].fold.K > 0) fr.push_back({k, q, e});
+      q = e;
+    }
+    auto gm_of = [&](int q) {
+      const FoldOut& f = jobs[jof[lr[q]]].fold;
+      return f.K + (f.corr ? f.cr[tloc[lr[q]]] : 0);
+    };
+    int Kg = 1, nfq = 0;
+    for (const FoldRange& r : fr)
+      for (int q = r.b; q < r.e; ++q) {
+        Kg = std::max(Kg, gm_of(q));
+        ++nfq;
+      }
+    if (!fr.empty()) {
       int64_t need = 0;
-      for (int q = 0; q < nf; ++q) need += (int64_t)fo.K * t1[lr[q]];
-      if (need > h->gbuf_cap) {
-        fold_apply(std::vector<int>(lr.begin(), lr.begin() + nf));
-        nf = 0;
+      for (const FoldRange& r : fr)
+        for (int q = r.b; q < r.e; ++q) need += (int64_t)Kg * t1[lr[q]];
+      bool shared = true;   // every folded W in the fold buffer, one leading dimension
+      for (const FoldRange& r : fr)
+        shared = shared && jobs[r.k].fold.ldw == jobs[fr[0].k].fold.ldw && jobs[r.k].fold.W >= h->Wf &&
+                 jobs[r.k].fold.W < h->Wf + h->wf_cap;
+      if (need > h->gbuf_cap || !shared) {
+        for (const FoldRange& r : fr) fold_apply(r.k, std::vector<int>(lr.begin() + r.b, lr.begin() + r.e));
+        fr.clear();
+        nfq = 0;
       }
     }
     const int64_t ay_chunks = apply_chunks(hq_ay, L);
-    meta_reserve(h, 3 * (int64_t)L + nbg + 3 * (int64_t)nf + 2 * ay_chunks,
-                 3 * (int64_t)L + 2 * (int64_t)nbg + 4 * (int64_t)nf);
-    // projection Bt_g = C_g^T Q1_g (ncols x t1)
-    int *m_d, *n_d, *k_d;
+    meta_reserve(h, 4 * (int64_t)L + nbg + 3 * (int64_t)nfq + 2 * ay_chunks,
+                 6 * (int64_t)L + 2 * (int64_t)nbg + 4 * (int64_t)nfq);
+    // projection Bt_g = C_g^T Q1_g (ncols x t1); per tile also the folded
+    // segments' offsets (b1: G, a2 / b2 / k2: the correction's P_t and H_t)
+    int *m_d, *n_d, *k_d, *k2_d;
     int* m_h = im_take(h, L, &m_d);
     int* n_h = im_take(h, L, &n_d);
     int* k_h = im_take(h, L, &k_d);
-    int64_t *a_d, *b_d, *c_d;
+    int* k2_h = im_take(h, L, &k2_d);
+    int64_t *a_d, *b_d, *c_d, *b1_d, *a2_d, *b2_d;
     int64_t* a_h = lm_take(h, L, &a_d);
     int64_t* b_h = lm_take(h, L, &b_d);
     int64_t* c_h = lm_take(h, L, &c_d);
+    int64_t* b1_h = lm_take(h, L, &b1_d);
+    int64_t* a2_h = lm_take(h, L, &a2_d);
+    int64_t* b2_h = lm_take(h, L, &b2_d);
     int maxn = 1;
     for (int q = 0; q < L; ++q) {
       const int g = lr[q];
       m_h[q] = ncols;
       n_h[q] = t1[g];
       k_h[q] = rows[g];
+      k2_h[q] = 0;
       a_h[q] = srow[g];                               // row offset of the tile in the workspace (contigT frame)
       b_h[q] = (int64_t)g * nb * h->smax;             // Q1 block
       c_h[q] = (int64_t)g * nb * h->smax;             // Bt block
+      b1_h[q] = a2_h[q] = b2_h[q] = 0;
       maxn = std::max(maxn, n_h[q]);
       cflops += 2.0 * ncols * t1[g] * k_h[q];
     }
-    im_push(h, m_h, m_d, 3 * (int64_t)L);
-    lm_push(h, a_h, a_d, 3 * (int64_t)L);
     int big_m = 0;
     int* nn_d = nullptr;
     int64_t *so_d = nullptr, *do_d = nullptr;
@@ -985,67 +1075,120 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
       im_push(h, nn_h, nn_d, nbg);
       lm_push(h, so_h, so_d, 2 * (int64_t)nbg);
     }
-    GemmBatch gbt{};   // G_q = -(W_q^T Q1_q): fold.K x t1, at gbuf + offset
+    GemmBatch gbt{};   // [G; H]_q = -(W_q^T Q1_q): (K + cr) x t1 at gbuf + offset, leading dimension Kg
     int* gm_h = nullptr;
     int* gn_h = nullptr;
-    int64_t* b1_d = nullptr;
-    if (nf > 0) {
+    if (nfq > 0) {
       int *gm_d, *gn_d, *gk_d;
-      gm_h = im_take(h, nf, &gm_d);
-      gn_h = im_take(h, nf, &gn_d);
-      int* gk_h = im_take(h, nf, &gk_d);
+      gm_h = im_take(h, nfq, &gm_d);
+      gn_h = im_take(h, nfq, &gn_d);
+      int* gk_h = im_take(h, nfq, &gk_d);
       int64_t *ga_d, *gb_d, *gc_d;
-      int64_t* ga_h = lm_take(h, nf, &ga_d);
-      int64_t* gb_h = lm_take(h, nf, &gb_d);
-      int64_t* gc_h = lm_take(h, nf, &gc_d);
-      int64_t* b1_h = lm_take(h, nf, &b1_d);
+      int64_t* ga_h = lm_take(h, nfq, &ga_d);
+      int64_t* gb_h = lm_take(h, nfq, &gb_d);
+      int64_t* gc_h = lm_take(h, nfq, &gc_d);
       int64_t goff = 0;
-      for (int q = 0; q < nf; ++q) {
-        const int g = lr[q];
-        gm_h[q] = fo.K;
-        gn_h[q] = t1[g];
-        gk_h[q] = rows[g];
-        ga_h[q] = (int64_t)(1 + tloc[g]) * nb;        // W rows of the tile
-        gb_h[q] = (int64_t)g * nb * h->smax;          // Q1 block
-        gc_h[q] = goff;
-        b1_h[q] = goff;
-        goff += (int64_t)fo.K * t1[g];
-        cflops += 2.0 * fo.K * t1[g] * (double)rows[g] + 2.0 * ncols * t1[g] * (double)fo.K;
+      int i = 0;
+      for (const FoldRange& r : fr) {
+        const FoldOut& f = jobs[r.k].fold;
+        const int64_t wofs = f.W - h->Wf;
+        for (int q = r.b; q < r.e; ++q, ++i) {
+          const int g = lr[q], t = tloc[g];
+          gm_h[i] = gm_of(q);
+          gn_h[i] = t1[g];
+          gk_h[i] = rows[g];
+          ga_h[i] = wofs + (int64_t)(1 + t) * nb;      // W rows of the tile
+          gb_h[i] = (int64_t)g * nb * h->smax;          // Q1 block
+          gc_h[i] = goff;
+          b1_h[q] = goff;
+          if (f.corr) {
+            k2_h[q] = f.cr[t];
+            a2_h[q] = f.cp[t] * nb;
+            b2_h[q] = goff + f.K;
+          }
+          goff += (int64_t)Kg * t1[g];
+          cflops += 2.0 * gm_h[i] * t1[g] * (double)rows[g] + 2.0 * ncols * t1[g] * (double)gm_h[i];
+        }
       }
-      im_push(h, gm_h, gm_d, 3 * (int64_t)nf);
-      lm_push(h, ga_h, ga_d, 4 * (int64_t)nf);
-      gbt.count = nf; gbt.m_of = gm_d; gbt.n_of = gn_d; gbt.k_of = gk_d;
+      im_push(h, gm_h, gm_d, 3 * (int64_t)nfq);
+      lm_push(h, ga_h, ga_d, 3 * (int64_t)nfq);
+      gbt.count = nfq; gbt.m_of = gm_d; gbt.n_of = gn_d; gbt.k_of = gk_d;
       gbt.a_off = ga_d; gbt.b_off = gb_d; gbt.c_off = gc_d;
       flat_tiles(h, gbt, 64, 64, gm_h, gn_h);
     }
-    GemmBatch btf{}, btr{};   // projections of the folded tiles and of the rest
-    btf.count = nf; btf.m_of = m_d; btf.n_of = n_d; btf.k_of = k_d;
-    btf.a_off = a_d; btf.b_off = b_d; btf.c_off = c_d; btf.b_off1 = b1_d;
-    btr.count = L - nf; btr.m_of = m_d + nf; btr.n_of = n_d + nf; btr.k_of = k_d + nf;
-    btr.a_off = a_d + nf; btr.b_off = b_d + nf; btr.c_off = c_d + nf;
-    if (nf > 0) flat_tiles(h, btf, 128, 32, m_h, n_h);
-    if (L > nf) flat_tiles(h, btr, 128, 32, m_h + nf, n_h + nf);
+    im_push(h, m_h, m_d, 4 * (int64_t)L);
+    lm_push(h, a_h, a_d, 6 * (int64_t)L);
+    // launches of the projection: one per folded job, then the other tiles
+    // (ranges of lr; the non-folded ones are merged when adjacent)
+    struct ProjRange {
+      int k, b, e;   // k < 0: not folded
+    };
+    std::vector<ProjRange> pr;
+    {
+      size_t f = 0;
+      for (int q = 0; q < L;) {
+        if (f < fr.size() && fr[f].b == q) {
+          pr.push_back({fr[f].k, fr[f].b, fr[f].e});
+          q = fr[f].e;
+          ++f;
+          continue;
+        }
+        int e = q;
+        while (e < L && !(f < fr.size() && fr[f].b == e)) ++e;
+        pr.push_back({-1, q, e});
+        q = e;
+      }
+    }
+    std::vector<GemmBatch> pbt(pr.size());
+    for (size_t i = 0; i < pr.size(); ++i) {
+      const int b = pr[i].b;
+      GemmBatch& bt = pbt[i];
+      bt.count = pr[i].e - b; bt.m_of = m_d + b; bt.n_of = n_d + b; bt.k_of = k_d + b;
+      bt.a_off = a_d + b; bt.b_off = b_d + b; bt.c_off = c_d + b;
+      if (pr[i].k >= 0) {
+        bt.b_off1 = b1_d + b;
+        if (jobs[pr[i].k].fold.corr) {
+          bt.a_off2 = a2_d + b; bt.b_off2 = b2_d + b; bt.k_of2 = k2_d + b;
+        }
+      }
+      flat_tiles(h, bt, 128, 32, m_h + b, n_h + b);
+    }
     int n_ay = 0;
     const int* ay_items = apply_items(h, hq_ay, L, &n_ay);
     HIPCHK(launch_hqr_apply(h->hq_d + gc, L, h->s, max_kx, ay_items, n_ay));
     dbg_mark(h, 18, h->s);
     {
-      GemmSeg sg[2] = {};
-      sg[0].A = op_contigT(h->colbase, ld, 0, 0);
-      sg[0].B = op_contigT(h->Q1, nb, 0, 0);
-      sg[0].K = nb;
-      if (nf > 0) {
+      if (nfq > 0) {
         GemmSeg gs{};
-        gs.A = op_contigT(fo.W, fo.ldw, 0, 0);
+        gs.A = op_contigT(h->Wf, jobs[fr[0].k].fold.ldw, 0, 0);
         gs.B = op_contigT(h->Q1, nb, 0, 0);
         gs.K = nb;
-        gemm(h, fo.K, maxn, 1, &gs, h->gbuf, fo.K, epi_linear(-1.0, 0.0), &gbt, false, 64, 64, gm_h, gn_h);
-        sg[1].A = op_contig(fo.U, nb, 0, 0);
-        sg[1].B = op_contigT(h->gbuf, fo.K, 0, 0);
-        sg[1].K = fo.K;
-        gemm(h, ncols, maxn, 2, sg, h->Bt, nb, epi_linear(1.0, 0.0), &btf, false, 128, 32, m_h, n_h);
+        gemm(h, Kg, maxn, 1, &gs, h->gbuf, Kg, epi_linear(-1.0, 0.0), &gbt, false, 64, 64, gm_h, gn_h);
       }
-      if (L > nf) gemm(h, ncols, maxn, 1, sg, h->Bt, nb, epi_linear(1.0, 0.0), &btr, false, 128, 32, m_h + nf, n_h + nf);
+      for (size_t i = 0; i < pr.size(); ++i) {
+        GemmSeg sg[3] = {};
+        sg[0].A = op_contigT(h->colbase, ld, 0, 0);
+        sg[0].B = op_contigT(h->Q1, nb, 0, 0);
+        sg[0].K = nb;
+        int nsg = 1;
+        if (pr[i].k >= 0) {
+          const FoldOut& f = jobs[pr[i].k].fold;
+          sg[1].A = op_contig(f.U, nb, 0, 0);
+          sg[1].B = op_contigT(h->gbuf, Kg, 0, 0);
+          sg[1].K = f.K;
+          nsg = 2;
+          if (f.corr) {
+            int kc = 0;
+            for (int q = pr[i].b; q < pr[i].e; ++q) kc = std::max(kc, k2_h[q]);
+            sg[2].A = op_contig(f.Pc, nb, 0, 0);
+            sg[2].B = op_contigT(h->gbuf, Kg, 0, 0);
+            sg[2].K = std::max(kc, 1);
+            nsg = 3;
+          }
+        }
+        const int b = pr[i].b;
+        gemm(h, ncols, maxn, nsg, sg, h->Bt, nb, epi_linear(1.0, 0.0), &pbt[i], false, 128, 32, m_h + b, n_h + b);
+      }
     }
     dbg_mark(h, 6, h->s);
     HIPCHK(launch_hqr_factor(h->hq_d + 2 * gc, L, h->s));
@@ -1119,12 +1262,13 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
                    jb.F == &h->fam[1] ? "'" : "", jb.T, rounds, s_max, t1_max, k_max, nbig, nd);
     }
   }
-  // a folded job's dense tiles take their pending term before they are copied
-  if (ndense > 0 && jobs[0].fold.K > 0) {
+  // a folded job's dense tiles take their pending terms before they are copied
+  for (int k = 0; k < (int)jobs.size() && ndense > 0; ++k) {
+    if (jobs[k].fold.K <= 0) continue;
     std::vector<int> gs;
     for (int g = 0; g < G; ++g)
-      if (dense[g] && jof[g] == 0) gs.push_back(g);
-    fold_apply(gs);
+      if (dense[g] && jof[g] == k) gs.push_back(g);
+    fold_apply(k, gs);
   }
   // 6. V~ = Q_b [Q_r; 0] and U_g = Q1_g Z_g (m_g x k_g) for the low-rank tiles
   int64_t k_chunks = 0;   // 16-column chunks of the V~ (and Q_r) applications
@@ -1351,9 +1495,11 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       Ktrue += r;
     }
   const size_t e_urow = prof_mark(h);
-  // U_row (nb_j x R): the right factors of row j, side by side
+  // U_row (nb_j x R): the right factors of row j, side by side (a folded
+  // tangent column builds it where its compression reads it)
+  double* Ut = (fold && fold->udst) ? fold->udst : h->Urow;
   if (R > 0) {
-    if ((int64_t)nb * R > h->urow_cap) NOMEM("row factor buffer");
+    if (!(fold && fold->udst) && (int64_t)nb * R > h->urow_cap) NOMEM("row factor buffer");
     int cnt = 0;
     for (int tm = 0; tm < nterms; ++tm)
       for (int k = kb; k < ke; ++k)
@@ -1381,9 +1527,14 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       }
     im_push(h, m_h, m_d, 2 * (int64_t)cnt);
     lm_push(h, so_h, so_d, 2 * (int64_t)cnt);
-    HIPCHK(launch_batched_copy(h->arena, nb, so_d, h->Urow, nb, do_d, m_d, k_d, maxe, cnt, h->s));
+    HIPCHK(launch_batched_copy(h->arena, nb, so_d, Ut, nb, do_d, m_d, k_d, maxe, cnt, h->s));
   }
   prof_add(h, TLR_K_LOWRANK, e_urow, 0.0, 16.0 * nbj * (double)Ktrue);
+  // W in the fold buffer when the caller asks for a fold (one chunk, its own
+  // leading dimension), else in this stream's scratch
+  const bool fb = fold && fold->wdst && R > 0 && R + fold->extra <= fold->wcols;
+  double* Wt = fb ? fold->wdst : h->Wb;
+  const int64_t wcap = fb ? fold->wld * (int64_t)fold->wcols : h->w_cap;
   // chunks of row tiles [i0, i1) such that W and X fit
   int i0 = j;
   while (i0 < nt) {
@@ -1397,20 +1548,20 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           const int a = terms[tm].Fi->rk[tid_of(h, i1, k)];
           xadd += (int64_t)(a > h->maxrank ? nb : h->maxrank) * terms[tm].Fj->rk[tid_of(h, j, k)];
         }
-      if (wrows * std::max<int64_t>(R, 1) > h->w_cap || xneed + xadd > h->x_cap) break;
+      if (wrows * std::max<int64_t>(R, 1) > wcap || xneed + xadd > h->x_cap) break;
       xneed += xadd;
       ++i1;
     }
     if (i1 == i0) NOMEM("W/X workspace for one row of tiles");
     int64_t mrows = 0;
     for (int i = i0; i < i1; ++i) mrows += tile_rows(h, i);
-    const int64_t ldw = (int64_t)(i1 - i0) * nb;
+    const int64_t ldw = fb ? fold->wld : (int64_t)(i1 - i0) * nb;
     const size_t e_w = prof_mark(h);
     double wflops = 0.0, wbytes = 0.0;
     if (R > 0) {
       const int64_t pairs = (int64_t)nterms * (i1 - i0) * j;
       meta_reserve(h, 6 * pairs, 6 * pairs);
-      HIPCHK(launch_fill(h->Wb, ldw, ldw, R, 0.0, h->s));
+      HIPCHK(launch_fill(Wt, ldw, (int64_t)(i1 - i0) * nb, R, 0.0, h->s));
       int64_t xoff = 0;
       // pairs grouped by the kind of the left tile: low-rank (a <= maxrank) and dense
       for (int tm = 0; tm < nterms; ++tm)
@@ -1481,21 +1632,21 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
           wb.a_off = wa_d; wb.b_off = wb_d; wb.c_off = wc_d;
           if (grp == 0 && maxa <= kThinMaxK) {
             // W_ik = U_ik X_ik, inner dimension a rank: a streaming kernel
-            HIPCHK(launch_thin_gemm(h->arena, nb, h->Xb, maxa, h->Wb, ldw, wb, maxrows, maxa, maxb, h->s));
+            HIPCHK(launch_thin_gemm(h->arena, nb, h->Xb, maxa, Wt, ldw, wb, maxrows, maxa, maxb, h->s));
           } else {
             GemmSeg ws{};
             ws.A = op_contig(h->arena, nb, 0, 0);
             ws.B = op_contigT(h->Xb, maxa, 0, 0);
             ws.K = maxa;
-            gemm(h, maxrows, maxb, 1, &ws, h->Wb, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32, wm_h, wn_h);
+            gemm(h, maxrows, maxb, 1, &ws, Wt, ldw, epi_linear(1.0, 0.0), &wb, false, 128, 32, wm_h, wn_h);
           }
         }
     }
     prof_add(h, TLR_K_LOWRANK, e_w, wflops, wbytes);
     // column GEMM with generation epilogue
     GemmSeg cs{};
-    cs.A = op_contig(h->Wb, ldw, 0, 0);
-    cs.B = op_contig(h->Urow, nb, 0, 0);
+    cs.A = op_contig(Wt, ldw, 0, 0);
+    cs.B = op_contig(Ut, nb, 0, 0);
     cs.K = R;
     // Matern generation of the block, then C -= W U_row^T
     double* cblk = out + (int64_t)(i0 - j) * nb;
@@ -1506,9 +1657,10 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       prof_add(h, TLR_K_GEN, eg, 0.0, 8.0 * (double)mrows * nbj);
     }
     // fold: one chunk from the diagonal tile to the last row, no generation;
-    // only the diagonal tile is updated here (W and U_row stay in this
-    // stream's scratch for the compression)
-    const bool folding = fold && !gen && i0 == j && i1 == nt && R > 0 && R <= h->maxrank;
+    // only the diagonal tile is updated here (W and U_row stay for the
+    // compression); a tangent column (fold->corr) keeps fold->extra columns
+    // of W after the term's own for its correction
+    const bool folding = fb && !gen && i0 == j && i1 == nt && (fold->corr || R <= h->maxrank);
     const bool split = !folding && rest_on && !gen && i0 == j && i1 == nt && mrows > nbj && h->prof != 2;
     const int64_t grows = (folding || split) ? nbj : mrows;
     prof_alone_begin(h);
@@ -1528,7 +1680,7 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       hipStream_t own = h->s;
       h->s = rest_on;
       GemmSeg rs = cs;
-      rs.A = op_contig(h->Wb + nbj, ldw, 0, 0);
+      rs.A = op_contig(Wt + nbj, ldw, 0, 0);
       const int64_t rrows = mrows - nbj;
       const size_t e1 = prof_mark(h);
       gemm(h, rrows, nbj, 1, &rs, cblk + nbj, h->n, epi_linear(-1.0, 1.0), nullptr, false, 0, 0, nullptr, nullptr,
@@ -1540,9 +1692,9 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
       h->rest_pending = true;
     }
     if (folding) {
-      fold->W = h->Wb;
+      fold->W = Wt;
       fold->ldw = ldw;
-      fold->U = h->Urow;
+      fold->U = Ut;
       fold->K = (int)R;
     }
     i0 = i1;
@@ -1822,9 +1974,39 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
   // dC(:, j) = dSigma/dbeta - sum_k [dL_ik L_jk^T + L_ik dL_jk^T]; the
   // tangent of the diagonal step; dC_ij <- dC_ij - L_ij dL_jj^T (then
   // compressed: dL_ij = (that) L_jj^{-T}, low-rank V <- L_jj^{-1} V)
-  auto tangent_update = [&](int j, int kb, int ke, bool gen, hipStream_t rest_on = nullptr) {
+  auto tangent_update = [&](int j, int kb, int ke, bool gen, hipStream_t rest_on = nullptr,
+                            FoldOut* fold = nullptr) {
     LRTerm tt[2] = {{&G, &P}, {&P, &G}};
-    tlr_column_update(h, j, 2, tt, tbuf(j), kEpiDGenMinus, kb, ke, gen, nullptr, rest_on);
+    tlr_column_update(h, j, 2, tt, tbuf(j), kEpiDGenMinus, kb, ke, gen, fold, rest_on);
+  };
+  // Whether tangent column j's last term (beyond its diagonal tile) and its
+  // correction can be left to its compression, and where their factors go:
+  // W in the fold buffer's tangent part with the primal tiles' U after the
+  // term's columns; U_row then the P_t side by side behind the V~ copies in
+  // Ptmp; -(Omega^T [U_row P]) in zst2.  Needs every primal tile of column j
+  // low-rank, and the ranks within those buffers.
+  auto tangent_fold_setup = [&](int j, FoldOut& f) {
+    const int T = nt - j - 1;
+    if (!h->Wf || j == 0 || T <= 0 || h->upd_tag == 2) return false;
+    int kc = 0;
+    int64_t rsum = 0;
+    for (int t = 0; t < T; ++t) {
+      const size_t id = tid_of(h, j + 1 + t, j);
+      if (P.isdense[id] || P.rk[id] > h->maxrank) return false;
+      kc = std::max(kc, P.rk[id]);
+      rsum += std::max(P.rk[id], 0);
+    }
+    const int64_t R = (int64_t)P.rk[tid_of(h, j, j - 1)] + G.rk[tid_of(h, j, j - 1)];
+    if (R <= 0 || R + kc > h->wf_tcols || rsum > kFoldRsumMax || R + rsum > h->zst2_cols ||
+        (int64_t)nb * (2 * rsum + R) > h->ptmp_cap)
+      return false;
+    f.wdst = h->Wf + h->wf_ld * h->wf_pcols;
+    f.wld = h->wf_ld;
+    f.wcols = h->wf_tcols;
+    f.udst = h->Ptmp + (int64_t)nb * rsum;
+    f.extra = kc;
+    f.corr = true;
+    return true;
   };
   // the correction below reads and writes the rows below the diagonal tile
   auto rest_wait = [&]() {
@@ -1832,7 +2014,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     HIPCHK(hipStreamWaitEvent(h->s, h->ev_rest, 0));
     h->rest_pending = false;
   };
-  auto tangent_rest = [&](int j) {
+  auto tangent_rest = [&](int j, FoldOut* tf = nullptr) {
     const int nbj = tile_rows(h, j);
     double* cold = tbuf(j);
     double* ddj = h->Dd + (int64_t)j * nb * nb;
@@ -1842,6 +2024,82 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     dbg_mark(h, 15, h->s);
     const int T = nt - j - 1;
     if (T <= 0) return;
+    if (tf && tf->K > 0) {
+      // folded: the correction's factors for the compression instead of
+      // dC_t -= U_t P_t^T over the column.  P_t = dL_jj V~_t for all tiles
+      // (the V~_t side by side, one GEMM) behind U_row; the primal U_t into
+      // W beside the last term's columns; Zs = -(Omega^T [U_row P]).
+      const size_t e_c = prof_mark(h);
+      double cf = 0.0;
+      int64_t rsum = 0;
+      int cnt = 0;
+      tf->cu.assign(T, 0);
+      tf->cr.assign(T, 0);
+      tf->cp.assign(T, 0);
+      for (int t = 0; t < T; ++t) {
+        const size_t id = tid_of(h, j + 1 + t, j);
+        tf->cu[t] = P.uoff[id];
+        tf->cr[t] = P.rk[id];
+        tf->cp[t] = rsum;
+        rsum += P.rk[id];
+        if (P.rk[id] > 0) ++cnt;
+      }
+      const int64_t R = tf->K;
+      double* vcat = h->Ptmp;
+      double* pcat = h->Ptmp + (int64_t)nb * (rsum + R);
+      tf->Pc = pcat;
+      if (cnt > 0) {
+        meta_reserve(h, 4 * (int64_t)cnt, 4 * (int64_t)cnt);
+        int *m_d, *k_d, *m2_d, *k2_d;
+        int* m_h = im_take(h, cnt, &m_d);
+        int* k_h = im_take(h, cnt, &k_d);
+        int* m2_h = im_take(h, cnt, &m2_d);
+        int* k2_h = im_take(h, cnt, &k2_d);
+        int64_t *so_d, *do_d, *so2_d, *do2_d;
+        int64_t* so_h = lm_take(h, cnt, &so_d);
+        int64_t* do_h = lm_take(h, cnt, &do_d);
+        int64_t* so2_h = lm_take(h, cnt, &so2_d);
+        int64_t* do2_h = lm_take(h, cnt, &do2_d);
+        int q = 0;
+        int64_t maxe = 0, maxe2 = 0;
+        for (int t = 0; t < T; ++t) {
+          const size_t id = tid_of(h, j + 1 + t, j);
+          if (P.rk[id] <= 0) continue;
+          m_h[q] = nbj; k_h[q] = P.rk[id];
+          so_h[q] = P.voff[id];
+          do_h[q] = tf->cp[t] * nb;
+          m2_h[q] = tile_rows(h, j + 1 + t); k2_h[q] = P.rk[id];
+          so2_h[q] = P.uoff[id];
+          do2_h[q] = (tf->W - h->Wf) + (int64_t)(1 + t) * nb + R * tf->ldw;
+          maxe = std::max<int64_t>(maxe, (int64_t)nbj * P.rk[id]);
+          maxe2 = std::max<int64_t>(maxe2, (int64_t)m2_h[q] * P.rk[id]);
+          ++q;
+        }
+        im_push(h, m_h, m_d, 4 * (int64_t)cnt);
+        lm_push(h, so_h, so_d, 4 * (int64_t)cnt);
+        HIPCHK(launch_batched_copy(h->arena, nb, so_d, vcat, nb, do_d, m_d, k_d, maxe, cnt, h->s));
+        HIPCHK(launch_batched_copy(h->arena, nb, so2_d, h->Wf, tf->ldw, do2_d, m2_d, k2_d, maxe2, cnt, h->s));
+        GemmSeg ps{};
+        ps.A = op_contig(ddj, nb, 0, 0);
+        ps.B = op_contigT(vcat, nb, 0, 0);
+        ps.K = nbj;
+        gemm(h, nbj, rsum, 1, &ps, pcat, nb, epi_linear(1.0, 0.0), nullptr, false, 64, 64);
+        cf += 2.0 * nbj * nbj * (double)rsum;
+      }
+      GemmSeg zs{};
+      zs.A = op_contigT(h->omega, nb, 0, 0);
+      zs.B = op_contigT(tf->U, nb, 0, 0);   // U_row, then P right behind it
+      zs.K = nbj;
+      gemm(h, h->smax, R + rsum, 1, &zs, h->zst2, h->smax, epi_linear(-1.0, 0.0));
+      cf += 2.0 * h->smax * (double)(R + rsum) * nbj;
+      tf->zs = h->zst2;
+      prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
+      dbg_mark(h, 16, h->s);
+      return;
+    }
+    // a fold that was set up but not taken left U_row in Ptmp, where the rows
+    // below (on the diagonal-step stream) read it: wait for them first
+    if (tf && tf->udst) rest_wait();
     int kmax = 0, cnt = 0;
     for (int t = 0; t < T; ++t) {
       const int r = P.rk[tid_of(h, j + 1 + t, j)];
@@ -2066,7 +2324,10 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       // as fast as the GPU runs these short kernels.
       // The last term of primal column j + 1 updates only its diagonal tile
       // here; the tiles below take it inside their compression (fold).
-      FoldOut pfold;
+      FoldOut pfold, tfold;
+      pfold.wdst = h->Wf;
+      pfold.wld = h->wf_ld;
+      pfold.wcols = h->wf_pcols;
       if (j + 1 < nt) {
         primal_update(j + 1, j, j + 1, false, &pfold);
         HIPCHK(hipEventRecord(h->ev_post, h->s_main));
@@ -2079,9 +2340,13 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         dbg_mark(h, 2, h->s);
         // the tangent's rows below its diagonal tile on the diagonal-step stream
         // (idle here), beside the tangent of the diagonal step
-        tangent_update(j, j - 1, j, false, h->s_diag);
+        // its rows below the diagonal tile and its correction folded into the
+        // compression when they fit (tfold.K > 0), else on the diagonal-step
+        // stream and here
+        if (!tangent_fold_setup(j, tfold)) tfold = FoldOut{};
+        tangent_update(j, j - 1, j, false, h->s_diag, tfold.wdst ? &tfold : nullptr);
         dbg_mark(h, 14, h->s);
-        tangent_rest(j);
+        tangent_rest(j, &tfold);
         rest_wait();
         HIPCHK(hipEventRecord(h->ev_join, h->s));
         dbg_mark(h, 3, h->s);
@@ -2107,6 +2372,7 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       }
       jobs.push_back(tangent_job(j));
       jobs.back().wait = h->ev_join;
+      jobs.back().fold = tfold;
       jobs.back().sketch_stream = h->s_side;
       // The compressions of step j are issued first; the host issues the pre
       // parts of step j + 1 (side stream) in its first wait, for the range

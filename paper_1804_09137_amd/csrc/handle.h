@@ -40,6 +40,9 @@ using namespace tlrk;
 
 namespace tlri {
 constexpr int64_t kAlign = 16;
+// a tangent column's correction is folded into its compression only while
+// the primal column's ranks sum to at most this many columns
+constexpr int kFoldRsumMax = 8192;
 inline int64_t pad16(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 }  // namespace tlri
 
@@ -185,6 +188,14 @@ struct tlr_handle_s {
   double* lrtws = nullptr;  // nt x kLrMaxRank: the low-rank apply's t = B^T v per tile
   double* gbuf = nullptr;   // -(W_i^T Q1_i) of a folded column's tiles, gbuf_cap doubles
   int64_t gbuf_cap = 0;
+  // the W of folded column updates: the primal column's (wf_ld rows apart,
+  // wf_pcols columns) then the tangent column's (wf_tcols columns), one
+  // leading dimension so that one launch takes the projections' W^T Q1
+  double* Wf = nullptr;
+  int64_t wf_cap = 0, wf_ld = 0;
+  int wf_pcols = 0, wf_tcols = 0;
+  double* zst2 = nullptr;   // smax x zst2_cols: -(Omega^T [U P]) of a folded tangent column
+  int zst2_cols = 0;
   AcaTask* aca_d = nullptr;  // gcap ACA task records (tlr_compress with TLR_FLAG_ACA)
   AcaTask* aca_h = nullptr;
   int* qr_d = nullptr;  // 2 * gcap: ranks, flags

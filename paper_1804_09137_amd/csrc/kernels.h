@@ -9,7 +9,7 @@ hipError_t launch_matern_block(const MaternParams& p, const double* x, const dou
                                int64_t c0, int64_t ncol, double* out, int64_t ld, bool deriv, hipStream_t s);
 
 // ------------------------------------------------------------------ gemm.hip
-// C[M x N] = epilogue( sum_s A_s[M x K_s] * B_s[N x K_s]^T ), FP64 MFMA.
+// C[M x N] = epilogue( sum_s A_s[M x K_s] * B_s[N x K_s]^T ), FP64 MFMA, up to 3 segments.
 // Operand layouts: kContig (rows contiguous), kContigT (columns contiguous,
 // i.e. X[r, c] = base[(r0 + r) * ld + c0 + c]) and kPanels.
 enum : int { kContigT = 2 };
@@ -55,6 +55,13 @@ struct GemmBatch {
   // optional device arrays: per-batch element offsets of segment 1's A and B
   const int64_t* a_off1;
   const int64_t* b_off1;
+  // optional device arrays: per-batch element offsets of segment 2's A and B,
+  // and per-batch K of segments 1 and 2 (at most the segment's K; the rest of
+  // the segment reads as zero)
+  const int64_t* a_off2;
+  const int64_t* b_off2;
+  const int* k_of1;
+  const int* k_of2;
 };
 
 // Returns hipErrorInvalidValue on bad shapes.  work (may be null) must hold
@@ -69,6 +76,14 @@ struct GemmBatch {
 hipError_t launch_gemm(int64_t M, int64_t N, int nseg, const GemmSeg* segs, double* C, int64_t ldc,
                        const GemmEpi& ep, const GemmBatch* batch, int splitk, double* work, hipStream_t s,
                        int tile_m = 0, int tile_n = 0, int tag = 0);
+
+// ----------------------------------------------------------- gemm_update.hip
+// C = alpha A B^T + beta C (ep linear) by the column-update kernel when the call
+// fits it: one segment, both operands kContig with even leading dimensions
+// and 16-byte aligned origins, N = 256 q or 256 q + 32.  Returns false (and
+// launches nothing) otherwise; else *err is the launch status.
+bool launch_gemm_update(const GemmSeg& sg, int64_t M, int64_t N, double* C, int64_t ldc, const GemmEpi& ep,
+                        hipStream_t s, hipError_t* err);
 
 // C_p = alpha A_p B_p + beta C_p for a batch of products with a small inner
 // dimension (k_p <= kThinMaxK): batch supplies m_of, n_of, k_of and the
