@@ -57,8 +57,11 @@ def test_dense_gradient_central_difference():
     assert abs(gs - fds) <= 1e-6 * max(1.0, abs(fds))
 
 
+# (4321, 800): the column-update kernel's tiles of 256 columns plus the 32
+# beyond 768, a ragged last tile (321 rows: update workgroups past M), and the
+# tangent columns folded into their compression
 @pytest.mark.parametrize("n,nb,th,eps", [(1600, 320, (1.0, 0.1, 0.5), 1e-9), (2000, 256, (1.0, 0.1, 1.0), 1e-7),
-                                         (1234, 160, (0.8, 0.05, 1.5), 1e-9)])
+                                         (1234, 160, (0.8, 0.05, 1.5), 1e-9), (4321, 800, (1.0, 0.1, 0.5), 1e-7)])
 def test_tlr_gradient_matches_oracle(n, nb, th, eps):
     x, y, z = field(n, 1, th)
     ref = D.gradient(x, y, z, th)
