@@ -703,10 +703,8 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
   }
   bool waited = false;   // the jobs' wait events are on the stream
   while (!todo.empty()) {
-    // job order, and by sketch width within a job (the sketch launches one
-    // tile width per run of equal-class widths)
-    std::stable_sort(todo.begin(), todo.end(),
-                     [&](int a, int b) { return jof[a] != jof[b] ? jof[a] < jof[b] : sz[a] < sz[b]; });
+    // job order (a job's tiles are sketched by one launch)
+    std::stable_sort(todo.begin(), todo.end(), [&](int a, int b) { return jof[a] < jof[b]; });
     const int cnt = (int)todo.size();
     // the factor's task list is uploaded before the sketch (no upload
     // between the two launches)
@@ -787,31 +785,18 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         sg[2].K = std::max(kc, 1);
         cflops += 2.0 * maxm * sw * (double)kc * sn;
       }
-      // the items come sorted by width within the job: one launch per tile
-      // width (32, 64 or 128 columns), so a narrow sketch does not fill a wide
-      // tile with padding
-      auto wcls = [](int w) { return w <= 32 ? 32 : (w <= 64 ? 64 : 128); };
-      for (int q0 = 0; q0 < sn;) {
-        const int cls = wcls(n_h[q0]);
-        int q1 = q0 + 1, subm = m_h[q0], subw = n_h[q0];
-        while (q1 < sn && wcls(n_h[q1]) == cls) {
-          subm = std::max(subm, m_h[q1]);
-          subw = std::max(subw, n_h[q1]);
-          ++q1;
-        }
-        GemmBatch bt{};
-        bt.count = q1 - q0; bt.m_of = m_d + q0; bt.n_of = n_d + q0; bt.a_off = a_d + q0; bt.c_off = c_d + q0;
-        bt.a_off1 = a1_d ? a1_d + q0 : nullptr;
-        if (co) {
-          bt.k_of2 = k2_d + q0;
-          bt.a_off2 = a2_d + q0;
-          bt.b_off2 = b2_d + q0;
-        }
-        gemm(h, subm, subw, nsg, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, cls, m_h + q0, n_h + q0);
-        q0 = q1;
+      // one launch of 128 x 32 tiles over all the job's tiles: a wide sketch
+      // takes several workgroups side by side, so its K loop (the column,
+      // plus the folded terms) is not the serial time of one wide tile
+      GemmBatch bt{};
+      bt.count = sn; bt.m_of = m_d; bt.n_of = n_d; bt.a_off = a_d; bt.c_off = c_d;
+      bt.a_off1 = a1_d;
+      if (co) {
+        bt.k_of2 = k2_d;
+        bt.a_off2 = a2_d;
+        bt.b_off2 = b2_d;
       }
-      (void)maxm;
-      (void)sw;
+      gemm(h, maxm, sw, nsg, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
       h->s = own;
     };
     // todo is in job order: [b, e) ranges of one job each
