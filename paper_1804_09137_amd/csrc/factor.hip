@@ -697,7 +697,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     zs.A = op_contigT(h->omega, nb, 0, 0);
     zs.B = op_contigT(jb.fold.U, nb, 0, 0);
     zs.K = ncols;
-    gemm(h, h->smax, jb.fold.K, 1, &zs, h->zst, h->smax, epi_linear(-1.0, 0.0));
+    gemm(h, h->smax, jb.fold.K, 1, &zs, h->zst, h->smax, epi_linear(-1.0, 0.0), nullptr, false, 64, 64);
     cflops += 2.0 * h->smax * (double)jb.fold.K * ncols;
     jb.fold.zs = h->zst;
   }
@@ -1650,7 +1650,10 @@ void tlr_column_update(tlr_handle_s* h, int j, int nterms, const LRTerm* terms, 
     const int64_t grows = (folding || split) ? nbj : mrows;
     prof_alone_begin(h);
     const size_t e0 = prof_mark(h);
-    gemm(h, grows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, true, 0, 0, nullptr, nullptr,
+    // the diagonal tile alone (folded or split column): 64 x 64 tiles, as
+    // 128 x 256 ones would leave all but a few dozen CUs idle
+    const int ht = grows == nbj ? 64 : 0;
+    gemm(h, grows, nbj, 1, &cs, cblk, h->n, epi_linear(-1.0, 1.0), nullptr, ht == 0, ht, ht, nullptr, nullptr,
          h->upd_tag);
     // algorithmic bytes: W and U_row read once, C read (generated) and written
     prof_add(h, TLR_K_UPDATE, e0, 2.0 * grows * nbj * (double)Ktrue,
@@ -2075,7 +2078,9 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
       zs.A = op_contigT(h->omega, nb, 0, 0);
       zs.B = op_contigT(tf->U, nb, 0, 0);   // U_row, then P right behind it
       zs.K = nbj;
-      gemm(h, h->smax, R + rsum, 1, &zs, h->zst2, h->smax, epi_linear(-1.0, 0.0));
+      // 64 x 64 tiles: the product is smax x (R + rsum) over K = nb, a few
+      // dozen 128 x 128 tiles with a long K loop each
+      gemm(h, h->smax, R + rsum, 1, &zs, h->zst2, h->smax, epi_linear(-1.0, 0.0), nullptr, false, 64, 64);
       cf += 2.0 * h->smax * (double)(R + rsum) * nbj;
       tf->zs = h->zst2;
       prof_add(h, TLR_K_LOWRANK, e_c, cf, 0.0);
