@@ -2283,7 +2283,8 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
     // tangent: "pre") runs on the side stream while step j - 1 compresses;
     // afterwards the last term, the diagonal steps and the tangent's
     // correction ("post") complete them, the primal on the main stream and
-    // the tangent on the side stream.
+    // the tangent on the side stream; the last terms beyond the diagonal
+    // tiles (and the tangent's correction) are folded into the compression.
     auto pre = [&](int j) {   // side stream: pre parts of step j
       SideStream ss(h);
       if (j + 1 < nt) primal_update(j + 1, 0, j, true);
@@ -2328,11 +2329,10 @@ void factor_tlr(tlr_handle_s* h, bool tangent) {
         SideStream ss(h);
         HIPCHK(hipStreamWaitEvent(h->s, h->ev_fin, 0));
         dbg_mark(h, 2, h->s);
-        // the tangent's rows below its diagonal tile on the diagonal-step stream
-        // (idle here), beside the tangent of the diagonal step
-        // its rows below the diagonal tile and its correction folded into the
-        // compression when they fit (tfold.K > 0), else on the diagonal-step
-        // stream and here
+        // the tangent's last term beyond its diagonal tile and its correction
+        // folded into the compression when they fit (tfold.K > 0); else the
+        // rows below on the diagonal-step stream (idle here), beside the
+        // tangent of the diagonal step, and the correction here
         if (!tangent_fold_setup(j, tfold)) tfold = FoldOut{};
         tangent_update(j, j - 1, j, false, h->s_diag, tfold.wdst ? &tfold : nullptr);
         dbg_mark(h, 14, h->s);
