@@ -61,20 +61,11 @@ struct HqrTask {
   int zcap;
   double* Z;
   int64_t ldz;
-  // factor, split != 0: only panel `panel` (columns 16 panel ..), without its
-  // trailing update (hqr_trail applies it); the rank epilogue runs with the
-  // last panel.  hqr_trail: the panel whose Q^T it applies.
-  int split;
-  int panel;
 };
 
 hipError_t launch_qrcp(const QrcpTask* d_tasks, int count, hipStream_t s, int max_m = kQrMaxRows);
 hipError_t launch_qrcp_reg(const QrcpTask* d_tasks, int count, hipStream_t s);
 hipError_t launch_hqr_factor(const HqrTask* d_tasks, int count, hipStream_t s);
-// Trailing update of one panel of a split factorisation: workgroup b applies
-// Q_p^T of task d_items[2b] (p = its `panel`) to the 16 columns from
-// 16 d_items[2b + 1] on (chunk index > panel).
-hipError_t launch_hqr_trail(const HqrTask* d_tasks, const int* d_items, int nitems, hipStream_t s);
 // X columns are split over workgroups kApplyCols at a time: max_kx must be
 // at least every task's kx (columns beyond the split it covers are left
 // untouched).

@@ -183,10 +183,8 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
   const int nref = m < s ? m : s;
   const int np = (nref + PB - 1) / PB;
   const int r0 = tid, r1 = tid + NT;
-  const int p_lo = tk.split ? tk.panel : 0;
-  const int p_hi = tk.split ? (tk.panel + 1 < np ? tk.panel + 1 : np) : np;
 
-  for (int p = p_lo; p < p_hi; ++p) {
+  for (int p = 0; p < np; ++p) {
     const int c0 = p * PB;
     const int mm = m - c0;
     const int pw = (s - c0) < PB ? (s - c0) : PB;
@@ -307,14 +305,11 @@ __global__ void __launch_bounds__(NT) hqr_factor_kernel(const HqrTask* __restric
       }
     }
     __syncthreads();
-    // 5. trailing columns: A -= V T^T V^T A (a split factorisation leaves
-    // them to hqr_trail)
-    if (!tk.split)
-      for (int col0 = c0 + PB; col0 < s; col0 += PB)
-        wy_update<true>(A, lda, c0, mm, col0, s, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
+    // 5. trailing columns: A -= V T^T V^T A
+    for (int col0 = c0 + PB; col0 < s; col0 += PB)
+      wy_update<true>(A, lda, c0, mm, col0, s, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
     __syncthreads();
   }
-  if (tk.split && tk.panel < np - 1) return;   // the rank needs the whole R
 
   if (tk.tol > 0.0 && tk.trunc) {
     // Truncation rank from the unpivoted R: dropping rows k.. of R leaves an
@@ -482,50 +477,6 @@ __global__ void __launch_bounds__(NT) hqr_apply_kernel(const HqrTask* __restrict
     for (int col0 = (tk.identity && c0 > x0) ? c0 : x0; col0 < kx; col0 += PB)
       wy_update<false>(X, ldx, c0, mm, col0, kx, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Trailing update of panel p of a split factorisation: A[:, cols] -= V_p T_p^T
-// V_p^T A[:, cols] for one 16-column chunk, the panel and T_p as hqr_factor
-// left them in A and tk.T.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT) hqr_trail_kernel(const HqrTask* __restrict__ tasks,
-                                                       const int* __restrict__ items) {
-  const HqrTask tk = tasks[items[2 * blockIdx.x]];
-  const int chunk = items[2 * blockIdx.x + 1];
-  __shared__ double P[PB * LDP];
-  __shared__ double red[NW * RS];
-  __shared__ double Wf[256], Wp[256], Ts[256];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int m = tk.m, s = tk.s;
-  const int nref = m < s ? m : s;
-  const int p = tk.panel;
-  const int c0 = p * PB;
-  const int col0 = chunk * PB;
-  if (m <= 0 || c0 >= nref || col0 <= c0 || col0 >= s) return;
-  gdouble* A = gptr(tk.A);
-  const int64_t lda = tk.lda;
-  const int mm = m - c0;
-  const int nlive = nref - c0;
-  if (tid < 256) Ts[tid] = gptr(tk.T)[(int64_t)p * 256 + tid];
-#pragma unroll
-  for (int c = 0; c < PB; ++c) {
-    const gdouble* ac = A + (int64_t)(c0 + c) * lda + c0;
-    for (int r = tid; r < mm; r += NT) P[c * LDP + r] = (c < nlive) ? ac[r] : 0.0;
-  }
-  __syncthreads();
-  const int rw = ((mm + NW * 16 - 1) / (NW * 16)) * 16;
-  const int nblk = rw / 16;
-  const int rb = w * rw;
-  double vx[MB][4];
-#pragma unroll
-  for (int b = 0; b < MB; ++b)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int cx = lane & 15;
-      vx[b][q] = (b < nblk) ? vval_lds(P, rb + 16 * b + 4 * q + (lane >> 4), cx, mm, cx < nlive) : 0.0;
-    }
-  wy_update<true>(A, lda, c0, mm, col0, s, rb, nblk, vx, P, nlive, red, Wf, Wp, Ts, tid, lane, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -927,13 +878,6 @@ hipError_t launch_hqr_apply(const HqrTask* d_tasks, int count, hipStream_t s, in
   const int chunks = max_kx > kApplyCols ? (max_kx + kApplyCols - 1) / kApplyCols : 1;
   hipLaunchKernelGGL(hqr_apply_kernel, dim3((unsigned)count, (unsigned)chunks), dim3(NT), 0, s, d_tasks,
                      (const int*)nullptr);
-  return hipGetLastError();
-}
-
-hipError_t launch_hqr_trail(const HqrTask* d_tasks, const int* d_items, int nitems, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-  if (!d_items) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hqr_trail_kernel, dim3((unsigned)nitems), dim3(NT), 0, s, d_tasks, d_items);
   return hipGetLastError();
 }
 
