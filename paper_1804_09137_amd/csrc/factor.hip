@@ -785,7 +785,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         sg[2].K = std::max(kc, 1);
         cflops += 2.0 * maxm * sw * (double)kc * sn;
       }
-      // one launch of 128 x 32 tiles over all the job's tiles: a wide sketch
+      // one launch of 64 x 32 tiles over all the job's tiles: a wide sketch
       // takes several workgroups side by side, so its K loop (the column,
       // plus the folded terms) is not the serial time of one wide tile
       GemmBatch bt{};
@@ -796,7 +796,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
         bt.a_off2 = a2_d;
         bt.b_off2 = b2_d;
       }
-      gemm(h, maxm, sw, nsg, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+      gemm(h, maxm, sw, nsg, sg, h->Ybuf, nb, epi_linear(1.0, 0.0), &bt, false, 64, 32, m_h, n_h);
       h->s = own;
     };
     // todo is in job order: [b, e) ranges of one job each
@@ -1136,7 +1136,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
           bt.a_off2 = a2_d + b; bt.b_off2 = b2_d + b; bt.k_of2 = k2_d + b;
         }
       }
-      flat_tiles(h, bt, 128, 32, m_h + b, n_h + b);
+      flat_tiles(h, bt, 64, 32, m_h + b, n_h + b);
     }
     int n_ay = 0;
     const int* ay_items = apply_items(h, hq_ay, L, &n_ay);
@@ -1172,7 +1172,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
           }
         }
         const int b = pr[i].b;
-        gemm(h, ncols, maxn, nsg, sg, h->Bt, nb, epi_linear(1.0, 0.0), &pbt[i], false, 128, 32, m_h + b, n_h + b);
+        gemm(h, ncols, maxn, nsg, sg, h->Bt, nb, epi_linear(1.0, 0.0), &pbt[i], false, 64, 32, m_h + b, n_h + b);
       }
     }
     dbg_mark(h, 6, h->s);
@@ -1337,7 +1337,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     lm_push(h, a_h, a_d, 3 * (int64_t)nlr);
     GemmBatch bt{};
     bt.count = nlr; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
-    flat_tiles(h, bt, 128, 32, m_h, n_h);
+    flat_tiles(h, bt, 64, 32, m_h, n_h);
     int n_qr = 0, n_ab = 0;
     const int* qr_items = nq > 0 ? apply_items(h, hq_qr, nq, &n_qr) : nullptr;
     const int* ab_items = apply_items(h, hq_ab, nlr, &n_ab);
@@ -1351,7 +1351,7 @@ void compress_columns(tlr_handle_s* h, std::vector<ColumnJob>& jobs, std::functi
     sg.A = op_contig(h->Q1, nb, 0, 0);
     sg.B = op_contigT(h->Zb, h->smax, 0, 0);
     sg.K = h->smax;
-    gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+    gemm(h, maxm, maxk, 1, &sg, h->arena, nb, epi_linear(1.0, 0.0), &bt, false, 64, 32, m_h, n_h);
     if (h->debug)
       h->host_ms[6] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - u0).count();
   }
@@ -1439,7 +1439,7 @@ void lowrank_trsm(tlr_handle_s* h, int col, int i_first, int T, const double* vt
   GemmBatch bt{};
   bt.count = items; bt.m_of = m_d; bt.n_of = n_d; bt.k_of = k_d; bt.a_off = a_d; bt.b_off = b_d; bt.c_off = c_d;
   const size_t e_t = prof_mark(h);
-  gemm(h, RB, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 128, 32, m_h, n_h);
+  gemm(h, RB, maxk, 1, &sg, h->arena, h->nb, epi_linear(1.0, 0.0), &bt, false, 64, 32, m_h, n_h);
   prof_add(h, TLR_K_LOWRANK, e_t, 2.0 * nbj * nbj * kt, 8.0 * (2.0 * nbj * kt + (double)nbj * nbj));
 }
 
