@@ -39,18 +39,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def fit_cpu_time(meds: dict, n_target: int):
+    """Extrapolates the CPU oracle's time from two measured sizes.
+
+    meds maps two sample sizes n1 < n2 to their median times.  Fits
+    t(n) = a n^2 + b n^3 exactly through both points.  b > 0 exactly when the
+    measured exponent p = log(t2/t1) / log(n2/n1) exceeds 2, and a >= 0 exactly
+    when p <= 3; outside that range (timing noise) it falls back to
+    t(n) = t2 (n / n2)^p with p clamped to [2, 3], which then sits on a bound,
+    so the result is continuous in t2/t1.  Returns (t(n_target), the law as
+    text, a, b), with a and b None for the fallback."""
+    import numpy as np
+    n1, n2 = sorted(meds)
+    t1, t2 = meds[n1], meds[n2]
+    # t = a n^2 + b n^3 through (n1, t1), (n2, t2)
+    b = (t2 / n2 ** 2 - t1 / n1 ** 2) / (n2 - n1)
+    a = t1 / n1 ** 2 - b * n1
+    if b > 0.0 and a >= 0.0:
+        return a * n_target ** 2 + b * n_target ** 3, f"{a:.3e} n^2 + {b:.3e} n^3", a, b
+    # noisy medians: a power law through the larger sample
+    pw = min(3.0, max(2.0, np.log(t2 / t1) / np.log(n2 / n1)))
+    return t2 * (n_target / n2) ** pw, f"{t2:.3e} (n / {n2})^{pw:.3f}", None, None
+
+
 def cpu_baseline(n_target: int, theta, n_sample: int) -> dict:
     """The CPU oracle's dense l + gradient (numpy/scipy FP64, explicit
     Sigma^{-1}) timed at n_sample / 2 and n_sample points of the same design,
     median of 3 runs each.  Its cost has an O(n^2) part (generating Sigma and
     both dSigma with scipy's Bessel function, the contractions) and an O(n^3)
     part (Cholesky, inverse, product): t(n) = a n^2 + b n^3 is fitted exactly
-    through the two medians and evaluated at n_target.  When the medians
-    grow by less than the n^3 law allows a non-negative a for (timing noise),
-    the split cannot be resolved: t(n) = t2 (n / n2)^p is used instead, with
-    p from the two medians clamped to [2, 3] (the smaller extrapolation)."""
+    through the two medians and evaluated at n_target; when no non-negative
+    split fits the medians (timing noise), the nearer pure law is used
+    (fit_cpu_time)."""
     import statistics
-    import numpy as np
     import synth
     from oracle import dense as D
     from oracle import ordering as O
@@ -68,18 +89,8 @@ def cpu_baseline(n_target: int, theta, n_sample: int) -> dict:
             log(f"[bench] CPU oracle n={ns} run {r + 1}/3: {ts[-1]:.2f} s")
         meds[ns] = statistics.median(ts)
     n1, n2 = sorted(meds)
-    # t = a n^2 + b n^3 through (n1, t1), (n2, t2)
     t1, t2 = meds[n1], meds[n2]
-    b = (t2 / n2 ** 2 - t1 / n1 ** 2) / (n2 - n1)
-    a = t1 / n1 ** 2 - b * n1
-    if b > 0.0 and a >= 0.0:
-        t_target = a * n_target ** 2 + b * n_target ** 3
-        law = f"{a:.3e} n^2 + {b:.3e} n^3"
-    else:   # noisy medians: a power law through the larger sample
-        pw = min(3.0, max(2.0, np.log(t2 / t1) / np.log(n2 / n1)))
-        t_target = t2 * (n_target / n2) ** pw
-        a = b = None
-        law = f"{t2:.3e} (n / {n2})^{pw:.3f}"
+    t_target, law, a, b = fit_cpu_time(meds, n_target)
     try:
         from threadpoolctl import threadpool_info
         cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else os.cpu_count()
