@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libtlrmle.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 HIP_SOURCES = ["matern.hip", "gemm.hip", "gemm_update.hip", "chol.hip", "tile_chol.hip", "compress.hip", "hqr.hip", "solve.hip",
-               "grad.hip", "factor.hip", "api.hip",
+               "grad.hip", "runtime.hip", "compress_cols.hip", "column_update.hip",
+               "factor.hip", "api.hip",
                "predict.hip", "noalloc.hip", "aca.hip"]
 CPP_SOURCES = ["morton.cpp"]
 

@@ -1,5 +1,5 @@
 // C-ABI entry points (include/tlr.h).  Each call validates its arguments,
-// then runs the drivers of factor.hip under guarded(), which turns internal
+// then runs the factorisation drivers under guarded(), which turns internal
 // failures into status codes.
 #include "handle.h"
 

@@ -1,7 +1,7 @@
 // Private header of the library (not part of the C-ABI): the handle behind
-// tlr_handle_t and the helpers shared by the factorisation drivers
-// (factor.hip), the C-ABI entry points (api.hip) and the kriging
-// prediction (predict.hip).
+// tlr_handle_t and the helpers shared by the factorisation's host code
+// (runtime.hip, compress_cols.hip, column_update.hip, factor.hip), the C-ABI
+// entry points (api.hip) and the kriging prediction (predict.hip).
 #pragma once
 #include "tlr.h"
 #include "common.h"
@@ -293,7 +293,7 @@ inline double* diag_tile(tlr_handle_s* h, int j) { return h->D + (int64_t)j * h-
 using Family = tlr_handle_s::Family;
 inline size_t tid_of(const tlr_handle_s* h, int i, int j) { return (size_t)i * h->nt + j; }
 
-// ---- drivers (factor.hip) used by the entry points ----
+// ---- drivers (factor.hip, runtime.hip) used by the entry points ----
 void sync(tlr_handle_s* h);
 void free_all(tlr_handle_s* h);
 float elapsed(hipEvent_t a, hipEvent_t b);

@@ -21,7 +21,7 @@
 #include <mutex>
 
 namespace tlri {
-extern thread_local char g_last_error[256];   // tlr_last_error's text (factor.hip)
+extern thread_local char g_last_error[256];   // tlr_last_error's text (runtime.hip)
 }
 
 using namespace tlrk;
