@@ -283,6 +283,7 @@ tlr_status tlr_compress(tlr_handle_t h) {
   if (h->dense) return TLR_ENOTIMPL;
   if (!h->bound) return TLR_ESTATE;
   return guarded(h, [&]() -> tlr_status {
+    arena_ensure(h);
     for (;;) {
       try {
         if (h->o.flags & TLR_FLAG_ACA) compress_sigma_aca(h); else compress_sigma(h);

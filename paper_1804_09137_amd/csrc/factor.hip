@@ -833,6 +833,7 @@ tlr_status factor_checked(tlr_handle_s* h, bool tangent, int64_t* info) {
   const bool f32 = h->o.prec == TLR_PREC_FP32_UPDATES && h->info.fp64_retries == 0;
   h->upd_tag = f32 ? 2 : 1;
   h->info.prec_used = f32 ? TLR_PREC_FP32_UPDATES : TLR_PREC_FP64;
+  arena_ensure(h);
   for (;;) {
     tlr_status st;
     h->splitk_count = 0;

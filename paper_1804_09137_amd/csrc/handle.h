@@ -307,6 +307,7 @@ void compress_sigma(tlr_handle_s* h);
 void compress_sigma_aca(tlr_handle_s* h);
 void arena_alloc(tlr_handle_s* h, int64_t cap);
 void arena_grow(tlr_handle_s* h);
+void arena_ensure(tlr_handle_s* h);
 void family_reset(tlr_handle_s* h, Family& F, int kind);
 void drop_history(tlr_handle_s* h);
 void family_upload(tlr_handle_s* h, Family& F);

@@ -397,8 +397,11 @@ void family_upload(tlr_handle_s* h, Family& F) {
 // (Re)allocate the TLR arena: identity block, inverses of the diagonal
 // tiles, then cap doubles of tile storage.  The previous arena (if any) is
 // freed first; its contents are not kept (a factorisation starts afresh).
+// When the new size cannot be had, the previous size is taken again (so that
+// the handle keeps storage for its next pass) and TLR_ENOMEM is reported.
 void arena_alloc(tlr_handle_s* h, int64_t cap) {
   const int64_t nb = h->nb, nt = h->nt;
+  const int64_t prev_cap = h->arena ? h->tile_cap : -1;
   if (h->arena) {
     sync(h);
     (void)hipFree(h->arena);
@@ -414,6 +417,13 @@ void arena_alloc(tlr_handle_s* h, int64_t cap) {
   void* p = nullptr;
   if (hipMalloc(&p, (size_t)h->arena_len * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
+    if (prev_cap >= 0 && prev_cap < h->tile_cap) {
+      try {
+        arena_alloc(h, prev_cap);
+      } catch (const Fail&) {
+        // left without an arena: arena_ensure() retries before the next pass
+      }
+    }
     throw Fail{TLR_ENOMEM};
   }
   h->arena = (double*)p;
@@ -422,6 +432,13 @@ void arena_alloc(tlr_handle_s* h, int64_t cap) {
   h->tile_used = 0;
   HIPCHK(launch_fill(h->arena + h->ident_off, nb, nb, nb, 0.0, h->s));
   HIPCHK(launch_identity(h->arena + h->ident_off, nb, nb, h->s));
+}
+
+// A TLR handle whose arena could not be reallocated gets it back (at the
+// capacity last asked for) before a pass uses it, or the pass fails with
+// TLR_ENOMEM.
+void arena_ensure(tlr_handle_s* h) {
+  if (!h->dense && !h->arena) arena_alloc(h, h->tile_cap);
 }
 
 // nd doubles of tile storage (128-byte aligned); TLR_ENOMEM when the arena is full
