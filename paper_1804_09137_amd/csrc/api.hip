@@ -107,8 +107,10 @@ tlr_status tlr_create(tlr_handle_t* out, const tlr_opts* o, void* stream) {
         const int64_t rg = std::max<int64_t>(12, mr / 16);
         cap = nfam * (h->ntiles * 2 * nb * pad16(rg) + nt * nb * nb);
         // TLR_ARENA_START (doubles) lowers the first automatic capacity, so
-        // that tests reach the doubling
-        if (const char* as = std::getenv("TLR_ARENA_START")) cap = std::min<int64_t>(cap, std::atoll(as));
+        // that tests reach the doubling (at least kAlign: a capacity that
+        // rounds down to 0 would double to 0 forever)
+        if (const char* as = std::getenv("TLR_ARENA_START"))
+          cap = std::min<int64_t>(cap, std::max<int64_t>(kAlign, std::atoll(as)));
       }
       for (int f = 0; f < 2; ++f) {
         Family& F = h->fam[f];
