@@ -568,6 +568,8 @@ extern "C" tlr_status tlr_loglik_grad_batched(int32_t nfields, const tlr_handle_
       if (hs[f]->device != dev) {
         dev = hs[f]->device;
         if (hipSetDevice(dev) != hipSuccess) {
+          (void)hipGetLastError();
+          dev = -1;   // not switched: the next field tries again
           st[f] = TLR_EHIP;
           continue;
         }
