@@ -21,6 +21,14 @@ def _lib():
     return _lib, _lib.load()
 
 
+def test_missing_library_raises(monkeypatch, tmp_path):
+    # no CPU fallback: without the built library the binding refuses to load
+    from paper_1804_09137_amd import _lib as m
+    monkeypatch.setattr(m, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        m.load(str(tmp_path / "libtlrmle.so"))
+
+
 def test_header_symbols_exported():
     _m, lib = _lib()
     header = open(os.path.join(ROOT, "include", "tlr.h")).read()
