@@ -36,10 +36,19 @@ class RankError(TLRError):
         self.tile = tile
 
 
-def _ptr(t) -> ctypes.c_void_p:
+def _check_len(t, count: int, what: str = "tensor"):
+    """The C-ABI takes bare device pointers: a tensor shorter than the count
+    the call reads or writes would be accessed out of bounds on the GPU."""
+    if t.numel() < count:
+        raise ValueError(f"{what}: expected at least {count} elements, got {t.numel()}")
+
+
+def _ptr(t, count: int = None, what: str = "tensor") -> ctypes.c_void_p:
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("expected a contiguous float64 torch tensor on the GPU")
+    if count is not None:
+        _check_len(t, count, what)
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -103,7 +112,7 @@ class Handle:
         raise TLRError(st, what)
 
     def generate(self, x, y, theta):
-        st = self._lib.tlr_generate(self._h, _ptr(x), _ptr(y), _d3(theta))
+        st = self._lib.tlr_generate(self._h, _ptr(x, self.n, "x"), _ptr(y, self.n, "y"), _d3(theta))
         self._check(st, "tlr_generate")
         self._keep = (x, y)
 
@@ -118,7 +127,7 @@ class Handle:
 
     def loglik(self, z):
         ll, ld, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        st = self._lib.tlr_loglik(self._h, _ptr(z), ctypes.byref(ll), ctypes.byref(ld), ctypes.byref(q))
+        st = self._lib.tlr_loglik(self._h, _ptr(z, self.n, "z"), ctypes.byref(ll), ctypes.byref(ld), ctypes.byref(q))
         self._check(st, "tlr_loglik")
         return ll.value, ld.value, q.value
 
@@ -126,8 +135,8 @@ class Handle:
         ll = ctypes.c_double()
         g = (ctypes.c_double * 2)()
         info = ctypes.c_int64(0)
-        st = self._lib.tlr_loglik_grad(self._h, _ptr(x), _ptr(y), _ptr(z), _d3(theta), ctypes.byref(ll), g,
-                                       ctypes.byref(info))
+        st = self._lib.tlr_loglik_grad(self._h, _ptr(x, self.n, "x"), _ptr(y, self.n, "y"), _ptr(z, self.n, "z"),
+                                       _d3(theta), ctypes.byref(ll), g, ctypes.byref(info))
         self._check(st, "tlr_loglik_grad", info.value)
         self._keep = (x, y)
         return ll.value, (g[0], g[1])
@@ -140,7 +149,7 @@ class Handle:
         m = int(xnew.shape[0])
         pred = torch.empty(m, dtype=torch.float64, device="cuda")
         var = torch.empty(m, dtype=torch.float64, device="cuda") if variance else None
-        st = self._lib.tlr_predict(self._h, _ptr(z), m, _ptr(xnew), _ptr(ynew), _ptr(pred),
+        st = self._lib.tlr_predict(self._h, _ptr(z, self.n, "z"), m, _ptr(xnew), _ptr(ynew, m, "ynew"), _ptr(pred),
                                    _ptr(var) if variance else ctypes.c_void_p())
         self._check(st, "tlr_predict")
         return (pred, var) if variance else pred
@@ -150,8 +159,8 @@ class Handle:
         ll = ctypes.c_double()
         g = (ctypes.c_double * 3)()
         info = ctypes.c_int64(0)
-        st = self._lib.tlr_loglik_grad3(self._h, _ptr(x), _ptr(y), _ptr(z), _d3(theta), ctypes.byref(ll), g,
-                                        ctypes.byref(info))
+        st = self._lib.tlr_loglik_grad3(self._h, _ptr(x, self.n, "x"), _ptr(y, self.n, "y"), _ptr(z, self.n, "z"),
+                                        _d3(theta), ctypes.byref(ll), g, ctypes.byref(info))
         self._check(st, "tlr_loglik_grad3", info.value)
         self._keep = (x, y)
         return ll.value, (g[0], g[1], g[2])
@@ -160,7 +169,7 @@ class Handle:
         """z = L eps with the current factor (after potrf)."""
         import torch
         z = torch.empty_like(eps)
-        self._check(self._lib.tlr_sample(self._h, _ptr(eps), _ptr(z)), "tlr_sample")
+        self._check(self._lib.tlr_sample(self._h, _ptr(eps, self.n, "eps"), _ptr(z)), "tlr_sample")
         return z
 
     def profile(self, enable=True):
@@ -225,9 +234,9 @@ def loglik_grad_batched(handles, xs, ys, zs, thetas, nthreads: int = 4):
     lib = _lib.load()
     P = ctypes.c_void_p
     hs = (P * nf)(*[h._h.value for h in handles])
-    px = (P * nf)(*[_ptr(t).value for t in xs])
-    py = (P * nf)(*[_ptr(t).value for t in ys])
-    pz = (P * nf)(*[_ptr(t).value for t in zs])
+    px = (P * nf)(*[_ptr(t, h.n, f"x[{f}]").value for f, (h, t) in enumerate(zip(handles, xs))])
+    py = (P * nf)(*[_ptr(t, h.n, f"y[{f}]").value for f, (h, t) in enumerate(zip(handles, ys))])
+    pz = (P * nf)(*[_ptr(t, h.n, f"z[{f}]").value for f, (h, t) in enumerate(zip(handles, zs))])
     th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).reshape(nf, 3))
     ll = np.zeros(nf)
     gr = np.zeros((nf, 2))
@@ -255,7 +264,7 @@ def dense_loglik_noalloc(x, y, z, theta, stream=None):
     ll, ld, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     info = ctypes.c_int64(0)
     s = stream if stream is not None else torch.cuda.current_stream()
-    st = lib.tlr_dense_loglik_noalloc(n, _ptr(x), _ptr(y), _ptr(z), _d3(theta), ctypes.byref(ll), ctypes.byref(ld),
+    st = lib.tlr_dense_loglik_noalloc(n, _ptr(x), _ptr(y, n, "y"), _ptr(z, n, "z"), _d3(theta), ctypes.byref(ll), ctypes.byref(ld),
                                       ctypes.byref(q), ctypes.byref(info), ctypes.c_void_p(s.cuda_stream))
     if st == _lib.TLR_ENOTSPD:
         raise NotSPDError(info.value, "tlr_dense_loglik_noalloc")

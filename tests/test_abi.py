@@ -29,6 +29,16 @@ def test_missing_library_raises(monkeypatch, tmp_path):
         m.load(str(tmp_path / "libtlrmle.so"))
 
 
+def test_short_tensors_are_refused_before_any_call():
+    # the C-ABI takes bare pointers: the binding checks lengths on the host
+    import torch
+    from paper_1804_09137_amd import _check_len
+    _check_len(torch.zeros(5, dtype=torch.float64), 5)
+    _check_len(torch.zeros(6, dtype=torch.float64), 5)
+    with pytest.raises(ValueError, match="z: expected at least 5 elements, got 4"):
+        _check_len(torch.zeros(4, dtype=torch.float64), 5, "z")
+
+
 def test_header_symbols_exported():
     _m, lib = _lib()
     header = open(os.path.join(ROOT, "include", "tlr.h")).read()
