@@ -184,7 +184,9 @@ typedef struct {
 
 /* Create a handle for problems of size opts->n on the current HIP device.
  * stream: a hipStream_t (NULL = the null stream).  All device memory the
- * handle will use is allocated here (TLR_ENOMEM on failure). */
+ * handle will use is allocated here (TLR_ENOMEM on failure), except the
+ * tile storage of a TLR handle with opts->arena_bytes = 0, which a pass that
+ * needs more reallocates at twice the size (see tlr_opts.arena_bytes). */
 tlr_status tlr_create(tlr_handle_t* h, const tlr_opts* opts, void* stream);
 
 /* Release every resource of the handle (NULL is accepted). */
@@ -192,8 +194,9 @@ tlr_status tlr_destroy(tlr_handle_t h);
 
 /* Bind the locations d_x[n], d_y[n] (device, read-only) and theta =
  * (sigma^2, beta, nu) (host, all finite, beta > 0, nu > 0, sigma^2 != 0) to the
- * handle.  Sigma(theta) is defined by Eq. (MaternCov) with Euclidean distance
- * (Section IV); C(0) = sigma^2.  No n x n storage is written here: the tiles
+ * handle.  Sigma(theta) is defined by Eq. (MaternCov) with the distance of
+ * opts->metric (Euclidean, or great-circle by Eq. (gcd); Section IV);
+ * C(0) = sigma^2.  No n x n storage is written here: the tiles
  * are generated inside tlr_compress / tlr_potrf where they are consumed. */
 tlr_status tlr_generate(tlr_handle_t h, const double* d_x, const double* d_y, const double theta[3]);
 
