@@ -201,10 +201,12 @@ tlr_status tlr_destroy(tlr_handle_t h);
 tlr_status tlr_generate(tlr_handle_t h, const double* d_x, const double* d_y, const double theta[3]);
 
 /* TLR mode: compress every strictly-lower tile of Sigma(theta) to U V^T with
- * ||A_ij - U V^T||_2 <= tol (Section V; randomized range finder followed by a
- * column-pivoted Householder QR truncation).  Fills the rank table that
- * tlr_get_ranks returns.  This is the TLR form of Sigma itself; tlr_potrf
- * does not need it. */
+ * ||A_ij - U V^T||_2 <= tol (Section V; a randomized range finder, then the
+ * truncation of the projection's Householder R factor, column-pivoted with
+ * TLR_FLAG_PIVOTED_TRUNC; or adaptive cross approximation with TLR_FLAG_ACA).
+ * Fills the rank table that tlr_get_ranks returns.  This is the TLR form of
+ * Sigma itself; tlr_potrf does not need it.  TLR_ENOTIMPL in DENSE mode;
+ * TLR_ESTATE before tlr_generate. */
 tlr_status tlr_compress(tlr_handle_t h);
 
 /* Factor Sigma(theta) = L L^T.  TLR mode: left-looking tile low-rank
