@@ -279,6 +279,8 @@ def main():
         print("bench.py measures one GPU only: the TLR likelihood here runs on a single MI355X "
               "(multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        sys.exit("--steps must be at least 1 and --warmup at least 0")
 
     if args.batched:
         # Every field runs on a stream of its own; the HIP runtime maps all

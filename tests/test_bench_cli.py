@@ -23,3 +23,10 @@ def test_batched_hardware_queue_count_is_bounded():
     r = _run("--batched", "--hw-queues", "64")
     assert r.returncode != 0
     assert "--hw-queues" in r.stderr and r.stdout == ""
+
+
+def test_step_counts_are_checked():
+    for args in (("--steps", "0"), ("--warmup", "-1")):
+        r = _run(*args)
+        assert r.returncode != 0
+        assert "--steps must be at least 1" in r.stderr and r.stdout == ""
